@@ -1,0 +1,437 @@
+"""Oracle: the HEVI split-explicit large step of the THOR dynamical core.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+The step follows Sec. 3 (flux-form deep non-hydrostatic Euler equations,
+Eqs. mass / mom / entropy, equation of state Eq. pressure, 3D operator split
+with Eqs. proj_h / proj_r, Wicker-Skamarock RK3 for the slow terms,
+forward-backward acoustic substeps in perturbation form, Eqs. dens2 / mom2 /
+momr2 / pt2 / theta_to_p, HEVI vertical momentum solved per column with the
+Thomas algorithm and a rigid lid), Sec. 4 (fourth-order hyperdiffusion
+Eqs. diff_rho ... diff_p, 3D divergence damping every short step, Eqs. kd /
+tau_d) and Sec. 5 (backward-Euler Newtonian relaxation, Eq. im_eq_t).
+
+Readings taken where the paper is silent or garbled (also in the design
+notes):
+  * the three "large time steps" of the inner-loop schedule are the three
+    RK stages: (1 substep of dt/3), (n/2 of dt/n), (n of dt/n);
+  * every stage restarts the small-step state from Phi[t]; deviations are
+    taken from Phi[t]; advection, Coriolis and the linearisation
+    coefficients (theta, gamma p / rho theta) use the previous stage state;
+    hyperdiffusion, grad p[t] and the [t] vertical imbalance use Phi[t];
+  * the vertical-momentum equation is the tridiagonal that follows from
+    inserting the discrete density and rho-theta updates (linearised
+    pressure, p = EOS(rho theta)) into the discrete vertical momentum
+    equation; this is the content of the printed Eq. vr22 in theta form;
+  * hyperdiffusion of momentum acts on velocity, F_q = -lap(rho Kd lap v_q);
+    the pressure diffusion F_p becomes a rho-theta tendency through
+    d(rho theta)/dp = rho theta / (gamma p);
+  * divergence damping: DD = -Kd lap(grad D) per Cartesian component, with
+    D the 3D momentum divergence of the current small-step state;
+  * levels equally spaced in height, linear (k = 1) Lagrange interpolation
+    between centres and interfaces; W = 0 at the bottom and the lid.
+
+State arrays: rho[n, L], M[n, L, 3] (horizontal momentum, Cartesian),
+rth[n, L] (rho theta), W[n, L+1] (rho v_r at interfaces).
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import grid as grid_mod
+from . import operators as op
+from . import rng
+
+
+@dataclass
+class Planet:
+    radius: float
+    omega: float
+    gravity: float
+    Rd: float
+    Cp: float
+    p_ref: float = 1.0e5
+
+
+@dataclass
+class Vertical:
+    n_lev: int
+    z_top: float
+
+
+@dataclass
+class Numerics:
+    dt: float
+    diff_D: float
+    div_damp: bool = True
+
+
+@dataclass
+class Forcing:
+    kind: int = 0            # 0 none, 1 Newtonian relaxation
+    tau: float = 1.0e5
+    T_mean: float = 1300.0
+    dT_daynight: float = 500.0
+    lon_substellar: float = 0.0
+
+
+@dataclass
+class Init:
+    T0: float
+    p_surf: float
+    noise_amp: float = 0.0
+    seed: int = 0
+
+
+@dataclass
+class Model:
+    """Everything fixed for a run: grid, planet, levels and derived constants."""
+    G: object
+    planet: Planet
+    vert: Vertical
+    num: Numerics
+    forcing: Forcing = field(default_factory=Forcing)
+
+    def __post_init__(self):
+        pl, v = self.planet, self.vert
+        self.Cv = pl.Cp - pl.Rd
+        self.gamma = pl.Cp / self.Cv
+        L = v.n_lev
+        self.dz = v.z_top / L
+        self.zI = np.arange(L + 1) * self.dz
+        self.zC = (np.arange(L) + 0.5) * self.dz
+        self.rI = pl.radius + self.zI
+        self.rC = pl.radius + self.zC
+        # Eq. kd with dbar of Eq. grid_qts
+        dbar = grid_mod.mean_spacing(self.G.g, pl.radius)
+        self.Kd = self.num.diff_D * dbar ** 4 / self.num.dt
+        self.rhat = self.G.P
+        # Newtonian relaxation target (day/night contrast, height independent)
+        lam = np.arctan2(self.rhat[:, 1], self.rhat[:, 0])
+        phi = np.arcsin(np.clip(self.rhat[:, 2], -1.0, 1.0))
+        f = self.forcing
+        teq = f.T_mean + 0.5 * f.dT_daynight * np.cos(phi) * np.cos(lam - f.lon_substellar)
+        self.Teq = np.repeat(teq[:, None], L, axis=1)
+
+    # Eq. pressure and its inverse
+    def eos(self, rth):
+        pr, Rd = self.planet.p_ref, self.planet.Rd
+        return pr * (Rd * rth / pr) ** self.gamma
+
+    def rth_from_p(self, p):
+        pr, Rd = self.planet.p_ref, self.planet.Rd
+        return (pr / Rd) * (p / pr) ** (1.0 / self.gamma)
+
+
+@dataclass
+class State:
+    rho: np.ndarray
+    M: np.ndarray
+    rth: np.ndarray
+    W: np.ndarray
+
+    def copy(self):
+        return State(self.rho.copy(), self.M.copy(), self.rth.copy(), self.W.copy())
+
+
+# ---------------------------------------------------------------------------
+# Initial state: isothermal, in discrete hydrostatic balance, plus noise
+# ---------------------------------------------------------------------------
+def init_state(model, init, planet_index=0):
+    pl = model.planet
+    L, n = model.vert.n_lev, model.G.n
+    RT = pl.Rd * init.T0
+    half = 0.5 * pl.gravity * model.dz
+    rho_col = np.empty(L)
+    rho_col[0] = init.p_surf * np.exp(-half / RT) / RT
+    for k in range(1, L):
+        # p_k - p_{k-1} = -g dz (rho_{k-1} + rho_k) / 2 with p = rho Rd T0
+        rho_col[k] = rho_col[k - 1] * (RT - half) / (RT + half)
+    p_col = rho_col * RT
+    eps = rng.column_noise(init.seed, n, L, init.noise_amp, planet_index)
+    T = init.T0 + eps
+    p = np.repeat(p_col[None, :], n, axis=0)
+    rho = p / (pl.Rd * T)
+    rth = model.rth_from_p(p)
+    return State(rho, np.zeros((n, L, 3)), rth, np.zeros((n, L + 1)))
+
+
+# ---------------------------------------------------------------------------
+# Vertical helpers (linear Lagrange interpolation, flux divergence in r)
+# ---------------------------------------------------------------------------
+def to_interfaces(x):
+    """Interior interface values (j = 1..L-1) of a centre field [n, L, ...]."""
+    return 0.5 * (x[:, :-1] + x[:, 1:])
+
+
+def to_centres(W):
+    """Centre values of an interface field [n, L+1]."""
+    return 0.5 * (W[:, :-1] + W[:, 1:])
+
+
+def vertical_div(model, F):
+    """(1 / r_C^2) d(r^2 F)/dr for interface fluxes F[n, L+1, ...]."""
+    rI2 = model.rI ** 2
+    rC2 = model.rC ** 2
+    sh = (1, -1) + (1,) * (F.ndim - 2)
+    flux = F * rI2.reshape((1, -1) + (1,) * (F.ndim - 2))
+    return (flux[:, 1:] - flux[:, :-1]) / (rC2.reshape(sh) * model.dz)
+
+
+# ---------------------------------------------------------------------------
+# Thomas algorithm (Sec. 3, rigid lid)
+# ---------------------------------------------------------------------------
+def thomas(a, b, c, d):
+    """Solve a_j x_{j-1} + b_j x_j + c_j x_{j+1} = d_j, j = 0..m-1.
+
+    Arrays are [n, m]; a[:, 0] and c[:, -1] are ignored (the boundary values
+    are zero).  Forward elimination, then back substitution.
+    """
+    n, m = d.shape
+    cp = np.zeros((n, m))
+    dp = np.zeros((n, m))
+    cp[:, 0] = c[:, 0] / b[:, 0]
+    dp[:, 0] = d[:, 0] / b[:, 0]
+    for j in range(1, m):
+        den = b[:, j] - a[:, j] * cp[:, j - 1]
+        cp[:, j] = c[:, j] / den
+        dp[:, j] = (d[:, j] - a[:, j] * dp[:, j - 1]) / den
+    x = np.zeros((n, m))
+    x[:, -1] = dp[:, -1]
+    for j in range(m - 2, -1, -1):
+        x[:, j] = dp[:, j] - cp[:, j] * x[:, j + 1]
+    return x
+
+
+# ---------------------------------------------------------------------------
+# Split-explicit schedule (Wicker-Skamarock RK3 + inner loop)
+# ---------------------------------------------------------------------------
+def stage_schedule(dt, n):
+    """(substeps, dtau) of the three RK stages: (1, dt/3), (n/2, dt/n), (n, dt/n)."""
+    if n < 2 or n % 2:
+        raise ValueError("n_acoustic must be even and >= 2")
+    return [(1, dt / 3.0), (n // 2, dt / n), (n, dt / n)]
+
+
+def split_explicit(phi_t, slow, substep, dt, n):
+    """One large step: for each stage evaluate the slow forcing at the
+    previous stage state, restart from phi[t] and take the stage's substeps.
+
+    slow(phi_prev) -> forcing;  substep(phi, forcing, dtau) -> phi.
+    With only slow terms this is exactly the WS-RK3 predictor-corrector.
+    """
+    prev = phi_t
+    for ns, dtau in stage_schedule(dt, n):
+        forcing = slow(prev)
+        phi = phi_t
+        for _ in range(ns):
+            phi = substep(phi, forcing, dtau)
+        prev = phi
+    return prev
+
+
+# ---------------------------------------------------------------------------
+# Hyperdiffusion (Sec. 4), once per large step at Phi[t]
+# ---------------------------------------------------------------------------
+def hyperdiffusion(model, st, p):
+    G, Kd, rC = model.G, model.Kd, model.rC
+    Rd = model.planet.Rd
+    H_rho = -Kd * op.lap(G, op.lap(G, st.rho, rC), rC)
+    v = st.M / st.rho[..., None]
+    H_M = np.zeros_like(st.M)
+    for q in range(3):
+        H_M[..., q] = -op.lap(G, st.rho * Kd * op.lap(G, v[..., q], rC), rC)
+    H_M = op.proj_h(H_M, model.rhat)
+    L = model.vert.n_lev
+    H_W = np.zeros((G.n, L + 1))
+    if L > 1:
+        rhoI = to_interfaces(st.rho)
+        w = st.W[:, 1:L] / rhoI
+        rI = model.rI[1:L]
+        H_W[:, 1:L] = -op.lap(G, rhoI * Kd * op.lap(G, w, rI), rI)
+    T = p / (st.rho * Rd)
+    F_p = -Rd * op.lap(G, st.rho * Kd * op.lap(G, T, rC), rC)
+    H_rth = st.rth / (model.gamma * p) * F_p
+    return H_rho, H_M, H_W, H_rth
+
+
+# ---------------------------------------------------------------------------
+# Slow terms of one RK stage: advection, Coriolis, projections
+# ---------------------------------------------------------------------------
+def slow_forcing(model, prev, large):
+    """Forcings S_M, S_W, S_rho, S_rth and linearisation at the stage state."""
+    G, rC, rhat = model.G, model.rC, model.rhat
+    L = model.vert.n_lev
+    rh = rhat[:, None, :]
+    # full Cartesian momentum m = M + Wbar rhat and velocity m / rho
+    m = prev.M + to_centres(prev.W)[..., None] * rh
+    v = m / prev.rho[..., None]
+    # advection A_q = div(v_q M) + (1/r^2) d(r^2 W v_q)/dr
+    A = np.zeros_like(m)
+    for q in range(3):
+        A[..., q] = op.div(G, v[..., q, None] * prev.M, rC)
+    vI = np.zeros((G.n, L + 1, 3))
+    vI[:, 1:L] = to_interfaces(v)
+    A += vertical_div(model, prev.W[..., None] * vI)
+    # Coriolis 2 Omega zhat x m
+    Om = model.planet.omega
+    C = np.zeros_like(m)
+    C[..., 0] = -2.0 * Om * m[..., 1]
+    C[..., 1] = 2.0 * Om * m[..., 0]
+    AC = A + C
+    S_M = op.proj_h(-large["G_t"] - AC, rhat) + large["H_M"]
+    S_W = np.zeros((G.n, L + 1))
+    ACr = op.proj_r(AC, rhat)
+    S_W[:, 1:L] = large["I"][:, 1:L] - to_interfaces(ACr) + large["H_W"][:, 1:L]
+    thetaC = prev.rth / prev.rho
+    thetaI = np.empty((G.n, L + 1))
+    thetaI[:, 1:L] = to_interfaces(thetaC)
+    thetaI[:, 0] = thetaC[:, 0]
+    thetaI[:, L] = thetaC[:, L - 1]
+    Gam = model.gamma * model.eos(prev.rth) / prev.rth
+    return dict(S_M=S_M, S_W=S_W, S_rho=large["H_rho"], S_rth=large["H_rth"],
+                thetaC=thetaC, thetaI=thetaI, Gam=Gam)
+
+
+# ---------------------------------------------------------------------------
+# One acoustic substep (Eqs. mom2, momr2, dens2, pt2, theta_to_p)
+# ---------------------------------------------------------------------------
+def momentum_divergence(model, M, W):
+    """3D divergence of the momentum: div_h M + (1/r^2) d(r^2 W)/dr."""
+    return op.div(model.G, M, model.rC) + vertical_div(model, W)
+
+
+def acoustic_substep(model, st, f, dtau, large):
+    G, rC, rhat = model.G, model.rC, model.rhat
+    g = model.planet.gravity
+    dz = model.dz
+    L = model.vert.n_lev
+    p_t, rho_t = large["p_t"], large["rho_t"]
+    p = model.eos(st.rth)
+    # divergence damping on the current small-step state
+    DD = 0.0
+    if model.num.div_damp:
+        D = momentum_divergence(model, st.M, st.W)
+        GD = op.grad(G, D, rC)
+        DD = np.zeros_like(st.M)
+        for q in range(3):
+            DD[..., q] = -model.Kd * op.lap(G, GD[..., q], rC)
+    # (H) explicit horizontal momentum with the deviation pressure gradient
+    M = st.M + dtau * (-op.grad(G, p - p_t, rC) + f["S_M"] + DD)
+    M = op.proj_h(M, rhat)
+    # (Div) horizontal mass and theta fluxes of the new momentum
+    D_rho = op.div(G, M, rC)
+    D_th = op.div(G, f["thetaC"][..., None] * M, rC)
+    # (Pred) explicit parts of density and pressure
+    rho_hat = st.rho + dtau * (-D_rho + f["S_rho"])
+    p_hat = p + dtau * f["Gam"] * (-D_th + f["S_rth"])
+    rho_hs = rho_hat - rho_t
+    p_hs = p_hat - p_t
+    # (Tri) HEVI vertical momentum at interfaces 1..L-1
+    rI2, rC2 = model.rI ** 2, model.rC ** 2
+    ap = dtau * rI2[1:] / (rC2 * dz)        # alpha+_k, k = 0..L-1
+    am = dtau * rI2[:-1] / (rC2 * dz)       # alpha-_k
+    Gam, th = f["Gam"], f["thetaI"]
+    W = st.W.copy()
+    if L > 1:
+        j = np.arange(1, L)
+        c1 = dtau / dz
+        c2 = 0.5 * g * dtau
+        a = -c1 * Gam[:, j - 1] * am[j - 1] * th[:, j - 1] + c2 * am[j - 1]
+        b = (1.0 + c1 * th[:, j] * (Gam[:, j] * am[j] + Gam[:, j - 1] * ap[j - 1])
+             + c2 * (am[j] - ap[j - 1]))
+        c = -c1 * Gam[:, j] * ap[j] * th[:, j + 1] - c2 * ap[j]
+        d = (st.W[:, j] + dtau * f["S_W"][:, j] - c1 * (p_hs[:, j] - p_hs[:, j - 1])
+             - c2 * (rho_hs[:, j - 1] + rho_hs[:, j]))
+        W[:, 1:L] = thomas(a, b, c, d)
+    W[:, 0] = 0.0
+    W[:, L] = 0.0
+    # (Upd) density (Eq. dens2) and rho theta (Eq. pt2) with the new W
+    rho = rho_hat - ap * W[:, 1:] + am * W[:, :-1]
+    rth = (st.rth + dtau * (-D_th + f["S_rth"])
+           - ap * th[:, 1:] * W[:, 1:] + am * th[:, :-1] * W[:, :-1])
+    return State(rho, M, rth, W)
+
+
+# ---------------------------------------------------------------------------
+# Large step, physics, diagnostics
+# ---------------------------------------------------------------------------
+def large_step_terms(model, st):
+    """Quantities frozen over a large step at Phi[t]."""
+    G, rC = model.G, model.rC
+    g = model.planet.gravity
+    L = model.vert.n_lev
+    p_t = model.eos(st.rth)
+    H_rho, H_M, H_W, H_rth = hyperdiffusion(model, st, p_t)
+    G_t = op.proj_h(op.grad(G, p_t, rC), model.rhat)
+    I = np.zeros((G.n, L + 1))
+    if L > 1:
+        I[:, 1:L] = (-(p_t[:, 1:] - p_t[:, :-1]) / model.dz
+                     - 0.5 * g * (st.rho[:, :-1] + st.rho[:, 1:]))
+    return dict(p_t=p_t, rho_t=st.rho.copy(), H_rho=H_rho, H_M=H_M, H_W=H_W,
+                H_rth=H_rth, G_t=G_t, I=I)
+
+
+def newtonian(model, st):
+    """Eq. im_eq_t with constant K_T = 1/tau at fixed density."""
+    f, pl = model.forcing, model.planet
+    if f.kind != 1:
+        return st
+    dt = model.num.dt
+    p = model.eos(st.rth)
+    T = p / (st.rho * pl.Rd)
+    kt = dt / f.tau
+    Tn = (T + kt * model.Teq) / (1.0 + kt)
+    rth = model.rth_from_p(st.rho * pl.Rd * Tn)
+    return State(st.rho, st.M, rth, st.W)
+
+
+def large_step(model, st, n):
+    large = large_step_terms(model, st)
+    out = split_explicit(
+        st,
+        lambda prev: slow_forcing(model, prev, large),
+        lambda phi, f, dtau: acoustic_substep(model, phi, f, dtau, large),
+        model.num.dt, n)
+    return newtonian(model, out)
+
+
+def run(model, st, n_large, n):
+    for _ in range(n_large):
+        st = large_step(model, st, n)
+    return st
+
+
+def mass(model, st):
+    """sum_i sum_k rho A_c r_k^2 dz (A_c on the unit sphere)."""
+    return float(np.sum(st.rho * model.G.Ac[:, None] * model.rC[None, :] ** 2) * model.dz)
+
+
+def fields(model, st):
+    """Diagnostic fields T, u, v, w, p (canonical [col][lev])."""
+    pl = model.planet
+    p = model.eos(st.rth)
+    T = p / (st.rho * pl.Rd)
+    P = model.rhat
+    lam = np.arctan2(P[:, 1], P[:, 0])
+    phi = np.arcsin(np.clip(P[:, 2], -1.0, 1.0))
+    east = np.stack([-np.sin(lam), np.cos(lam), np.zeros_like(lam)], axis=-1)
+    north = np.stack([-np.sin(phi) * np.cos(lam), -np.sin(phi) * np.sin(lam),
+                      np.cos(phi)], axis=-1)
+    vel = st.M / st.rho[..., None]
+    u = np.sum(vel * east[:, None, :], axis=-1)
+    v = np.sum(vel * north[:, None, :], axis=-1)
+    w = to_centres(st.W) / st.rho
+    return dict(T=T, u=u, v=v, w=w, p=p, rho=st.rho, rhotheta=st.rth,
+                Mx=st.M[..., 0], My=st.M[..., 1], Mz=st.M[..., 2], W=st.W)
+
+
+def model_from_workload(w, G):
+    """Oracle model and initial state for a workload recipe (``workloads``)."""
+    planet = Planet(w.radius, w.omega, w.gravity, w.Rd, w.Cp, w.p_ref)
+    vert = Vertical(w.n_lev, w.z_top)
+    num = Numerics(w.dt, w.diff_D, w.div_damp)
+    forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar)
+    model = Model(G, planet, vert, num, forcing)
+    st = init_state(model, Init(w.T0, w.p_surf, w.noise_amp, w.seed))
+    return model, st

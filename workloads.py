@@ -1,0 +1,106 @@
+"""Seeded synthetic workloads of the THOR HEVI step.
+
+This module holds input recipes only (planet constants, level counts, time
+steps, seeds); it contains none of the method's arithmetic and is the one
+piece shared by the tests, the benchmark, the oracle runs and the library
+runs.
+
+Constants: Table 1 of the paper (Earth: radius 6.371e6 m, rotation
+7.292e-5 1/s, gravity 9.8; hot Jupiter: radius 1e8 m, rotation 2.1e-5 1/s,
+cp 13226.5, Rd 3779) as amended by the workload definitions below.  The
+nondimensional diffusion number D follows from Eqs. kd and tau_d:
+tau_d = dbar^4 / (32 Kd) and Kd = D dbar^4 / dt give D = dt / (32 tau_d),
+evaluated with the paper's benchmark time steps and damping times
+(Earth: 1000 s, 6.46e3 s; hot Jupiter: 600 s, 941.2 s).
+"""
+import math
+from dataclasses import dataclass, field
+
+D_EARTH = 1000.0 / (32.0 * 6460.0)     # 4.837e-3
+D_HOT_JUPITER = 600.0 / (32.0 * 941.2)  # 1.992e-2
+
+
+@dataclass
+class Workload:
+    name: str
+    glevel: int
+    n_lev: int
+    z_top: float
+    radius: float
+    omega: float
+    gravity: float
+    Rd: float
+    Cp: float
+    p_ref: float
+    dt: float
+    n_acoustic: int
+    n_large: int
+    diff_D: float
+    div_damp: bool
+    T0: float
+    p_surf: float
+    noise_amp: float
+    seed: int
+    forcing_kind: int = 0
+    tau: float = 1.0e5
+    T_mean: float = 0.0
+    dT_daynight: float = 0.0
+    lon_substellar: float = 0.0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_col(self):
+        return 10 * 4 ** self.glevel + 2
+
+    @property
+    def cells(self):
+        return self.n_col * self.n_lev
+
+    @property
+    def substeps_per_large(self):
+        return 1 + 3 * self.n_acoustic // 2
+
+
+def substellar_longitude(seed):
+    """Substellar longitude 2 pi U, U from the top 53 bits of a SplitMix64
+    output step applied to the seed (reproducible, no library state)."""
+    z = (seed + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
+    z ^= z >> 31
+    return 2.0 * math.pi * ((z >> 11) * 2.0 ** -53)
+
+
+def earth_c1():
+    """g4 (2562 columns) x 20 levels to 36 km, Earth air, isothermal 300 K
+    rest state with +/-0.1 K noise; 10 large steps of 600 s, 6 substeps."""
+    return Workload("g4L20-earth", 4, 20, 36.0e3, 6.371e6, 7.292e-5, 9.8, 287.0,
+                    1005.0, 1.0e5, 600.0, 6, 10, D_EARTH, True, 300.0, 1.0e5,
+                    0.1, 1)
+
+
+def gas_giant(glevel, n_lev, seed, n_large, dt=300.0, n_acoustic=8):
+    """Gas-giant-like planet with Newtonian relaxation (timescale 1e5 s)
+    toward a day/night equilibrium temperature of 500 K contrast."""
+    T0, g, Rd = 1300.0, 9.42, 3779.0
+    z_top = Rd * T0 / g * math.log(2.2e7 / 1.0e3)   # p_top ~ 1e3 Pa
+    return Workload(f"g{glevel}L{n_lev}-gasgiant", glevel, n_lev, z_top, 1.0e8,
+                    2.1e-5, g, Rd, 13226.0, 1.0e5, dt, n_acoustic, n_large,
+                    D_HOT_JUPITER, True, T0, 2.2e7, 0.1, seed, forcing_kind=1,
+                    tau=1.0e5, T_mean=1300.0, dT_daynight=500.0,
+                    lon_substellar=substellar_longitude(seed))
+
+
+def gas_giant_c2():
+    """g6 (40962 columns) x 32 levels, 300 s large steps with 8 substeps."""
+    return gas_giant(6, 32, 2, 1000)
+
+
+def gas_giant_c3():
+    """g7 (163842 columns) x 48 levels; one Earth day = 288 steps of 300 s."""
+    return gas_giant(7, 48, 3, 288)
+
+
+def small_gas_giant(glevel=3, n_lev=12, seed=7, n_large=3):
+    """Small gas-giant case for fast parity tests of the forcing path."""
+    return gas_giant(glevel, n_lev, seed, n_large, dt=300.0 * 2 ** (6 - glevel), n_acoustic=8)
