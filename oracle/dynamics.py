@@ -83,6 +83,15 @@ class Init:
     seed: int = 0
 
 
+def lon_lat(P):
+    """Longitude and latitude of unit vectors.  At a pole the longitude is
+    undefined; there it is taken as 0 (east = +y, north = -sign(z) x)."""
+    horiz = np.sqrt(P[:, 0] ** 2 + P[:, 1] ** 2)
+    lam = np.where(horiz < 1e-12, 0.0, np.arctan2(P[:, 1], P[:, 0]))
+    phi = np.arcsin(np.clip(P[:, 2], -1.0, 1.0))
+    return lam, phi
+
+
 @dataclass
 class Model:
     """Everything fixed for a run: grid, planet, levels and derived constants."""
@@ -107,8 +116,7 @@ class Model:
         self.Kd = self.num.diff_D * dbar ** 4 / self.num.dt
         self.rhat = self.G.P
         # Newtonian relaxation target (day/night contrast, height independent)
-        lam = np.arctan2(self.rhat[:, 1], self.rhat[:, 0])
-        phi = np.arcsin(np.clip(self.rhat[:, 2], -1.0, 1.0))
+        lam, phi = lon_lat(self.rhat)
         f = self.forcing
         teq = f.T_mean + 0.5 * f.dT_daynight * np.cos(phi) * np.cos(lam - f.lon_substellar)
         self.Teq = np.repeat(teq[:, None], L, axis=1)
@@ -413,8 +421,7 @@ def fields(model, st):
     p = model.eos(st.rth)
     T = p / (st.rho * pl.Rd)
     P = model.rhat
-    lam = np.arctan2(P[:, 1], P[:, 0])
-    phi = np.arcsin(np.clip(P[:, 2], -1.0, 1.0))
+    lam, phi = lon_lat(P)
     east = np.stack([-np.sin(lam), np.cos(lam), np.zeros_like(lam)], axis=-1)
     north = np.stack([-np.sin(phi) * np.cos(lam), -np.sin(phi) * np.sin(lam),
                       np.cos(phi)], axis=-1)
