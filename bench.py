@@ -1,0 +1,160 @@
+"""Throughput of the HEVI dynamical-core step on one MI355X.
+
+Workload: gas-giant-like planet on the g6 icosahedral grid (40962 columns) x
+32 levels, large step 300 s with 8 acoustic substeps (13 substeps per large
+step), Newtonian relaxation (1e5 s) toward a day/night equilibrium
+temperature, synthetic seeded initial state.  A "step" is one large step:
+the per-step hyperdiffusion and [t] terms, three RK stages of slow tendencies
+and all 13 acoustic substeps (explicit horizontal momentum, HEVI vertical
+solve, divergence damping), then the physics.
+
+Metric: cell-updates/s per acoustic substep,
+    N_col * L * (1 + 3n/2) * K / T_wall,
+with T_wall the time of K graph-launched large steps (inputs resident in
+HBM).  Printed as one JSON line with the FP64 value, the mixed-precision
+value beside it, the HBM roofline of the dominant kernel and the FP64 oracle
+timed on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E datasheet peak
+
+
+def vert_bytes_per_cell(L, mixed):
+    """Algorithmic bytes of one acoustic phase-V launch per cell: distinct
+    field words read and written once, plus the per-column stencil geometry
+    (neighbour ids and 7 coefficient vectors) once per column."""
+    h = 4 if mixed else 8
+    reads = 3 * h + h + h + 8 + 8 + 8 + h + 8 + 8 + 8 + 8 + 8   # M, thL, Gam, rho, rth, W, p*, S_W, H_rho, H_rth, rho_t, p_t
+    writes = 8 + 8 + 8 + h + h                                  # rho, rth, W, p*, D
+    geom = 6 * 4 + 21 * h
+    return reads + writes + geom / L
+
+
+def hmom_bytes_per_cell(L, mixed):
+    h = 4 if mixed else 8
+    fields = 13 * h              # M in (3), S_M (3), p* (1), G (3), M out (3)
+    geom = 6 * 4 + 18 * h + 6 * h + 3 * h
+    return fields + geom / L
+
+
+def run_gpu(w, precision, steps, warmup):
+    import torch
+    from paper_1607_05535_amd import thor
+    g = thor.Grid(w.glevel)
+    st = thor.State(g, *thor.structs_from_workload(w, precision), device="cuda:0")
+    n = w.n_acoustic
+    st.step(warmup, n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.step(steps, n)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    sc, rc = st.scalars()
+    if rc != 0:
+        raise RuntimeError("non-finite state after the timed steps")
+    # kernel durations with HIP events on the state's stream
+    thor.thor_set_timing(st.handle, 1)
+    st.step(steps, n)
+    kt = {k: thor.thor_kernel_time(st.handle, k) for k in ("vert", "hmom", "graddiv", "slow", "large", "newton")}
+    thor.thor_set_timing(st.handle, 0)
+    torch.cuda.synchronize()
+    return T, kt, sc
+
+
+def cpu_baseline(w):
+    """The FP64 oracle on the host: one large step's worth estimated from a
+    bounded sample (the per-step terms, one RK stage of slow terms and two
+    acoustic substeps), single thread."""
+    import numpy as np  # noqa: F401
+    from oracle import dynamics as odyn
+    from oracle import grid as ogrid
+    G = ogrid.Grid(w.glevel, k=100.0)
+    model, st = odyn.model_from_workload(w, G)
+    t0 = time.perf_counter()
+    large = odyn.large_step_terms(model, st)
+    t1 = time.perf_counter()
+    f = odyn.slow_forcing(model, st, large)
+    t2 = time.perf_counter()
+    s = st
+    dtau = w.dt / w.n_acoustic
+    for _ in range(2):
+        s = odyn.acoustic_substep(model, s, f, dtau, large)
+    t3 = time.perf_counter()
+    t_large = (t1 - t0) + 3 * (t2 - t1) + w.substeps_per_large * (t3 - t2) / 2
+    value = w.cells * w.substeps_per_large / t_large
+    return dict(value=value, unit="cell-updates/s", cores=1, kind="oracle",
+                sample=(f"{w.name}: per-step terms + 1 slow stage + 2 acoustic substeps "
+                        f"({t3 - t0:.1f} s), extrapolated to one large step "
+                        f"({t_large:.1f} s: 1 + 3 slow + {w.substeps_per_large} substeps)"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import workloads
+    w = workloads.gas_giant_c2()
+    subs = w.substeps_per_large
+    updates = w.cells * subs * args.steps
+
+    T64, kt64, sc64 = run_gpu(w, 0, args.steps, args.warmup)
+    value = updates / T64
+    vmean = kt64["vert"][0] * 1e-3
+    vb = vert_bytes_per_cell(w.n_lev, False) * w.cells
+    achieved = vb / vmean / 1e9 if vmean > 0 else 0.0
+    out = {
+        "metric": "cell-updates/s per acoustic substep, g6 L32, FP64 vs mixed; % HBM roofline",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T64 / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": ("gas giant g6 (40962 columns) x 32 levels, dt 300 s, "
+                                "8 acoustic substeps (13 per large step), Newtonian relaxation, "
+                                "divergence damping"),
+                   "n_col": w.n_col, "n_lev": w.n_lev, "substeps_per_step": subs},
+        "roofline": {"bound": "hbm", "kernel": "vert (acoustic phase V)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": vb, "mean_launch_ms": kt64["vert"][0]},
+        "kernel_ms": {k: v[0] for k, v in kt64.items()},
+    }
+    if not args.no_mixed:
+        T32, kt32, sc32 = run_gpu(w, 1, args.steps, args.warmup)
+        vm = kt32["vert"][0] * 1e-3
+        vb32 = vert_bytes_per_cell(w.n_lev, True) * w.cells
+        out["mixed"] = {"value": updates / T32, "ms_per_step": T32 / args.steps * 1e3,
+                        "speedup_vs_fp64": T64 / T32,
+                        "vert_achieved_GBs": vb32 / vm / 1e9 if vm > 0 else 0.0,
+                        "kernel_ms": {k: v[0] for k, v in kt32.items()}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * thor.h -- C ABI of the MI355X (gfx950) HEVI dynamical-core step.
+ *
+ * Method: Mendonca et al. 2016, "THOR: a new and flexible global circulation
+ * model to explore planetary atmospheres" (arXiv:1607.05535).  One time step
+ * is the split-explicit, horizontally explicit / vertically implicit (HEVI)
+ * integration of the deep non-hydrostatic Euler equations in flux form
+ * (Sec. 3, Eqs. mass, mom, entropy) on a spring-dynamics-smoothed
+ * icosahedral grid (Sec. 2), with fourth-order hyperdiffusion and 3D
+ * divergence damping (Sec. 4) and backward-Euler Newtonian relaxation
+ * (Sec. 5, Eq. im_eq_t).
+ *
+ * Conventions
+ *   - Every function returns THOR_OK (0) or a negative THOR_E* code and never
+ *     throws or longjmps across the ABI.  thor_last_error() then holds a
+ *     message for the calling thread.
+ *   - Argument errors are detected before anything is enqueued on the GPU.
+ *   - Handles (thor_grid, thor_state) are library-owned host objects freed by
+ *     the matching *_free.  All device memory is supplied by the caller.
+ *   - Fields at the boundary are FP64 in canonical [col][lev] order: column
+ *     ids as defined by thor_grid_build, levels from the bottom.
+ */
+#ifndef THOR_H
+#define THOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  THOR_OK = 0,
+  THOR_EINVAL = -1,      /* bad argument; nothing was done */
+  THOR_ENOMEM = -2,      /* host allocation failed, or dev_bytes too small */
+  THOR_EHIP = -3,        /* a HIP runtime call failed (message has the detail) */
+  THOR_ENONFINITE = -4,  /* thor_diag found NaN or Inf in the state */
+  THOR_ENOTCONV = -5     /* spring dynamics hit max_iter before the stop rule */
+};
+
+/* Message of the last failing call on this thread (empty if none).  Valid
+ * until the next library call on the same thread. */
+const char *thor_last_error(void);
+
+typedef struct thor_grid thor_grid;
+typedef struct thor_state thor_state;
+
+/* ---------------------------------------------------------------------------
+ * Grid (Sec. 2.1-2.2; Eqs. grid_qts, int_grid, spring_force, spr_vel, dbar,
+ * centroid equation).
+ *
+ * Icosahedron with two vertices at the poles, split into ten rhombi, each
+ * refined glevel times by recursive edge bisection onto the unit sphere:
+ * n_col = 10 * 4^glevel + 2 columns, 12 of them pentagons.  Column ids: rhombus
+ * r (north r = 0..4, south 5..9) owns lattice points a in [1, 2^g],
+ * b in [0, 2^g - 1] with id = r 4^g + (a - 1) 2^g + b; north pole 10 * 4^g,
+ * south pole 10 * 4^g + 1.  Neighbours are listed counter-clockwise (seen
+ * from outside) starting at the smallest id; a pentagon's 6th slot is -1.
+ *
+ * smooth = 1 builds the modified grid: spring dynamics on the hexagon points
+ *   dv/dt = sum_i k (d_i - dbar_spr) e_i - alpha v,
+ *   dbar_spr = beta * 2 pi / (10 * 2^(glevel-1)),
+ * integrated with step dt (symplectic Euler, tangent velocity) until no
+ * point moves more than tol in one step, then the control-volume corners are
+ * put at the triangle centroids and every point moved once to the centroid
+ * of its control volume.  smooth = 0 keeps the bisection points (corners
+ * still at the triangle centroids).  Paper values: beta 1.15, alpha 1,
+ * dt 0.01, tol 1e-5; the paper gives no k, this library uses k = 100.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int glevel;       /* 0..8 */
+  int smooth;       /* 1: spring dynamics + centroids; 0: standard grid */
+  double k;         /* spring constant (> 0) */
+  double beta;      /* natural-length factor (> 0) */
+  double alpha;     /* friction (>= 0) */
+  double dt;        /* pseudo time step (> 0) */
+  double tol;       /* stop when every point moved less than tol in one step */
+  int max_iter;     /* iteration cap (> 0) */
+} thor_grid_params;
+
+/* Fill p with the defaults above for grid level glevel. */
+void thor_grid_params_default(int glevel, thor_grid_params *p);
+
+/* Build the grid on the host.  EINVAL: bad parameters (glevel outside 0..8,
+ * non-positive k, beta, dt, tol or max_iter).  ENOTCONV: max_iter reached
+ * (*out is still returned and usable).  ENOMEM: allocation failure. */
+int thor_grid_build(const thor_grid_params *p, thor_grid **out);
+
+/* Number of columns, pentagons and spring-dynamics iterations taken. */
+int thor_grid_info(const thor_grid *g, int64_t *n_col, int *n_pent, int *spring_iters);
+
+/* Copy the grid into caller-owned host buffers (any pointer may be NULL):
+ *   nbr[n_col * 6]  neighbour ids, -1 in a pentagon's 6th slot
+ *   xyz[n_col * 3]  unit-sphere cell points
+ *   area[n_col]     control-volume areas on the unit sphere (sum = 4 pi) */
+int thor_grid_export(const thor_grid *g, int32_t *nbr, double *xyz, double *area);
+
+/* Operator coefficients derived from the geometry (host buffers, NULL ok):
+ *   div_coef[n_col * 7 * 3]  div F = (1/r) sum_{j=0..6} c_j . F_j  (j = 0 the
+ *                            cell itself, j >= 1 neighbour j-1; Eqs. flx_div,
+ *                            int_grid, div_gauss); also grad s =
+ *                            (1/r) sum_{j>=1} c_j (s_j - s_0) (Eq. grad)
+ *   lap_coef[n_col * 6]      lap s = (1/r^2) sum_j l_j (s_nbr_j - s_0), the
+ *                            triangle-gradient Laplacian of Sec. 4 */
+int thor_grid_coefficients(const thor_grid *g, double *div_coef, double *lap_coef);
+
+void thor_grid_free(thor_grid *g);
+
+/* ---------------------------------------------------------------------------
+ * Model configuration (Table 1 style planet parameters; Sec. 3-5).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double radius;   /* A [m] */
+  double omega;    /* rotation rate [1/s], axis +z */
+  double gravity;  /* constant, radial [m/s^2] */
+  double Rd;       /* gas constant [J/kg/K] */
+  double Cp;       /* heat capacity at constant pressure; Cv = Cp - Rd */
+  double p_ref;    /* reference pressure of Eq. pressure [Pa] */
+} thor_planet;
+
+typedef struct {
+  int n_lev;       /* layers, 1..64, equally spaced in height */
+  double z_top;    /* rigid lid height [m] */
+} thor_vertical;
+
+enum { THOR_FP64 = 0, THOR_MIXED = 1 };
+
+typedef struct {
+  double dt;       /* large time step [s] */
+  double diff_D;   /* nondimensional hyperdiffusion number, Kd = D dbar^4/dt (Eq. kd) */
+  int div_damp;    /* 1: 3D divergence damping every substep (Sec. 4) */
+  int precision;   /* THOR_FP64, or THOR_MIXED: horizontal stencils and
+                      advection in FP32, vertical solve and reference state in
+                      FP64 */
+} thor_numerics;
+
+enum { THOR_FORCING_NONE = 0, THOR_FORCING_NEWTONIAN = 1 };
+
+typedef struct {
+  int kind;               /* THOR_FORCING_* */
+  double tau;             /* relaxation time scale, K_T = 1/tau [s] */
+  double T_mean;          /* T_eq = T_mean + dT/2 cos(lat) cos(lon - lon_ss) */
+  double dT_daynight;     /* day/night contrast [K] */
+  double lon_substellar;  /* [rad] */
+} thor_forcing;
+
+typedef struct {
+  double T0;          /* isothermal temperature [K] */
+  double p_surf;      /* surface pressure [Pa] */
+  double noise_amp;   /* uniform temperature noise amplitude [K] */
+  uint64_t seed;      /* SplitMix64 counter-based noise (see thor_state_init) */
+  int planet_index;   /* counter offset of this planet in an ensemble */
+} thor_init;
+
+/* Device bytes thor_state_init needs for this grid and configuration. */
+int thor_state_bytes(const thor_grid *g, const thor_vertical *v,
+                     const thor_numerics *num, size_t *bytes);
+
+/* Build the initial state and upload grid and state to the device.
+ *
+ * Initial state: isothermal T0 in discrete hydrostatic balance with the
+ * vertical momentum equation, p at the first centre = p_surf exp(-g dz /
+ * (2 Rd T0)), rest; then T += eps at fixed p, eps uniform in
+ * [-noise_amp, noise_amp) from one SplitMix64 output step of
+ * seed XOR (planet_index 2^40 + col 2^20 + lev).
+ *
+ * dev_buf: caller-owned device memory of at least thor_state_bytes bytes,
+ *   256-byte aligned; it must stay allocated and unmoved for the life of the
+ *   state and is never freed by the library.
+ * hip_stream: the hipStream_t every later call enqueues on (NULL = default).
+ * EINVAL: bad configuration (dt <= 0, n_lev outside 1..64, z_top <= 0,
+ *   g dz / 2 >= Rd T0, Cp <= Rd, ...).  ENOMEM: dev_bytes too small.
+ * EHIP: copy failure.  The call synchronises the stream before returning. */
+int thor_state_init(const thor_grid *g, const thor_planet *planet,
+                    const thor_vertical *v, const thor_numerics *num,
+                    const thor_forcing *forcing, const thor_init *init,
+                    void *dev_buf, size_t dev_bytes, void *hip_stream,
+                    thor_state **out);
+
+/* Advance n_large large steps of dt, each the three RK stages of Sec. 3 with
+ * 1, n/2 and n acoustic substeps (n = n_acoustic; 1 + 3n/2 substeps per large
+ * step), followed by the Newtonian relaxation if configured.  Asynchronous
+ * on the state's stream.  EINVAL (nothing enqueued): n_large < 0,
+ * n_acoustic < 2 or odd. */
+int thor_step(thor_state *s, int n_large, int n_acoustic);
+
+/* Diagnostics (synchronise the stream; host_out is caller-owned). */
+enum {
+  THOR_DIAG_MASS = 1,          /* 1 double: sum rho A_c r_k^2 dz (A_c unit sphere) */
+  THOR_DIAG_FIELD = 2,         /* n_col * n_lev doubles of field `field` */
+  THOR_DIAG_STATE_EXPORT = 3,  /* checkpoint blob of thor_state_blob_bytes */
+  THOR_DIAG_SCALARS = 4        /* thor_scalars */
+};
+enum {
+  THOR_F_T = 0, THOR_F_U, THOR_F_V, THOR_F_W, THOR_F_P, THOR_F_RHO,
+  THOR_F_RHOTHETA, THOR_F_MX, THOR_F_MY, THOR_F_MZ,
+  THOR_F_WI   /* rho v_r at the interfaces 0..n_lev-1 (the lid value is 0) */
+};
+typedef struct {
+  double mass, max_speed, max_w, min_T, max_T;
+} thor_scalars;
+
+/* ENONFINITE if the state holds NaN or Inf (the output is still written).
+ * EINVAL: unknown kind/field or out_bytes too small. */
+int thor_diag(thor_state *s, int kind, int field, void *host_out, size_t out_bytes);
+
+/* Size of the checkpoint blob (prognostic fields, FP64, canonical layout). */
+size_t thor_state_blob_bytes(const thor_state *s);
+
+/* Restore prognostic fields from a blob of thor_diag(STATE_EXPORT).
+ * Synchronises.  EINVAL: wrong size or header. */
+int thor_state_import(thor_state *s, const void *blob, size_t bytes);
+
+/* Mean duration [ms] of the last n kernel launches of the named kernel family
+ * recorded with HIP events when timing is on (see thor_set_timing).  Used to
+ * measure achieved bandwidth; returns EINVAL for an unknown name. */
+int thor_set_timing(thor_state *s, int on);
+int thor_kernel_time(thor_state *s, const char *name, double *mean_ms, int *count);
+
+void thor_state_free(thor_state *s);   /* never frees dev_buf */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* THOR_H */

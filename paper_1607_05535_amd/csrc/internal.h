@@ -1,0 +1,38 @@
+// Internal declarations shared by the host sources of libthor.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/thor.h"
+
+namespace thor {
+
+struct Vec3 {
+  double x, y, z;
+};
+
+// Host-side grid: topology, unit-sphere geometry and operator coefficients.
+struct Grid {
+  int glevel = 0;
+  int smooth = 1;
+  int64_t n = 0;
+  int spring_iters = 0;
+  bool converged = true;
+  std::vector<int32_t> nbr;      // [n][6], -1 pads pentagons
+  std::vector<uint8_t> deg;      // 5 or 6
+  std::vector<Vec3> pos;         // cell points (unit sphere)
+  std::vector<double> area;      // control-volume area (unit sphere)
+  std::vector<double> div_coef;  // [n][7][3]
+  std::vector<double> lap_coef;  // [n][6]
+};
+
+void set_error(const std::string &msg);
+void clear_error();
+
+}  // namespace thor
+
+struct thor_grid {
+  thor::Grid g;
+};

@@ -1,0 +1,558 @@
+// Host runtime of libthor: state set-up in caller-owned device memory, the
+// large-step schedule (Sec. 3: WS-RK3 stages of 1, n/2 and n acoustic
+// substeps, Sec. 5 physics after the stages), HIP-graph replay of a large
+// step, diagnostics, checkpoints and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace thor {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+
+namespace {
+
+// SplitMix64 output step (Steele, Lea and Flood 2014) of a counter state.
+inline uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Assigns consecutive 256-byte aligned slices of a device buffer.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <typename T>
+  T *take(size_t count) {
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += align256(count * sizeof(T));
+    return p;
+  }
+};
+
+template <typename H>
+void carve(Carver &cv, Fields<H> &f, size_t N, size_t L) {
+  const size_t NL = N * L;
+  f.nbr = cv.take<int32_t>(N * 6);
+  f.dc = cv.take<H>(N * 21);
+  f.lc = cv.take<H>(N * 6);
+  f.rhat = cv.take<H>(N * 3);
+  f.area = cv.take<double>(N);
+  f.teq = cv.take<double>(N);
+  f.rho = cv.take<double>(NL);
+  f.rth = cv.take<double>(NL);
+  f.W = cv.take<double>(NL);
+  f.Mx = cv.take<H>(NL);
+  f.My = cv.take<H>(NL);
+  f.Mz = cv.take<H>(NL);
+  f.ps = cv.take<H>(NL);
+  f.rho_t = cv.take<double>(NL);
+  f.rth_t = cv.take<double>(NL);
+  f.W_t = cv.take<double>(NL);
+  f.p_t = cv.take<double>(NL);
+  f.Mx_t = cv.take<H>(NL);
+  f.My_t = cv.take<H>(NL);
+  f.Mz_t = cv.take<H>(NL);
+  f.FMx = cv.take<H>(NL);
+  f.FMy = cv.take<H>(NL);
+  f.FMz = cv.take<H>(NL);
+  f.FW = cv.take<double>(NL);
+  f.Hrho = cv.take<double>(NL);
+  f.Hrth = cv.take<double>(NL);
+  f.SMx = cv.take<H>(NL);
+  f.SMy = cv.take<H>(NL);
+  f.SMz = cv.take<H>(NL);
+  f.SW = cv.take<double>(NL);
+  f.thL = cv.take<H>(NL);
+  f.Gam = cv.take<H>(NL);
+  f.D = cv.take<H>(NL);
+  f.Gx = cv.take<H>(NL);
+  f.Gy = cv.take<H>(NL);
+  f.Gz = cv.take<H>(NL);
+  f.Dt = cv.take<H>(NL);
+  f.GDx = cv.take<H>(NL);
+  f.GDy = cv.take<H>(NL);
+  f.GDz = cv.take<H>(NL);
+  f.T = cv.take<double>(NL);
+  f.vx = cv.take<double>(NL);
+  f.vy = cv.take<double>(NL);
+  f.vz = cv.take<double>(NL);
+  f.wI = cv.take<double>(NL);
+  f.Xrho = cv.take<double>(NL);
+  f.Xvx = cv.take<double>(NL);
+  f.Xvy = cv.take<double>(NL);
+  f.Xvz = cv.take<double>(NL);
+  f.Xw = cv.take<double>(NL);
+  f.XT = cv.take<double>(NL);
+  // the staging/diagnostic area doubles as checkpoint staging (6 fields)
+  f.diag = cv.take<double>(6 * NL);
+  f.partial = cv.take<double>(2 * ((N + 3) / 4 + 16));
+}
+
+bool hip_ok(hipError_t e, const char *what) {
+  if (e == hipSuccess) return true;
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return false;
+}
+
+}  // namespace
+}  // namespace thor
+
+using namespace thor;
+
+struct TimedLaunch {
+  std::string family;
+  hipEvent_t start, stop;
+};
+
+struct thor_state {
+  int precision = THOR_FP64;
+  Consts c{};
+  Fields<double> f64{};
+  Fields<float> f32{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::map<int, hipGraphExec_t> graphs;   // one large step per n_acoustic
+  bool timing = false;
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> event_pool;
+  size_t next_event = 0;
+  int64_t n_col = 0;
+  int n_lev = 0;
+};
+
+namespace {
+
+bool validate(const thor_planet *pl, const thor_vertical *v, const thor_numerics *num,
+              const thor_forcing *fo, const thor_init *in) {
+  if (!pl || !v || !num || !fo || !in) { set_error("thor_state_init: NULL argument"); return false; }
+  if (!(pl->radius > 0 && pl->gravity >= 0 && pl->Rd > 0 && pl->Cp > pl->Rd && pl->p_ref > 0)) {
+    set_error("thor_state_init: planet needs radius > 0, Rd > 0, Cp > Rd, p_ref > 0");
+    return false;
+  }
+  if (v->n_lev < 1 || v->n_lev > 64 || !(v->z_top > 0)) {
+    set_error("thor_state_init: n_lev must be 1..64 and z_top > 0");
+    return false;
+  }
+  if (!(num->dt > 0) || !(num->diff_D >= 0) || (num->precision != THOR_FP64 && num->precision != THOR_MIXED) ||
+      (num->div_damp != 0 && num->div_damp != 1)) {
+    set_error("thor_state_init: numerics need dt > 0, diff_D >= 0, precision FP64|MIXED, div_damp 0|1");
+    return false;
+  }
+  if (fo->kind != THOR_FORCING_NONE && fo->kind != THOR_FORCING_NEWTONIAN) {
+    set_error("thor_state_init: unknown forcing kind");
+    return false;
+  }
+  if (fo->kind == THOR_FORCING_NEWTONIAN && !(fo->tau > 0)) {
+    set_error("thor_state_init: Newtonian forcing needs tau > 0");
+    return false;
+  }
+  if (!(in->T0 > 0 && in->p_surf > 0 && in->noise_amp >= 0 && in->noise_amp < in->T0)) {
+    set_error("thor_state_init: init needs T0 > 0, p_surf > 0, 0 <= noise_amp < T0");
+    return false;
+  }
+  if (in->planet_index < 0 || in->planet_index > 0xFFFFFF) {
+    set_error("thor_state_init: planet_index out of range");
+    return false;
+  }
+  double dz = v->z_top / v->n_lev;
+  if (!(0.5 * pl->gravity * dz < pl->Rd * in->T0)) {
+    set_error("thor_state_init: layers too thick for a discrete hydrostatic state (g dz / 2 >= Rd T0)");
+    return false;
+  }
+  return true;
+}
+
+size_t bytes_for(int precision, size_t N, size_t L) {
+  Carver cv{nullptr};
+  if (precision == THOR_MIXED) {
+    Fields<float> f;
+    carve(cv, f, N, L);
+  } else {
+    Fields<double> f;
+    carve(cv, f, N, L);
+  }
+  return cv.off;
+}
+
+template <typename H>
+int upload(thor_state *s, const Grid &G, const thor_planet *pl, const thor_vertical *v,
+           const thor_forcing *fo, const thor_init *in, char *base, Fields<H> &f) {
+  Carver cv{base};
+  const size_t N = G.n, L = v->n_lev, NL = N * L;
+  carve(cv, f, N, L);
+  const Consts &c = s->c;
+  // geometry
+  std::vector<H> dc(G.div_coef.begin(), G.div_coef.end());
+  std::vector<H> lc(G.lap_coef.begin(), G.lap_coef.end());
+  std::vector<H> rh(N * 3);
+  std::vector<double> teq(N);
+  for (size_t i = 0; i < N; ++i) {
+    const Vec3 p = G.pos[i];
+    rh[3 * i] = (H)p.x;
+    rh[3 * i + 1] = (H)p.y;
+    rh[3 * i + 2] = (H)p.z;
+    double lam = std::sqrt(p.x * p.x + p.y * p.y) < 1e-12 ? 0.0 : std::atan2(p.y, p.x);
+    double phi = std::asin(std::fmin(1.0, std::fmax(-1.0, p.z)));
+    teq[i] = fo->T_mean + 0.5 * fo->dT_daynight * std::cos(phi) * std::cos(lam - fo->lon_substellar);
+  }
+  // initial state: isothermal columns in discrete hydrostatic balance
+  std::vector<double> rcol(L), pcol(L);
+  const double RT = pl->Rd * in->T0, half = 0.5 * pl->gravity * c.dz;
+  rcol[0] = in->p_surf * std::exp(-half / RT) / RT;
+  for (size_t k = 1; k < L; ++k) rcol[k] = rcol[k - 1] * (RT - half) / (RT + half);
+  for (size_t k = 0; k < L; ++k) pcol[k] = rcol[k] * RT;
+  std::vector<double> rho(NL), rth(NL), zero(NL, 0.0);
+  std::vector<H> zeroH(NL, (H)0);
+  const uint64_t pbase = (uint64_t)in->planet_index << 40;
+  for (size_t i = 0; i < N; ++i)
+    for (size_t k = 0; k < L; ++k) {
+      uint64_t z = splitmix64(in->seed ^ (pbase + ((uint64_t)i << 20) + k));
+      double u = (double)(z >> 11) * 0x1.0p-53;
+      double T = in->T0 + in->noise_amp * (2.0 * u - 1.0);
+      double p = pcol[k];
+      rho[i * L + k] = p / (pl->Rd * T);
+      rth[i * L + k] = pl->p_ref / pl->Rd * std::pow(p / pl->p_ref, 1.0 / c.gamma);
+    }
+  hipStream_t st = s->stream;
+  bool ok = hip_ok(hipMemcpyAsync((void *)f.nbr, G.nbr.data(), N * 6 * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy nbr") &&
+            hip_ok(hipMemcpyAsync((void *)f.dc, dc.data(), dc.size() * sizeof(H), hipMemcpyHostToDevice, st), "copy dc") &&
+            hip_ok(hipMemcpyAsync((void *)f.lc, lc.data(), lc.size() * sizeof(H), hipMemcpyHostToDevice, st), "copy lc") &&
+            hip_ok(hipMemcpyAsync((void *)f.rhat, rh.data(), rh.size() * sizeof(H), hipMemcpyHostToDevice, st), "copy rhat") &&
+            hip_ok(hipMemcpyAsync((void *)f.area, G.area.data(), N * sizeof(double), hipMemcpyHostToDevice, st), "copy area") &&
+            hip_ok(hipMemcpyAsync((void *)f.teq, teq.data(), N * sizeof(double), hipMemcpyHostToDevice, st), "copy teq") &&
+            hip_ok(hipMemcpyAsync(f.rho, rho.data(), NL * sizeof(double), hipMemcpyHostToDevice, st), "copy rho") &&
+            hip_ok(hipMemcpyAsync(f.rth, rth.data(), NL * sizeof(double), hipMemcpyHostToDevice, st), "copy rth") &&
+            hip_ok(hipMemcpyAsync(f.W, zero.data(), NL * sizeof(double), hipMemcpyHostToDevice, st), "copy W") &&
+            hip_ok(hipMemcpyAsync(f.Mx, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy Mx") &&
+            hip_ok(hipMemcpyAsync(f.My, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy My") &&
+            hip_ok(hipMemcpyAsync(f.Mz, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy Mz") &&
+            hip_ok(hipMemcpyAsync(f.ps, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy ps") &&
+            hip_ok(hipStreamSynchronize(st), "init synchronize");
+  return ok ? THOR_OK : THOR_EHIP;
+}
+
+hipEvent_t next_event(thor_state *s) {
+  if (s->next_event == s->event_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    s->event_pool.push_back(e);
+  }
+  return s->event_pool[s->next_event++];
+}
+
+// Enqueue one launch, bracketed by timing events when timing is on.
+template <typename F>
+void timed(thor_state *s, hipStream_t st, const char *family, F &&launch) {
+  if (!s->timing) {
+    launch();
+    return;
+  }
+  hipEvent_t a = next_event(s), b = next_event(s);
+  (void)hipEventRecord(a, st);
+  launch();
+  (void)hipEventRecord(b, st);
+  s->timed.push_back({family, a, b});
+}
+
+template <typename H>
+void enqueue_large_step(thor_state *s, const Fields<H> &f, int n, hipStream_t st) {
+  const Consts &c = s->c;
+  timed(s, st, "large", [&] { launch_large(f, c, st); });
+  const double dt = c.dt;
+  const int ns[3] = {1, n / 2, n};
+  const double dtau[3] = {dt / 3.0, dt / n, dt / n};
+  for (int stage = 0; stage < 3; ++stage) {
+    timed(s, st, "slow", [&] { launch_slow(f, c, stage == 0, st); });
+    for (int i = 0; i < ns[stage]; ++i) {
+      const bool first = i == 0;
+      timed(s, st, "hmom", [&] { launch_hmom(f, c, dtau[stage], first, st); });
+      timed(s, st, "vert", [&] { launch_vert(f, c, dtau[stage], first, st); });
+      if (c.div_damp && i + 1 < ns[stage]) timed(s, st, "graddiv", [&] { launch_graddiv(f, c, st); });
+    }
+  }
+  if (c.forcing == THOR_FORCING_NEWTONIAN) timed(s, st, "newton", [&] { launch_newton(f, c, st); });
+}
+
+void enqueue(thor_state *s, int n, hipStream_t st) {
+  if (s->precision == THOR_MIXED) enqueue_large_step(s, s->f32, n, st);
+  else enqueue_large_step(s, s->f64, n, st);
+}
+
+int graph_for(thor_state *s, int n, hipGraphExec_t *out) {
+  auto it = s->graphs.find(n);
+  if (it != s->graphs.end()) {
+    *out = it->second;
+    return THOR_OK;
+  }
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  if (!hip_ok(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed), "graph capture")) return THOR_EHIP;
+  enqueue(s, n, s->cap_stream);
+  if (!hip_ok(hipStreamEndCapture(s->cap_stream, &g), "graph end capture")) return THOR_EHIP;
+  if (!hip_ok(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate")) {
+    (void)hipGraphDestroy(g);
+    return THOR_EHIP;
+  }
+  (void)hipGraphDestroy(g);
+  s->graphs[n] = ex;
+  *out = ex;
+  return THOR_OK;
+}
+
+template <typename H>
+int diag_impl(thor_state *s, const Fields<H> &f, int kind, int field, void *host_out, size_t out_bytes) {
+  const Consts &c = s->c;
+  const size_t NL = (size_t)c.N * c.L;
+  hipStream_t st = s->stream;
+  if (kind == THOR_DIAG_FIELD) {
+    if (field < THOR_F_T || field > THOR_F_WI) { set_error("thor_diag: unknown field"); return THOR_EINVAL; }
+    if (out_bytes < NL * sizeof(double)) { set_error("thor_diag: out_bytes too small"); return THOR_EINVAL; }
+  } else if (kind == THOR_DIAG_MASS) {
+    if (out_bytes < sizeof(double)) { set_error("thor_diag: out_bytes too small"); return THOR_EINVAL; }
+  } else if (kind == THOR_DIAG_SCALARS) {
+    if (out_bytes < sizeof(thor_scalars)) { set_error("thor_diag: out_bytes too small"); return THOR_EINVAL; }
+  } else if (kind == THOR_DIAG_STATE_EXPORT) {
+    if (out_bytes < thor_state_blob_bytes(s)) { set_error("thor_diag: out_bytes too small"); return THOR_EINVAL; }
+  } else {
+    set_error("thor_diag: unknown kind");
+    return THOR_EINVAL;
+  }
+  // mass and non-finite scan
+  int nb = 0;
+  launch_mass(f, c, st, &nb);
+  std::vector<double> part(2 * (size_t)nb);
+  if (!hip_ok(hipMemcpyAsync(part.data(), f.partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, st), "copy partial") ||
+      !hip_ok(hipStreamSynchronize(st), "diag synchronize"))
+    return THOR_EHIP;
+  double mass = 0.0, bad = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    mass += part[2 * i];
+    bad += part[2 * i + 1];
+  }
+  auto field_to_host = [&](int fld, double *dst) -> bool {
+    launch_diag_field(f, c, fld, st);
+    return hip_ok(hipMemcpyAsync(dst, f.diag, NL * sizeof(double), hipMemcpyDeviceToHost, st), "copy field") &&
+           hip_ok(hipStreamSynchronize(st), "diag synchronize");
+  };
+  if (kind == THOR_DIAG_MASS) {
+    *(double *)host_out = mass;
+  } else if (kind == THOR_DIAG_FIELD) {
+    if (!field_to_host(field, (double *)host_out)) return THOR_EHIP;
+  } else if (kind == THOR_DIAG_SCALARS) {
+    std::vector<double> a(NL), b(NL), w(NL);
+    thor_scalars sc{};
+    sc.mass = mass;
+    if (!field_to_host(THOR_F_U, a.data()) || !field_to_host(THOR_F_V, b.data()) || !field_to_host(THOR_F_W, w.data()))
+      return THOR_EHIP;
+    double ms = 0, mw = 0;
+    for (size_t i = 0; i < NL; ++i) {
+      ms = std::fmax(ms, std::sqrt(a[i] * a[i] + b[i] * b[i] + w[i] * w[i]));
+      mw = std::fmax(mw, std::fabs(w[i]));
+    }
+    if (!field_to_host(THOR_F_T, a.data())) return THOR_EHIP;
+    double tmin = a[0], tmax = a[0];
+    for (size_t i = 0; i < NL; ++i) {
+      tmin = std::fmin(tmin, a[i]);
+      tmax = std::fmax(tmax, a[i]);
+    }
+    sc.max_speed = ms;
+    sc.max_w = mw;
+    sc.min_T = tmin;
+    sc.max_T = tmax;
+    std::memcpy(host_out, &sc, sizeof(sc));
+  } else {
+    // checkpoint: header (magic, N, L) then rho, Mx, My, Mz, rho theta, W
+    double *out = (double *)host_out;
+    out[0] = 1953460050.0;  // 'THOR' tag
+    out[1] = (double)c.N;
+    out[2] = (double)c.L;
+    out[3] = 0.0;
+    const int flds[6] = {THOR_F_RHO, THOR_F_MX, THOR_F_MY, THOR_F_MZ, THOR_F_RHOTHETA, THOR_F_WI};
+    for (int i = 0; i < 6; ++i)
+      if (!field_to_host(flds[i], out + 4 + i * NL)) return THOR_EHIP;
+  }
+  if (bad > 0) {
+    set_error("thor_diag: state holds non-finite values");
+    return THOR_ENONFINITE;
+  }
+  return THOR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *thor_last_error(void) { return g_err.c_str(); }
+
+int thor_state_bytes(const thor_grid *g, const thor_vertical *v, const thor_numerics *num, size_t *bytes) {
+  clear_error();
+  if (!g || !v || !num || !bytes) { set_error("thor_state_bytes: NULL argument"); return THOR_EINVAL; }
+  if (v->n_lev < 1 || v->n_lev > 64) { set_error("thor_state_bytes: n_lev must be 1..64"); return THOR_EINVAL; }
+  if (num->precision != THOR_FP64 && num->precision != THOR_MIXED) { set_error("thor_state_bytes: bad precision"); return THOR_EINVAL; }
+  *bytes = bytes_for(num->precision, (size_t)g->g.n, (size_t)v->n_lev);
+  return THOR_OK;
+}
+
+int thor_state_init(const thor_grid *g, const thor_planet *pl, const thor_vertical *v,
+                    const thor_numerics *num, const thor_forcing *fo, const thor_init *in,
+                    void *dev_buf, size_t dev_bytes, void *hip_stream, thor_state **out) {
+  clear_error();
+  if (!g || !out || !dev_buf) { set_error("thor_state_init: NULL argument"); return THOR_EINVAL; }
+  *out = nullptr;
+  if (!validate(pl, v, num, fo, in)) return THOR_EINVAL;
+  if (((uintptr_t)dev_buf & 255) != 0) { set_error("thor_state_init: dev_buf must be 256-byte aligned"); return THOR_EINVAL; }
+  const size_t need = bytes_for(num->precision, (size_t)g->g.n, (size_t)v->n_lev);
+  if (dev_bytes < need) {
+    set_error("thor_state_init: dev_bytes smaller than thor_state_bytes");
+    return THOR_ENOMEM;
+  }
+  thor_state *s = new (std::nothrow) thor_state;
+  if (!s) { set_error("thor_state_init: out of host memory"); return THOR_ENOMEM; }
+  s->precision = num->precision;
+  s->stream = (hipStream_t)hip_stream;
+  s->n_col = g->g.n;
+  s->n_lev = v->n_lev;
+  Consts &c = s->c;
+  c.N = (int)g->g.n;
+  c.L = v->n_lev;
+  c.cpw = 64 / v->n_lev;
+  c.radius = pl->radius;
+  c.omega = pl->omega;
+  c.grav = pl->gravity;
+  c.Rd = pl->Rd;
+  c.Cp = pl->Cp;
+  c.Cv = pl->Cp - pl->Rd;
+  c.gamma = pl->Cp / c.Cv;
+  c.p_ref = pl->p_ref;
+  c.dz = v->z_top / v->n_lev;
+  const double dbar = std::sqrt(2.0 * M_PI / 5.0) * pl->radius / std::ldexp(1.0, g->g.glevel);  // Eq. grid_qts
+  c.Kd = num->diff_D * std::pow(dbar, 4) / num->dt;                                             // Eq. kd
+  c.dt = num->dt;
+  c.div_damp = num->div_damp;
+  c.forcing = fo->kind;
+  c.tau = fo->kind == THOR_FORCING_NEWTONIAN ? fo->tau : 1.0;
+  if (!hip_ok(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking), "capture stream")) {
+    delete s;
+    return THOR_EHIP;
+  }
+  int rc;
+  try {
+    rc = s->precision == THOR_MIXED ? upload(s, g->g, pl, v, fo, in, (char *)dev_buf, s->f32)
+                                    : upload(s, g->g, pl, v, fo, in, (char *)dev_buf, s->f64);
+  } catch (const std::bad_alloc &) {
+    set_error("thor_state_init: out of host memory");
+    rc = THOR_ENOMEM;
+  }
+  if (rc != THOR_OK) {
+    (void)hipStreamDestroy(s->cap_stream);
+    delete s;
+    return rc;
+  }
+  *out = s;
+  return THOR_OK;
+}
+
+int thor_step(thor_state *s, int n_large, int n_acoustic) {
+  clear_error();
+  if (!s) { set_error("thor_step: NULL state"); return THOR_EINVAL; }
+  if (n_large < 0) { set_error("thor_step: n_large must be >= 0"); return THOR_EINVAL; }
+  if (n_acoustic < 2 || (n_acoustic & 1)) { set_error("thor_step: n_acoustic must be even and >= 2"); return THOR_EINVAL; }
+  if (n_large == 0) return THOR_OK;
+  if (s->timing) {
+    for (int i = 0; i < n_large; ++i) enqueue(s, n_acoustic, s->stream);
+    return hip_ok(hipGetLastError(), "kernel launch") ? THOR_OK : THOR_EHIP;
+  }
+  hipGraphExec_t ex;
+  int rc = graph_for(s, n_acoustic, &ex);
+  if (rc != THOR_OK) return rc;
+  for (int i = 0; i < n_large; ++i)
+    if (!hip_ok(hipGraphLaunch(ex, s->stream), "graph launch")) return THOR_EHIP;
+  return THOR_OK;
+}
+
+int thor_diag(thor_state *s, int kind, int field, void *host_out, size_t out_bytes) {
+  clear_error();
+  if (!s || !host_out) { set_error("thor_diag: NULL argument"); return THOR_EINVAL; }
+  return s->precision == THOR_MIXED ? diag_impl(s, s->f32, kind, field, host_out, out_bytes)
+                                    : diag_impl(s, s->f64, kind, field, host_out, out_bytes);
+}
+
+size_t thor_state_blob_bytes(const thor_state *s) {
+  if (!s) return 0;
+  return (4 + 6 * (size_t)s->c.N * s->c.L) * sizeof(double);
+}
+
+int thor_state_import(thor_state *s, const void *blob, size_t bytes) {
+  clear_error();
+  if (!s || !blob) { set_error("thor_state_import: NULL argument"); return THOR_EINVAL; }
+  const double *b = (const double *)blob;
+  if (bytes != thor_state_blob_bytes(s) || b[0] != 1953460050.0 || b[1] != (double)s->c.N || b[2] != (double)s->c.L) {
+    set_error("thor_state_import: blob does not match this state");
+    return THOR_EINVAL;
+  }
+  const size_t NL = (size_t)s->c.N * s->c.L;
+  double *stage = s->precision == THOR_MIXED ? s->f32.diag : s->f64.diag;
+  if (!hip_ok(hipMemcpyAsync(stage, b + 4, 6 * NL * sizeof(double), hipMemcpyHostToDevice, s->stream), "copy blob"))
+    return THOR_EHIP;
+  if (s->precision == THOR_MIXED) launch_to_state(s->f32, s->c, stage, s->stream);
+  else launch_to_state(s->f64, s->c, stage, s->stream);
+  return hip_ok(hipStreamSynchronize(s->stream), "import synchronize") ? THOR_OK : THOR_EHIP;
+}
+
+int thor_set_timing(thor_state *s, int on) {
+  clear_error();
+  if (!s) { set_error("thor_set_timing: NULL state"); return THOR_EINVAL; }
+  if (!hip_ok(hipStreamSynchronize(s->stream), "timing synchronize")) return THOR_EHIP;
+  s->timing = on != 0;
+  s->timed.clear();
+  s->next_event = 0;
+  return THOR_OK;
+}
+
+int thor_kernel_time(thor_state *s, const char *name, double *mean_ms, int *count) {
+  clear_error();
+  if (!s || !name || !mean_ms || !count) { set_error("thor_kernel_time: NULL argument"); return THOR_EINVAL; }
+  static const char *known[] = {"large", "slow", "hmom", "vert", "graddiv", "newton"};
+  bool ok = false;
+  for (auto k : known) ok = ok || std::strcmp(k, name) == 0;
+  if (!ok) { set_error("thor_kernel_time: unknown kernel family"); return THOR_EINVAL; }
+  if (!hip_ok(hipStreamSynchronize(s->stream), "timing synchronize")) return THOR_EHIP;
+  double sum = 0.0;
+  int n = 0;
+  for (auto &t : s->timed)
+    if (t.family == name) {
+      float ms = 0.f;
+      if (!hip_ok(hipEventElapsedTime(&ms, t.start, t.stop), "event elapsed")) return THOR_EHIP;
+      sum += ms;
+      ++n;
+    }
+  *mean_ms = n ? sum / n : 0.0;
+  *count = n;
+  return THOR_OK;
+}
+
+void thor_state_free(thor_state *s) {
+  if (!s) return;
+  for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto e : s->event_pool) (void)hipEventDestroy(e);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  delete s;
+}
+
+}  // extern "C"

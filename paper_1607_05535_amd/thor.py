@@ -1,0 +1,285 @@
+"""ctypes binding of libthor (include/thor.h): argument marshalling only.
+
+Every computation happens inside libthor.so; PyTorch supplies the device
+buffer and the HIP stream.  Importing torch before loading the library makes
+libthor bind to the HIP runtime torch already loaded.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libthor.so")
+
+THOR_OK, THOR_EINVAL, THOR_ENOMEM, THOR_EHIP, THOR_ENONFINITE, THOR_ENOTCONV = 0, -1, -2, -3, -4, -5
+THOR_FP64, THOR_MIXED = 0, 1
+THOR_FORCING_NONE, THOR_FORCING_NEWTONIAN = 0, 1
+THOR_DIAG_MASS, THOR_DIAG_FIELD, THOR_DIAG_STATE_EXPORT, THOR_DIAG_SCALARS = 1, 2, 3, 4
+FIELDS = {"T": 0, "u": 1, "v": 2, "w": 3, "p": 4, "rho": 5, "rhotheta": 6,
+          "Mx": 7, "My": 8, "Mz": 9, "W": 10}
+
+EXPORTED = ["thor_last_error", "thor_grid_params_default", "thor_grid_build", "thor_grid_info",
+            "thor_grid_export", "thor_grid_coefficients", "thor_grid_free", "thor_state_bytes",
+            "thor_state_init", "thor_step", "thor_diag", "thor_state_blob_bytes",
+            "thor_state_import", "thor_set_timing", "thor_kernel_time", "thor_state_free"]
+
+
+class ThorError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libthor error {code}: {msg}")
+        self.code = code
+
+
+class GridParams(ctypes.Structure):
+    _fields_ = [("glevel", ctypes.c_int), ("smooth", ctypes.c_int), ("k", ctypes.c_double),
+                ("beta", ctypes.c_double), ("alpha", ctypes.c_double), ("dt", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int)]
+
+
+class Planet(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("radius", "omega", "gravity", "Rd", "Cp", "p_ref")]
+
+
+class Vertical(ctypes.Structure):
+    _fields_ = [("n_lev", ctypes.c_int), ("z_top", ctypes.c_double)]
+
+
+class Numerics(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("diff_D", ctypes.c_double), ("div_damp", ctypes.c_int),
+                ("precision", ctypes.c_int)]
+
+
+class Forcing(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("tau", ctypes.c_double), ("T_mean", ctypes.c_double),
+                ("dT_daynight", ctypes.c_double), ("lon_substellar", ctypes.c_double)]
+
+
+class Init(ctypes.Structure):
+    _fields_ = [("T0", ctypes.c_double), ("p_surf", ctypes.c_double), ("noise_amp", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("planet_index", ctypes.c_int)]
+
+
+class Scalars(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("mass", "max_speed", "max_w", "min_T", "max_T")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libthor.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libthor.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64p, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int), \
+        ctypes.POINTER(ctypes.c_double)
+    L.thor_last_error.restype = ctypes.c_char_p
+    L.thor_grid_params_default.argtypes = [ctypes.c_int, ctypes.POINTER(GridParams)]
+    L.thor_grid_params_default.restype = None
+    L.thor_grid_build.argtypes = [ctypes.POINTER(GridParams), ctypes.POINTER(vp)]
+    L.thor_grid_info.argtypes = [vp, i64p, ip, ip]
+    L.thor_grid_export.argtypes = [vp, vp, vp, vp]
+    L.thor_grid_coefficients.argtypes = [vp, vp, vp]
+    L.thor_grid_free.argtypes = [vp]
+    L.thor_grid_free.restype = None
+    L.thor_state_bytes.argtypes = [vp, ctypes.POINTER(Vertical), ctypes.POINTER(Numerics),
+                                   ctypes.POINTER(ctypes.c_size_t)]
+    L.thor_state_init.argtypes = [vp, ctypes.POINTER(Planet), ctypes.POINTER(Vertical),
+                                  ctypes.POINTER(Numerics), ctypes.POINTER(Forcing), ctypes.POINTER(Init),
+                                  vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.thor_step.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.thor_diag.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t]
+    L.thor_state_blob_bytes.argtypes = [vp]
+    L.thor_state_blob_bytes.restype = ctypes.c_size_t
+    L.thor_state_import.argtypes = [vp, vp, ctypes.c_size_t]
+    L.thor_set_timing.argtypes = [vp, ctypes.c_int]
+    L.thor_kernel_time.argtypes = [vp, ctypes.c_char_p, dp, ip]
+    L.thor_state_free.argtypes = [vp]
+    L.thor_state_free.restype = None
+    _lib = L
+    return L
+
+
+def _check(rc, allow=()):
+    if rc != THOR_OK and rc not in allow:
+        raise ThorError(rc, lib().thor_last_error().decode())
+    return rc
+
+
+# ---------------------------------------------------------------------------
+# One Python function per C entry point
+# ---------------------------------------------------------------------------
+def thor_grid_params_default(glevel):
+    p = GridParams()
+    lib().thor_grid_params_default(glevel, ctypes.byref(p))
+    return p
+
+
+def thor_grid_build(params):
+    """Returns (handle, rc); rc is THOR_OK or THOR_ENOTCONV."""
+    h = ctypes.c_void_p()
+    rc = _check(lib().thor_grid_build(ctypes.byref(params), ctypes.byref(h)), allow=(THOR_ENOTCONV,))
+    return h, rc
+
+
+def thor_grid_info(h):
+    n, npent, it = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().thor_grid_info(h, ctypes.byref(n), ctypes.byref(npent), ctypes.byref(it)))
+    return n.value, npent.value, it.value
+
+
+def thor_grid_export(h, n):
+    nbr = np.empty((n, 6), dtype=np.int32)
+    xyz = np.empty((n, 3))
+    area = np.empty(n)
+    _check(lib().thor_grid_export(h, nbr.ctypes.data, xyz.ctypes.data, area.ctypes.data))
+    return nbr, xyz, area
+
+
+def thor_grid_coefficients(h, n):
+    dc = np.empty((n, 7, 3))
+    lc = np.empty((n, 6))
+    _check(lib().thor_grid_coefficients(h, dc.ctypes.data, lc.ctypes.data))
+    return dc, lc
+
+
+def thor_grid_free(h):
+    lib().thor_grid_free(h)
+
+
+def thor_state_bytes(gh, vert, num):
+    out = ctypes.c_size_t()
+    _check(lib().thor_state_bytes(gh, ctypes.byref(vert), ctypes.byref(num), ctypes.byref(out)))
+    return out.value
+
+
+def thor_state_init(gh, planet, vert, num, forcing, init, dev_ptr, dev_bytes, stream_ptr):
+    h = ctypes.c_void_p()
+    _check(lib().thor_state_init(gh, ctypes.byref(planet), ctypes.byref(vert), ctypes.byref(num),
+                                 ctypes.byref(forcing), ctypes.byref(init), ctypes.c_void_p(dev_ptr),
+                                 dev_bytes, ctypes.c_void_p(stream_ptr), ctypes.byref(h)))
+    return h
+
+
+def thor_step(sh, n_large, n_acoustic):
+    _check(lib().thor_step(sh, n_large, n_acoustic))
+
+
+def thor_diag(sh, kind, field, out):
+    """out: a writable numpy array (host).  Returns the rc (ENONFINITE kept)."""
+    return _check(lib().thor_diag(sh, kind, field, out.ctypes.data, out.nbytes),
+                  allow=(THOR_ENONFINITE,))
+
+
+def thor_state_blob_bytes(sh):
+    return lib().thor_state_blob_bytes(sh)
+
+
+def thor_state_import(sh, blob):
+    _check(lib().thor_state_import(sh, blob.ctypes.data, blob.nbytes))
+
+
+def thor_set_timing(sh, on):
+    _check(lib().thor_set_timing(sh, int(on)))
+
+
+def thor_kernel_time(sh, name):
+    ms, cnt = ctypes.c_double(), ctypes.c_int()
+    _check(lib().thor_kernel_time(sh, name.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+def thor_state_free(sh):
+    lib().thor_state_free(sh)
+
+
+# ---------------------------------------------------------------------------
+# Small owning wrappers
+# ---------------------------------------------------------------------------
+class Grid:
+    def __init__(self, glevel, smooth=True, **kw):
+        p = thor_grid_params_default(glevel)
+        p.smooth = int(smooth)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        self.params = p
+        self.handle, self.rc = thor_grid_build(p)
+        self.n, self.n_pent, self.spring_iters = thor_grid_info(self.handle)
+
+    def export(self):
+        return thor_grid_export(self.handle, self.n)
+
+    def coefficients(self):
+        return thor_grid_coefficients(self.handle, self.n)
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                thor_grid_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+def structs_from_workload(w, precision=THOR_FP64):
+    planet = Planet(w.radius, w.omega, w.gravity, w.Rd, w.Cp, w.p_ref)
+    vert = Vertical(w.n_lev, w.z_top)
+    num = Numerics(w.dt, w.diff_D, int(w.div_damp), precision)
+    forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar)
+    init = Init(w.T0, w.p_surf, w.noise_amp, w.seed, 0)
+    return planet, vert, num, forcing, init
+
+
+class State:
+    """A state in a torch-owned device buffer on ``device``."""
+
+    def __init__(self, grid, planet, vert, num, forcing, init, device="cuda:0", stream=None):
+        self.grid = grid
+        self.n_col, self.n_lev = grid.n, vert.n_lev
+        nbytes = thor_state_bytes(grid.handle, vert, num)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.buf.device)
+        self.handle = thor_state_init(grid.handle, planet, vert, num, forcing, init,
+                                      self.buf.data_ptr(), nbytes, self.stream.cuda_stream)
+
+    def step(self, n_large, n_acoustic):
+        thor_step(self.handle, n_large, n_acoustic)
+
+    def field(self, name):
+        out = np.empty((self.n_col, self.n_lev))
+        rc = thor_diag(self.handle, THOR_DIAG_FIELD, FIELDS[name], out)
+        return out, rc
+
+    def mass(self):
+        out = np.empty(1)
+        rc = thor_diag(self.handle, THOR_DIAG_MASS, 0, out)
+        return float(out[0]), rc
+
+    def scalars(self):
+        s = Scalars()
+        arr = np.frombuffer(s, dtype=np.float64)
+        out = np.empty(5)
+        rc = thor_diag(self.handle, THOR_DIAG_SCALARS, 0, out)
+        del arr
+        return dict(zip(("mass", "max_speed", "max_w", "min_T", "max_T"), out)), rc
+
+    def export(self):
+        blob = np.empty(thor_state_blob_bytes(self.handle) // 8)
+        rc = thor_diag(self.handle, THOR_DIAG_STATE_EXPORT, 0, blob)
+        return blob, rc
+
+    def load(self, blob):
+        thor_state_import(self.handle, blob)
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                thor_state_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
