@@ -53,6 +53,7 @@ def run_gpu(w, precision, steps, warmup):
     g = thor.Grid(w.glevel)
     st = thor.State(g, *thor.structs_from_workload(w, precision), device="cuda:0")
     n = w.n_acoustic
+    tuned = thor.thor_autotune(st.handle, n)
     st.step(warmup, n)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -65,10 +66,10 @@ def run_gpu(w, precision, steps, warmup):
     # kernel durations with HIP events on the state's stream
     thor.thor_set_timing(st.handle, 1)
     st.step(steps, n)
-    kt = {k: thor.thor_kernel_time(st.handle, k) for k in ("vert", "hmom", "graddiv", "slow", "large", "newton")}
+    kt = {k: thor.thor_kernel_time(st.handle, k) for k in ("vert", "hmom", "graddiv", "slow", "large")}
     thor.thor_set_timing(st.handle, 0)
     torch.cuda.synchronize()
-    return T, kt, sc
+    return T, kt, sc, tuned
 
 
 def cpu_baseline(w):
@@ -98,6 +99,26 @@ def cpu_baseline(w):
                         f"({t_large:.1f} s: 1 + 3 slow + {w.substeps_per_large} substeps)"))
 
 
+def copy_probe():
+    """A plain device copy of known size (1 GiB read + 1 GiB written): the
+    reference for scaling FETCH_SIZE / WRITE_SIZE counters and for the
+    achievable streaming bandwidth."""
+    import torch
+    n = 1 << 27                       # doubles = 1 GiB
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    T = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n,
+                      "ms": T * 1e3, "GBs_read_plus_write": 16 * n / T / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,7 +126,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only time a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
               file=sys.stderr)
@@ -115,7 +141,7 @@ def main():
     subs = w.substeps_per_large
     updates = w.cells * subs * args.steps
 
-    T64, kt64, sc64 = run_gpu(w, 0, args.steps, args.warmup)
+    T64, kt64, sc64, tuned64 = run_gpu(w, 0, args.steps, args.warmup)
     value = updates / T64
     vmean = kt64["vert"][0] * 1e-3
     vb = vert_bytes_per_cell(w.n_lev, False) * w.cells
@@ -142,9 +168,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": vb, "mean_launch_ms": kt64["vert"][0]},
         "kernel_ms": {k: v[0] for k, v in kt64.items()},
+        "autotuned_wavefronts_per_workgroup": tuned64,
     }
     if not args.no_mixed:
-        T32, kt32, sc32 = run_gpu(w, 1, args.steps, args.warmup)
+        T32, kt32, sc32, tuned32 = run_gpu(w, 1, args.steps, args.warmup)
         vm = kt32["vert"][0] * 1e-3
         vb32 = vert_bytes_per_cell(w.n_lev, True) * w.cells
         out["mixed"] = {"value": updates / T32, "ms_per_step": T32 / args.steps * 1e3,

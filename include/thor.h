@@ -212,6 +212,15 @@ size_t thor_state_blob_bytes(const thor_state *s);
  * Synchronises.  EINVAL: wrong size or header. */
 int thor_state_import(thor_state *s, const void *blob, size_t bytes);
 
+/* Autotuner: for each kernel family ("large", "slow", "hmom", "vert",
+ * "graddiv") time the candidate workgroup sizes (1, 2, 4 or 8 wavefronts,
+ * i.e. column groups of 1-8 x floor(64 / n_lev) columns) inside real large
+ * steps with n_acoustic substeps on this state, keep the fastest, and restore
+ * the state from a checkpoint taken before tuning (the state is unchanged).
+ * Synchronises.  wpb_out (5 ints, may be NULL) receives the choice in the
+ * order above.  EINVAL: n_acoustic < 2 or odd. */
+int thor_autotune(thor_state *s, int n_acoustic, int *wpb_out);
+
 /* Mean duration [ms] of the last n kernel launches of the named kernel family
  * recorded with HIP events when timing is on (see thor_set_timing).  Used to
  * measure achieved bandwidth; returns EINVAL for an unknown name. */
@@ -219,6 +228,44 @@ int thor_set_timing(thor_state *s, int on);
 int thor_kernel_time(thor_state *s, const char *name, double *mean_ms, int *count);
 
 void thor_state_free(thor_state *s);   /* never frees dev_buf */
+
+/* ---------------------------------------------------------------------------
+ * Ensembles of planets (each with its own grid level, layer count, planet
+ * constants, time step and initial state) advanced together: every phase of
+ * the large step is one launch over all members (a device table maps each
+ * workgroup to a member and a local workgroup) and the whole large step is
+ * replayed as one HIP graph.  All members must share the precision.  A member
+ * advanced in an ensemble computes bit-identical results to the same
+ * configuration advanced alone with thor_step.
+ * ------------------------------------------------------------------------- */
+typedef struct thor_batch thor_batch;
+
+/* Device bytes for n members (arrays of n structs). */
+int thor_batch_bytes(int n, const thor_grid *const *grids, const thor_vertical *v,
+                     const thor_numerics *num, size_t *bytes);
+
+/* Initialise member i exactly as thor_state_init would, inside one
+ * caller-owned buffer (256-byte aligned).  EINVAL: any member's
+ * configuration is invalid or precisions differ.  ENOMEM: dev_bytes too
+ * small.  Synchronises. */
+int thor_batch_init(int n, const thor_grid *const *grids, const thor_planet *planets,
+                    const thor_vertical *v, const thor_numerics *num,
+                    const thor_forcing *forcings, const thor_init *inits,
+                    void *dev_buf, size_t dev_bytes, void *hip_stream, thor_batch **out);
+
+/* n_large large steps of every member with n_acoustic substeps (each member
+ * uses its own dt).  Asynchronous.  EINVAL as thor_step. */
+int thor_batch_step(thor_batch *b, int n_large, int n_acoustic);
+
+/* Member i as a thor_state for thor_diag / thor_state_import (thor_step on a
+ * member returns EINVAL).  The handle is owned by the batch. */
+int thor_batch_member(thor_batch *b, int i, thor_state **out);
+
+/* Workgroup-size autotuner over whole ensemble large steps (see
+ * thor_autotune); the members' states are restored afterwards. */
+int thor_batch_autotune(thor_batch *b, int n_acoustic, int *wpb_out);
+
+void thor_batch_free(thor_batch *b);   /* frees the members; never frees dev_buf */
 
 #ifdef __cplusplus
 }

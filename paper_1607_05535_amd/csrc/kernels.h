@@ -66,36 +66,56 @@ struct Consts {
   double tau;
 };
 
-// Launch shape shared by all kernels: 256 threads (4 wavefronts).
-constexpr int kBlock = 256;
+// Workgroups have 1, 2, 4 or 8 wavefronts (tuned per kernel family).
+constexpr int kMaxBlock = 512;
+constexpr int kXcds = 8;   // MI355X: 8 accelerator complex dies, one L2 each
 
-inline int n_blocks(const Consts &c) {
+// Launched workgroups of `wpb` wavefronts (a multiple of kXcds; surplus
+// workgroups store nothing).
+inline int n_blocks(const Consts &c, int wpb) {
   long waves = (c.N + c.cpw - 1) / c.cpw;
-  return (int)((waves + 3) / 4);
+  long wg = (waves + wpb - 1) / wpb;
+  return (int)((wg + kXcds - 1) / kXcds * kXcds);
 }
 
-// Per-substep launchers.  first = the first substep of an RK stage (the
-// small-step state restarts from Phi[t], p* = 0).
+// Launchers.  `wpb` = wavefronts per workgroup (tuned per kernel family).
+// The prognostic state between large steps lives in the *_t buffers; a large
+// step reads them as Phi[t] and leaves its result in the unsuffixed buffers,
+// after which the host swaps the two buffer sets.
+// Acoustic substeps take dtau = dt / div (div = 3 in stage 1, n otherwise);
+// first = first substep of an RK stage (restart from Phi[t], p* = 0);
+// last = final substep of the large step (the physics is applied there).
 template <typename H>
-void launch_hmom(const Fields<H> &f, const Consts &c, double dtau, bool first, hipStream_t s);
+void launch_hmom(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, hipStream_t s);
 template <typename H>
-void launch_vert(const Fields<H> &f, const Consts &c, double dtau, bool first, hipStream_t s);
+void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, bool last,
+                 hipStream_t s);
 template <typename H>
-void launch_graddiv(const Fields<H> &f, const Consts &c, hipStream_t s);
-// Per stage.
+void launch_graddiv(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s);
 template <typename H>
-void launch_slow(const Fields<H> &f, const Consts &c, bool from_t, hipStream_t s);
-// Per large step.
+void launch_slow(const Fields<H> &f, const Consts &c, int wpb, bool from_t, hipStream_t s);
 template <typename H>
-void launch_large(const Fields<H> &f, const Consts &c, hipStream_t s);
-template <typename H>
-void launch_newton(const Fields<H> &f, const Consts &c, hipStream_t s);
-// Diagnostics.
+void launch_large(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s);
 template <typename H>
 void launch_diag_field(const Fields<H> &f, const Consts &c, int field, hipStream_t s);
 template <typename H>
 void launch_mass(const Fields<H> &f, const Consts &c, hipStream_t s, int *nblocks_out);
 template <typename H>
 void launch_to_state(const Fields<H> &f, const Consts &c, const double *blob, hipStream_t s);
+
+// One member of an ensemble as the device sees it.
+template <typename H>
+struct Planet {
+  Fields<H> f[2];   // the two buffer-set orders (see thor_state)
+  Consts c;
+};
+
+enum class BatchOp { Large, Slow, Hmom, Vert, VertLast, Graddiv };
+
+// Every member of an ensemble in one launch per phase.  arg0/arg1: Slow:
+// from_t; Hmom/Vert: div, first.
+template <typename H>
+void launch_batch(const Planet<H> *P, const int2 *tiles, int n_tiles, int wpb, int parity, BatchOp op,
+                  int arg0, int arg1, hipStream_t s);
 
 }  // namespace thor

@@ -31,10 +31,20 @@ struct Lane {
   bool real_col;        // lane belongs to one of the wavefront's cpw columns
 };
 
-__device__ __forceinline__ Lane map_lane(const Consts &c) {
+// Workgroups are dispatched round-robin over the XCDs, each with its own L2.
+// Renumber them so that XCD x works on one contiguous range of the work: the
+// neighbours a column gathers from (ids +-1, +-2^g) then sit in the same L2.
+// The launched count is a multiple of kXcds.
+__device__ __forceinline__ int xcd_block() {
+  const int per = gridDim.x / kXcds;
+  return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+
+// Lane of logical workgroup lb (blockDim.x / 64 wavefronts per workgroup).
+__device__ __forceinline__ Lane map_lane(const Consts &c, int lb) {
   Lane r;
   r.lane = threadIdx.x & 63;
-  int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int wave = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
   int cw = r.lane / c.L;
   r.lev = r.lane - cw * c.L;
   int col = wave * c.cpw + cw;
@@ -100,8 +110,7 @@ __device__ __forceinline__ T lap_at(const T *s, const int nb[6], const H *lc, in
 // horizontal projection (Eq. proj_h).
 // ---------------------------------------------------------------------------
 template <typename H>
-__global__ __launch_bounds__(kBlock) void k_hmom(Fields<H> f, Consts c, double dtau, int first) {
-  const Lane ln = map_lane(c);
+__device__ __forceinline__ void b_hmom(const Fields<H> &f, const Consts &c, const Lane &ln, double dtau, int first) {
   if (!ln.store) return;
   const int L = c.L, lev = ln.lev, col = ln.col;
   const size_t idx = (size_t)col * L + lev;
@@ -144,9 +153,8 @@ __global__ __launch_bounds__(kBlock) void k_hmom(Fields<H> f, Consts c, double d
 // combined), its solution, and the density / rho-theta updates with the new
 // W; pressure from the nonlinear equation of state (Eq. theta_to_p).
 // ---------------------------------------------------------------------------
-template <typename H>
-__global__ __launch_bounds__(kBlock) void k_vert(Fields<H> f, Consts c, double dtau, int first) {
-  const Lane ln = map_lane(c);
+template <typename H, bool LAST>
+__device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, const Lane &ln, double dtau, int first) {
   const int L = c.L, lev = ln.lev, col = ln.col;
   const size_t idx = (size_t)col * L + lev;
   int nb[6];
@@ -220,10 +228,11 @@ __global__ __launch_bounds__(kBlock) void k_vert(Fields<H> f, Consts c, double d
     const bool lo = ln.real_col && lev >= s, hi = ln.real_col && lev + s < L;
     const int sl = lo ? ln.lane - s : ln.lane;
     const int sh = hi ? ln.lane + s : ln.lane;
-    const double a_l = shfl(a, sl), b_l = shfl(b, sl), c_l = shfl(cc, sl), d_l = shfl(d, sl);
-    const double a_h = shfl(a, sh), b_h = shfl(b, sh), c_h = shfl(cc, sh), d_h = shfl(d, sh);
-    const double k1 = lo ? a / b_l : 0.0;
-    const double k2 = hi ? cc / b_h : 0.0;
+    const double rb = 1.0 / b;
+    const double a_l = shfl(a, sl), rb_l = shfl(rb, sl), c_l = shfl(cc, sl), d_l = shfl(d, sl);
+    const double a_h = shfl(a, sh), rb_h = shfl(rb, sh), c_h = shfl(cc, sh), d_h = shfl(d, sh);
+    const double k1 = lo ? a * rb_l : 0.0;
+    const double k2 = hi ? cc * rb_h : 0.0;
     const double na = lo ? -a_l * k1 : 0.0;
     const double nc = hi ? -c_h * k2 : 0.0;
     b = b - (lo ? c_l * k1 : 0.0) - (hi ? a_h * k2 : 0.0);
@@ -236,8 +245,16 @@ __global__ __launch_bounds__(kBlock) void k_vert(Fields<H> f, Consts c, double d
   if (lev == L - 1) Wp = 0.0;
 
   const double rho_new = rho_hat - ap * Wp + am * Wn;
-  const double rth_new = rth_hat - ap * thI_p * Wp + am * thI * Wn;
-  const double p = c.p_ref * pow(c.Rd * rth_new / c.p_ref, c.gamma);
+  double rth_new = rth_hat - ap * thI_p * Wp + am * thI * Wn;
+  double p = c.p_ref * pow(c.Rd * rth_new / c.p_ref, c.gamma);
+  if (LAST && c.forcing == THOR_FORCING_NEWTONIAN) {
+    // physics after the dynamics (Eq. im_eq_t, K_T = 1/tau) at fixed density
+    const double kt = c.dt / c.tau;
+    const double T = p / (rho_new * c.Rd);
+    const double Tn = (T + kt * f.teq[col]) / (1.0 + kt);
+    p = rho_new * c.Rd * Tn;
+    rth_new = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
+  }
   const double D3 = Drho + (rI1 * rI1 * Wp - rI * rI * Wn) / (rC * rC * dz);
   if (ln.store) {
     f.rho[idx] = rho_new;
@@ -250,8 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_vert(Fields<H> f, Consts c, double d
 
 // G = grad D for the next substep's divergence damping.
 template <typename H>
-__global__ __launch_bounds__(kBlock) void k_graddiv(Fields<H> f, Consts c) {
-  const Lane ln = map_lane(c);
+__device__ __forceinline__ void b_graddiv(const Fields<H> &f, const Consts &c, const Lane &ln) {
   if (!ln.store) return;
   const int L = c.L, lev = ln.lev, col = ln.col;
   const size_t idx = (size_t)col * L + lev;
@@ -270,8 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_graddiv(Fields<H> f, Consts c) {
 // and the linearisation coefficients theta_L and gamma p / (rho theta).
 // ---------------------------------------------------------------------------
 template <typename H>
-__global__ __launch_bounds__(kBlock) void k_slow(Fields<H> f, Consts c, int from_t) {
-  const Lane ln = map_lane(c);
+__device__ __forceinline__ void b_slow(const Fields<H> &f, const Consts &c, const Lane &ln, int from_t) {
   const int L = c.L, lev = ln.lev, col = ln.col;
   const size_t idx = (size_t)col * L + lev;
   const int lm = ln.lane > 0 ? ln.lane - 1 : 0;
@@ -296,7 +311,8 @@ __global__ __launch_bounds__(kBlock) void k_slow(Fields<H> f, Consts c, int from
   const H rho0 = (H)rho[idx];
   const H mx0 = Mx[idx], my0 = My[idx], mz0 = Mz[idx];
   const H fx = mx0 + wbar * rx, fy = my0 + wbar * ry, fz = mz0 + wbar * rz;
-  const H vx0 = fx / rho0, vy0 = fy / rho0, vz0 = fz / rho0;
+  const H irho0 = (H)1 / rho0;
+  const H vx0 = fx * irho0, vy0 = fy * irho0, vz0 = fz * irho0;
   // horizontal flux divergence of v_q M
   H Ax, Ay, Az;
   {
@@ -313,12 +329,12 @@ __global__ __launch_bounds__(kBlock) void k_slow(Fields<H> f, Consts c, int from
     if (lev == L - 1) wn1 = 0.0;
     const H wb = (H)(0.5 * (wn + wn1));
     const H *rn = f.rhat + (size_t)nb[j] * 3;
-    const H rn_ = (H)rho[nj];
     const H mxj = Mx[nj], myj = My[nj], mzj = Mz[nj];
-    const H t = dc[3 * (j + 1)] * mxj + dc[3 * (j + 1) + 1] * myj + dc[3 * (j + 1) + 2] * mzj;
-    Ax += (mxj + wb * rn[0]) / rn_ * t;
-    Ay += (myj + wb * rn[1]) / rn_ * t;
-    Az += (mzj + wb * rn[2]) / rn_ * t;
+    const H t = (dc[3 * (j + 1)] * mxj + dc[3 * (j + 1) + 1] * myj + dc[3 * (j + 1) + 2] * mzj) /
+                (H)rho[nj];
+    Ax += (mxj + wb * rn[0]) * t;
+    Ay += (myj + wb * rn[1]) * t;
+    Az += (mzj + wb * rn[2]) * t;
   }
   const H rC = (H)radius_c(c, lev);
   Ax /= rC;
@@ -346,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_slow(Fields<H> f, Consts c, int from
   const H acr_m = shfl(acr, lm);
   // linearisation coefficients
   const double rth0 = rth[idx];
-  const double p0 = c.p_ref * pow(c.Rd * rth0 / c.p_ref, c.gamma);
+  const double p0 = f.p_t[idx] + (from_t ? 0.0 : (double)f.ps[idx]);
   if (ln.store) {
     f.SMx[idx] = f.FMx[idx] - (ACx - acr * rx);
     f.SMy[idx] = f.FMy[idx] - (ACy - acr * ry);
@@ -364,34 +380,26 @@ __global__ __launch_bounds__(kBlock) void k_slow(Fields<H> f, Consts c, int from
 // Phi[t].
 // ---------------------------------------------------------------------------
 template <typename H>
-__global__ __launch_bounds__(kBlock) void k_large0(Fields<H> f, Consts c) {
-  const Lane ln = map_lane(c);
+__device__ __forceinline__ void b_large0(const Fields<H> &f, const Consts &c, const Lane &ln) {
   const int L = c.L, lev = ln.lev, col = ln.col;
   const size_t idx = (size_t)col * L + lev;
   const int lm = ln.lane > 0 ? ln.lane - 1 : 0;
-  const double rho = f.rho[idx], rth = f.rth[idx];
-  const double W = lev == 0 ? 0.0 : f.W[idx];
+  const double rho = f.rho_t[idx], rth = f.rth_t[idx];
+  const double W = lev == 0 ? 0.0 : f.W_t[idx];
   const double rho_m = shfl(rho, lm);
   const double p = c.p_ref * pow(c.Rd * rth / c.p_ref, c.gamma);
   if (!ln.store) return;
-  const H mx = f.Mx[idx], my = f.My[idx], mz = f.Mz[idx];
-  f.rho_t[idx] = rho;
-  f.rth_t[idx] = rth;
-  f.W_t[idx] = W;
-  f.Mx_t[idx] = mx;
-  f.My_t[idx] = my;
-  f.Mz_t[idx] = mz;
+  const double irho = 1.0 / rho;
   f.p_t[idx] = p;
-  f.T[idx] = p / (rho * c.Rd);
-  f.vx[idx] = (double)mx / rho;
-  f.vy[idx] = (double)my / rho;
-  f.vz[idx] = (double)mz / rho;
+  f.T[idx] = p * irho / c.Rd;
+  f.vx[idx] = (double)f.Mx_t[idx] * irho;
+  f.vy[idx] = (double)f.My_t[idx] * irho;
+  f.vz[idx] = (double)f.Mz_t[idx] * irho;
   f.wI[idx] = lev == 0 ? 0.0 : W / (0.5 * (rho_m + rho));
 }
 
 template <typename H>
-__global__ __launch_bounds__(kBlock) void k_large1(Fields<H> f, Consts c) {
-  const Lane ln = map_lane(c);
+__device__ __forceinline__ void b_large1(const Fields<H> &f, const Consts &c, const Lane &ln) {
   const int L = c.L, lev = ln.lev, col = ln.col;
   const size_t idx = (size_t)col * L + lev;
   const int lm = ln.lane > 0 ? ln.lane - 1 : 0;
@@ -452,8 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_large1(Fields<H> f, Consts c) {
 }
 
 template <typename H>
-__global__ __launch_bounds__(kBlock) void k_large2(Fields<H> f, Consts c) {
-  const Lane ln = map_lane(c);
+__device__ __forceinline__ void b_large2(const Fields<H> &f, const Consts &c, const Lane &ln) {
   if (!ln.store) return;
   const int L = c.L, lev = ln.lev, col = ln.col;
   const size_t idx = (size_t)col * L + lev;
@@ -482,43 +489,27 @@ __global__ __launch_bounds__(kBlock) void k_large2(Fields<H> f, Consts c) {
   f.GDz[idx] = gz;
 }
 
-// Newtonian relaxation (Eq. im_eq_t, K_T = 1/tau) at fixed density.
-template <typename H>
-__global__ __launch_bounds__(kBlock) void k_newton(Fields<H> f, Consts c) {
-  const Lane ln = map_lane(c);
-  if (!ln.store) return;
-  const size_t idx = (size_t)ln.col * c.L + ln.lev;
-  const double rho = f.rho[idx];
-  const double p = c.p_ref * pow(c.Rd * f.rth[idx] / c.p_ref, c.gamma);
-  const double T = p / (rho * c.Rd);
-  const double kt = c.dt / c.tau;
-  const double Tn = (T + kt * f.teq[ln.col]) / (1.0 + kt);
-  const double pn = rho * c.Rd * Tn;
-  f.rth[idx] = c.p_ref / c.Rd * pow(pn / c.p_ref, 1.0 / c.gamma);
-}
-
 // Diagnostic field into f.diag (FP64, canonical layout).
 template <typename H>
-__global__ __launch_bounds__(kBlock) void k_diag(Fields<H> f, Consts c, int field) {
-  const Lane ln = map_lane(c);
+__device__ __forceinline__ void b_diag(const Fields<H> &f, const Consts &c, const Lane &ln, int field) {
   const int L = c.L, lev = ln.lev, col = ln.col;
   const size_t idx = (size_t)col * L + lev;
   const int lp = ln.lane < 63 ? ln.lane + 1 : 63;
-  const double W = lev == 0 ? 0.0 : f.W[idx];
+  const double W = lev == 0 ? 0.0 : f.W_t[idx];
   double W1 = shfl(W, lp);
   if (lev == L - 1) W1 = 0.0;
   if (!ln.store) return;
-  const double rho = f.rho[idx];
+  const double rho = f.rho_t[idx];
   double out = 0.0;
   const H *rh = f.rhat + (size_t)col * 3;
   const double x = rh[0], y = rh[1], z = rh[2];
   if (field == THOR_F_T || field == THOR_F_P) {
-    const double p = c.p_ref * pow(c.Rd * f.rth[idx] / c.p_ref, c.gamma);
+    const double p = c.p_ref * pow(c.Rd * f.rth_t[idx] / c.p_ref, c.gamma);
     out = field == THOR_F_P ? p : p / (rho * c.Rd);
   } else if (field == THOR_F_U || field == THOR_F_V) {
     const double lam = (sqrt(x * x + y * y) < 1e-12) ? 0.0 : atan2(y, x);
     const double phi = asin(fmin(1.0, fmax(-1.0, z)));
-    const double vx = (double)f.Mx[idx] / rho, vy = (double)f.My[idx] / rho, vz = (double)f.Mz[idx] / rho;
+    const double vx = (double)f.Mx_t[idx] / rho, vy = (double)f.My_t[idx] / rho, vz = (double)f.Mz_t[idx] / rho;
     if (field == THOR_F_U) out = -sin(lam) * vx + cos(lam) * vy;
     else out = -sin(phi) * cos(lam) * vx - sin(phi) * sin(lam) * vy + cos(phi) * vz;
   } else if (field == THOR_F_W) {
@@ -526,13 +517,13 @@ __global__ __launch_bounds__(kBlock) void k_diag(Fields<H> f, Consts c, int fiel
   } else if (field == THOR_F_RHO) {
     out = rho;
   } else if (field == THOR_F_RHOTHETA) {
-    out = f.rth[idx];
+    out = f.rth_t[idx];
   } else if (field == THOR_F_MX) {
-    out = (double)f.Mx[idx];
+    out = (double)f.Mx_t[idx];
   } else if (field == THOR_F_MY) {
-    out = (double)f.My[idx];
+    out = (double)f.My_t[idx];
   } else if (field == THOR_F_MZ) {
-    out = (double)f.Mz[idx];
+    out = (double)f.Mz_t[idx];
   } else {
     out = W;
   }
@@ -541,18 +532,18 @@ __global__ __launch_bounds__(kBlock) void k_diag(Fields<H> f, Consts c, int fiel
 
 // Mass partial sums and a non-finite count per block (fixed reduction order).
 template <typename H>
-__global__ __launch_bounds__(kBlock) void k_mass(Fields<H> f, Consts c) {
-  __shared__ double sm[kBlock / 64][2];
-  const Lane ln = map_lane(c);
+__global__ __launch_bounds__(256) void k_mass(Fields<H> f, Consts c) {
+  __shared__ double sm[4][2];
+  const Lane ln = map_lane(c, xcd_block());
   const int L = c.L, lev = ln.lev, col = ln.col;
   const size_t idx = (size_t)col * L + lev;
   double m = 0.0, bad = 0.0;
   if (ln.store) {
     const double rC = radius_c(c, lev);
-    const double rho = f.rho[idx];
+    const double rho = f.rho_t[idx];
     m = rho * f.area[col] * rC * rC * c.dz;
-    const double chk = rho + f.rth[idx] + f.W[idx] + (double)f.Mx[idx] + (double)f.My[idx] +
-                       (double)f.Mz[idx];
+    const double chk = rho + f.rth_t[idx] + f.W_t[idx] + (double)f.Mx_t[idx] + (double)f.My_t[idx] +
+                       (double)f.Mz_t[idx];
     bad = isfinite(chk) ? 0.0 : 1.0;
   }
   for (int o = 32; o > 0; o >>= 1) {
@@ -567,7 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_mass(Fields<H> f, Consts c) {
   __syncthreads();
   if (threadIdx.x == 0) {
     double a = 0.0, b2 = 0.0;
-    for (int i = 0; i < kBlock / 64; ++i) {
+    for (int i = 0; i < 4; ++i) {
       a += sm[i][0];
       b2 += sm[i][1];
     }
@@ -578,71 +569,149 @@ __global__ __launch_bounds__(kBlock) void k_mass(Fields<H> f, Consts c) {
 
 // Prognostic fields from a staged FP64 blob (checkpoint import).
 template <typename H>
-__global__ __launch_bounds__(kBlock) void k_import(Fields<H> f, Consts c, const double *blob) {
-  const Lane ln = map_lane(c);
+__device__ __forceinline__ void b_import(const Fields<H> &f, const Consts &c, const Lane &ln, const double *blob) {
   if (!ln.store) return;
   const size_t NL = (size_t)c.N * c.L;
   const size_t idx = (size_t)ln.col * c.L + ln.lev;
-  f.rho[idx] = blob[idx];
-  f.Mx[idx] = (H)blob[NL + idx];
-  f.My[idx] = (H)blob[2 * NL + idx];
-  f.Mz[idx] = (H)blob[3 * NL + idx];
-  f.rth[idx] = blob[4 * NL + idx];
-  f.W[idx] = ln.lev == 0 ? 0.0 : blob[5 * NL + idx];
+  f.rho_t[idx] = blob[idx];
+  f.Mx_t[idx] = (H)blob[NL + idx];
+  f.My_t[idx] = (H)blob[2 * NL + idx];
+  f.Mz_t[idx] = (H)blob[3 * NL + idx];
+  f.rth_t[idx] = blob[4 * NL + idx];
+  f.W_t[idx] = ln.lev == 0 ? 0.0 : blob[5 * NL + idx];
 }
+
+// OCC: minimum wavefronts per SIMD the register allocation must allow
+// (caps VGPRs at 512 / OCC), chosen per kernel so that the gathers keep
+// enough wavefronts in flight without spilling.
+//
+// k_NAME: one planet; kb_NAME: an ensemble, where logical workgroup b runs
+// local workgroup tiles[b].y of planet tiles[b].x (x < 0: padding).  Both call
+// the same body, so a planet computes bit-identical results either way.
+#define THOR_KERNEL(NAME, OCC, PARAMS, ARGS)                                              \
+  template <typename H>                                                                   \
+  __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(OCC)))       \
+  void k_##NAME(Fields<H> f, Consts c PARAMS) {                                           \
+    b_##NAME(f, c, map_lane(c, xcd_block()) ARGS);                                        \
+  }                                                                                       \
+  template <typename H>                                                                   \
+  __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(OCC)))       \
+  void kb_##NAME(const Planet<H> *P, const int2 *tiles, int parity PARAMS) {             \
+    const int2 t = tiles[xcd_block()];                                                    \
+    if (t.x < 0) return;                                                                  \
+    const Fields<H> &f = P[t.x].f[parity];                                                \
+    const Consts &c = P[t.x].c;                                                           \
+    b_##NAME(f, c, map_lane(c, t.y) ARGS);                                                \
+  }
+#define COMMA ,
+THOR_KERNEL(hmom, 6, COMMA int div COMMA int first, COMMA c.dt / div COMMA first)
+THOR_KERNEL(graddiv, 8, , )
+THOR_KERNEL(slow, 3, COMMA int from_t, COMMA from_t)
+THOR_KERNEL(large0, 8, , )
+THOR_KERNEL(large1, 4, , )
+THOR_KERNEL(large2, 5, , )
+THOR_KERNEL(diag, 8, COMMA int field, COMMA field)
+THOR_KERNEL(import, 8, COMMA const double *blob, COMMA blob)
+template <typename H, bool LAST>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void k_vert(Fields<H> f, Consts c, int div, int first) {
+  b_vert<H, LAST>(f, c, map_lane(c, xcd_block()), c.dt / div, first);
+}
+template <typename H, bool LAST>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void kb_vert(const Planet<H> *P, const int2 *tiles, int parity, int div, int first) {
+  const int2 t = tiles[xcd_block()];
+  if (t.x < 0) return;
+  const Fields<H> &f = P[t.x].f[parity];
+  const Consts &c = P[t.x].c;
+  b_vert<H, LAST>(f, c, map_lane(c, t.y), c.dt / div, first);
+}
+#undef COMMA
+#undef THOR_KERNEL
 
 }  // namespace
 
 template <typename H>
-void launch_hmom(const Fields<H> &f, const Consts &c, double dtau, bool first, hipStream_t s) {
-  hipLaunchKernelGGL(k_hmom<H>, dim3(n_blocks(c)), dim3(kBlock), 0, s, f, c, dtau, (int)first);
+void launch_hmom(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, hipStream_t s) {
+  hipLaunchKernelGGL(k_hmom<H>, dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c, div, (int)first);
 }
 template <typename H>
-void launch_vert(const Fields<H> &f, const Consts &c, double dtau, bool first, hipStream_t s) {
-  hipLaunchKernelGGL(k_vert<H>, dim3(n_blocks(c)), dim3(kBlock), 0, s, f, c, dtau, (int)first);
+void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, bool last,
+                 hipStream_t s) {
+  if (last)
+    hipLaunchKernelGGL((k_vert<H, true>), dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c, div, (int)first);
+  else
+    hipLaunchKernelGGL((k_vert<H, false>), dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c, div, (int)first);
 }
 template <typename H>
-void launch_graddiv(const Fields<H> &f, const Consts &c, hipStream_t s) {
-  hipLaunchKernelGGL(k_graddiv<H>, dim3(n_blocks(c)), dim3(kBlock), 0, s, f, c);
+void launch_graddiv(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s) {
+  hipLaunchKernelGGL(k_graddiv<H>, dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c);
 }
 template <typename H>
-void launch_slow(const Fields<H> &f, const Consts &c, bool from_t, hipStream_t s) {
-  hipLaunchKernelGGL(k_slow<H>, dim3(n_blocks(c)), dim3(kBlock), 0, s, f, c, (int)from_t);
+void launch_slow(const Fields<H> &f, const Consts &c, int wpb, bool from_t, hipStream_t s) {
+  hipLaunchKernelGGL(k_slow<H>, dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c, (int)from_t);
 }
 template <typename H>
-void launch_large(const Fields<H> &f, const Consts &c, hipStream_t s) {
-  hipLaunchKernelGGL(k_large0<H>, dim3(n_blocks(c)), dim3(kBlock), 0, s, f, c);
-  hipLaunchKernelGGL(k_large1<H>, dim3(n_blocks(c)), dim3(kBlock), 0, s, f, c);
-  hipLaunchKernelGGL(k_large2<H>, dim3(n_blocks(c)), dim3(kBlock), 0, s, f, c);
-}
-template <typename H>
-void launch_newton(const Fields<H> &f, const Consts &c, hipStream_t s) {
-  hipLaunchKernelGGL(k_newton<H>, dim3(n_blocks(c)), dim3(kBlock), 0, s, f, c);
+void launch_large(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s) {
+  hipLaunchKernelGGL(k_large0<H>, dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c);
+  hipLaunchKernelGGL(k_large1<H>, dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c);
+  hipLaunchKernelGGL(k_large2<H>, dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c);
 }
 template <typename H>
 void launch_diag_field(const Fields<H> &f, const Consts &c, int field, hipStream_t s) {
-  hipLaunchKernelGGL(k_diag<H>, dim3(n_blocks(c)), dim3(kBlock), 0, s, f, c, field);
+  hipLaunchKernelGGL(k_diag<H>, dim3(n_blocks(c, 4)), dim3(256), 0, s, f, c, field);
 }
 template <typename H>
 void launch_mass(const Fields<H> &f, const Consts &c, hipStream_t s, int *nblocks_out) {
-  *nblocks_out = n_blocks(c);
-  hipLaunchKernelGGL(k_mass<H>, dim3(n_blocks(c)), dim3(kBlock), 0, s, f, c);
+  *nblocks_out = n_blocks(c, 4);
+  hipLaunchKernelGGL(k_mass<H>, dim3(n_blocks(c, 4)), dim3(256), 0, s, f, c);
 }
 template <typename H>
 void launch_to_state(const Fields<H> &f, const Consts &c, const double *blob, hipStream_t s) {
-  hipLaunchKernelGGL(k_import<H>, dim3(n_blocks(c)), dim3(kBlock), 0, s, f, c, blob);
+  hipLaunchKernelGGL(k_import<H>, dim3(n_blocks(c, 4)), dim3(256), 0, s, f, c, blob);
 }
 
-#define THOR_INSTANTIATE(H)                                                                     \
-  template void launch_hmom<H>(const Fields<H> &, const Consts &, double, bool, hipStream_t);   \
-  template void launch_vert<H>(const Fields<H> &, const Consts &, double, bool, hipStream_t);   \
-  template void launch_graddiv<H>(const Fields<H> &, const Consts &, hipStream_t);              \
-  template void launch_slow<H>(const Fields<H> &, const Consts &, bool, hipStream_t);           \
-  template void launch_large<H>(const Fields<H> &, const Consts &, hipStream_t);                \
-  template void launch_newton<H>(const Fields<H> &, const Consts &, hipStream_t);               \
-  template void launch_diag_field<H>(const Fields<H> &, const Consts &, int, hipStream_t);      \
-  template void launch_mass<H>(const Fields<H> &, const Consts &, hipStream_t, int *);          \
-  template void launch_to_state<H>(const Fields<H> &, const Consts &, const double *, hipStream_t);
+// Ensemble launchers: `tiles` holds n_tiles (multiple of kXcds) entries for
+// workgroups of `wpb` wavefronts.
+template <typename H>
+void launch_batch(const Planet<H> *P, const int2 *tiles, int n_tiles, int wpb, int parity, BatchOp op,
+                  int arg0, int arg1, hipStream_t s) {
+  const dim3 g(n_tiles), b(64 * wpb);
+  switch (op) {
+    case BatchOp::Large:
+      hipLaunchKernelGGL(kb_large0<H>, g, b, 0, s, P, tiles, parity);
+      hipLaunchKernelGGL(kb_large1<H>, g, b, 0, s, P, tiles, parity);
+      hipLaunchKernelGGL(kb_large2<H>, g, b, 0, s, P, tiles, parity);
+      break;
+    case BatchOp::Slow:
+      hipLaunchKernelGGL(kb_slow<H>, g, b, 0, s, P, tiles, parity, arg0);
+      break;
+    case BatchOp::Hmom:
+      hipLaunchKernelGGL(kb_hmom<H>, g, b, 0, s, P, tiles, parity, arg0, arg1);
+      break;
+    case BatchOp::Vert:
+      hipLaunchKernelGGL((kb_vert<H, false>), g, b, 0, s, P, tiles, parity, arg0, arg1);
+      break;
+    case BatchOp::VertLast:
+      hipLaunchKernelGGL((kb_vert<H, true>), g, b, 0, s, P, tiles, parity, arg0, arg1);
+      break;
+    case BatchOp::Graddiv:
+      hipLaunchKernelGGL(kb_graddiv<H>, g, b, 0, s, P, tiles, parity);
+      break;
+  }
+}
+
+#define THOR_INSTANTIATE(H)                                                                          \
+  template void launch_hmom<H>(const Fields<H> &, const Consts &, int, int, bool, hipStream_t);      \
+  template void launch_vert<H>(const Fields<H> &, const Consts &, int, int, bool, bool, hipStream_t); \
+  template void launch_graddiv<H>(const Fields<H> &, const Consts &, int, hipStream_t);              \
+  template void launch_slow<H>(const Fields<H> &, const Consts &, int, bool, hipStream_t);           \
+  template void launch_large<H>(const Fields<H> &, const Consts &, int, hipStream_t);                \
+  template void launch_diag_field<H>(const Fields<H> &, const Consts &, int, hipStream_t);           \
+  template void launch_mass<H>(const Fields<H> &, const Consts &, hipStream_t, int *);               \
+  template void launch_to_state<H>(const Fields<H> &, const Consts &, const double *, hipStream_t);  \
+  template void launch_batch<H>(const Planet<H> *, const int2 *, int, int, int, BatchOp, int, int,  \
+                                hipStream_t);
 
 THOR_INSTANTIATE(double)
 THOR_INSTANTIATE(float)

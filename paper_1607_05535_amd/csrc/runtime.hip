@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <new>
@@ -104,6 +105,18 @@ void carve(Carver &cv, Fields<H> &f, size_t N, size_t L) {
   f.partial = cv.take<double>(2 * ((N + 3) / 4 + 16));
 }
 
+template <typename H>
+Fields<H> swapped(const Fields<H> &a) {
+  Fields<H> b = a;
+  std::swap(b.rho, b.rho_t);
+  std::swap(b.rth, b.rth_t);
+  std::swap(b.W, b.W_t);
+  std::swap(b.Mx, b.Mx_t);
+  std::swap(b.My, b.My_t);
+  std::swap(b.Mz, b.Mz_t);
+  return b;
+}
+
 bool hip_ok(hipError_t e, const char *what) {
   if (e == hipSuccess) return true;
   set_error(std::string(what) + ": " + hipGetErrorString(e));
@@ -120,20 +133,30 @@ struct TimedLaunch {
   hipEvent_t start, stop;
 };
 
+// Kernel families with a tuned workgroup size (wavefronts per workgroup).
+enum { FAM_LARGE = 0, FAM_SLOW, FAM_HMOM, FAM_VERT, FAM_GRADDIV, FAM_COUNT };
+static const char *kFamily[FAM_COUNT] = {"large", "slow", "hmom", "vert", "graddiv"};
+
 struct thor_state {
   int precision = THOR_FP64;
   Consts c{};
-  Fields<double> f64{};
-  Fields<float> f32{};
+  // f[0] and f[1] are the same buffers with the state set and the Phi[t] set
+  // exchanged; between large steps the state is in the *_t buffers of
+  // f[parity], and every large step flips the parity.
+  Fields<double> f64[2]{};
+  Fields<float> f32[2]{};
+  int parity = 0;
+  int wpb[FAM_COUNT] = {4, 4, 4, 4, 4};
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
-  std::map<int, hipGraphExec_t> graphs;   // one large step per n_acoustic
+  std::map<int, hipGraphExec_t> graphs;   // key: n_acoustic * 2 + parity
   bool timing = false;
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> event_pool;
   size_t next_event = 0;
   int64_t n_col = 0;
   int n_lev = 0;
+  bool in_batch = false;   // members of an ensemble are stepped by thor_batch_step
 };
 
 namespace {
@@ -192,10 +215,12 @@ size_t bytes_for(int precision, size_t N, size_t L) {
 
 template <typename H>
 int upload(thor_state *s, const Grid &G, const thor_planet *pl, const thor_vertical *v,
-           const thor_forcing *fo, const thor_init *in, char *base, Fields<H> &f) {
+           const thor_forcing *fo, const thor_init *in, char *base, Fields<H> *fp) {
   Carver cv{base};
   const size_t N = G.n, L = v->n_lev, NL = N * L;
-  carve(cv, f, N, L);
+  carve(cv, fp[0], N, L);
+  fp[1] = swapped(fp[0]);
+  const Fields<H> &f = fp[0];
   const Consts &c = s->c;
   // geometry
   std::vector<H> dc(G.div_coef.begin(), G.div_coef.end());
@@ -236,12 +261,12 @@ int upload(thor_state *s, const Grid &G, const thor_planet *pl, const thor_verti
             hip_ok(hipMemcpyAsync((void *)f.rhat, rh.data(), rh.size() * sizeof(H), hipMemcpyHostToDevice, st), "copy rhat") &&
             hip_ok(hipMemcpyAsync((void *)f.area, G.area.data(), N * sizeof(double), hipMemcpyHostToDevice, st), "copy area") &&
             hip_ok(hipMemcpyAsync((void *)f.teq, teq.data(), N * sizeof(double), hipMemcpyHostToDevice, st), "copy teq") &&
-            hip_ok(hipMemcpyAsync(f.rho, rho.data(), NL * sizeof(double), hipMemcpyHostToDevice, st), "copy rho") &&
-            hip_ok(hipMemcpyAsync(f.rth, rth.data(), NL * sizeof(double), hipMemcpyHostToDevice, st), "copy rth") &&
-            hip_ok(hipMemcpyAsync(f.W, zero.data(), NL * sizeof(double), hipMemcpyHostToDevice, st), "copy W") &&
-            hip_ok(hipMemcpyAsync(f.Mx, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy Mx") &&
-            hip_ok(hipMemcpyAsync(f.My, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy My") &&
-            hip_ok(hipMemcpyAsync(f.Mz, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy Mz") &&
+            hip_ok(hipMemcpyAsync(f.rho_t, rho.data(), NL * sizeof(double), hipMemcpyHostToDevice, st), "copy rho") &&
+            hip_ok(hipMemcpyAsync(f.rth_t, rth.data(), NL * sizeof(double), hipMemcpyHostToDevice, st), "copy rth") &&
+            hip_ok(hipMemcpyAsync(f.W_t, zero.data(), NL * sizeof(double), hipMemcpyHostToDevice, st), "copy W") &&
+            hip_ok(hipMemcpyAsync(f.Mx_t, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy Mx") &&
+            hip_ok(hipMemcpyAsync(f.My_t, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy My") &&
+            hip_ok(hipMemcpyAsync(f.Mz_t, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy Mz") &&
             hip_ok(hipMemcpyAsync(f.ps, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy ps") &&
             hip_ok(hipStreamSynchronize(st), "init synchronize");
   return ok ? THOR_OK : THOR_EHIP;
@@ -273,29 +298,30 @@ void timed(thor_state *s, hipStream_t st, const char *family, F &&launch) {
 template <typename H>
 void enqueue_large_step(thor_state *s, const Fields<H> &f, int n, hipStream_t st) {
   const Consts &c = s->c;
-  timed(s, st, "large", [&] { launch_large(f, c, st); });
-  const double dt = c.dt;
+  const int *it = s->wpb;
+  timed(s, st, "large", [&] { launch_large(f, c, it[FAM_LARGE], st); });
   const int ns[3] = {1, n / 2, n};
-  const double dtau[3] = {dt / 3.0, dt / n, dt / n};
+  const int div[3] = {3, n, n};   // dtau = dt / div
   for (int stage = 0; stage < 3; ++stage) {
-    timed(s, st, "slow", [&] { launch_slow(f, c, stage == 0, st); });
+    timed(s, st, "slow", [&] { launch_slow(f, c, it[FAM_SLOW], stage == 0, st); });
     for (int i = 0; i < ns[stage]; ++i) {
-      const bool first = i == 0;
-      timed(s, st, "hmom", [&] { launch_hmom(f, c, dtau[stage], first, st); });
-      timed(s, st, "vert", [&] { launch_vert(f, c, dtau[stage], first, st); });
-      if (c.div_damp && i + 1 < ns[stage]) timed(s, st, "graddiv", [&] { launch_graddiv(f, c, st); });
+      const bool first = i == 0, last = stage == 2 && i + 1 == ns[stage];
+      timed(s, st, "hmom", [&] { launch_hmom(f, c, it[FAM_HMOM], div[stage], first, st); });
+      timed(s, st, "vert", [&] { launch_vert(f, c, it[FAM_VERT], div[stage], first, last, st); });
+      if (c.div_damp && i + 1 < ns[stage])
+        timed(s, st, "graddiv", [&] { launch_graddiv(f, c, it[FAM_GRADDIV], st); });
     }
   }
-  if (c.forcing == THOR_FORCING_NEWTONIAN) timed(s, st, "newton", [&] { launch_newton(f, c, st); });
 }
 
-void enqueue(thor_state *s, int n, hipStream_t st) {
-  if (s->precision == THOR_MIXED) enqueue_large_step(s, s->f32, n, st);
-  else enqueue_large_step(s, s->f64, n, st);
+void enqueue(thor_state *s, int n, int parity, hipStream_t st) {
+  if (s->precision == THOR_MIXED) enqueue_large_step(s, s->f32[parity], n, st);
+  else enqueue_large_step(s, s->f64[parity], n, st);
 }
 
-int graph_for(thor_state *s, int n, hipGraphExec_t *out) {
-  auto it = s->graphs.find(n);
+int graph_for(thor_state *s, int n, int parity, hipGraphExec_t *out) {
+  const int key = 2 * n + parity;
+  auto it = s->graphs.find(key);
   if (it != s->graphs.end()) {
     *out = it->second;
     return THOR_OK;
@@ -303,16 +329,37 @@ int graph_for(thor_state *s, int n, hipGraphExec_t *out) {
   hipGraph_t g = nullptr;
   hipGraphExec_t ex = nullptr;
   if (!hip_ok(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed), "graph capture")) return THOR_EHIP;
-  enqueue(s, n, s->cap_stream);
+  enqueue(s, n, parity, s->cap_stream);
   if (!hip_ok(hipStreamEndCapture(s->cap_stream, &g), "graph end capture")) return THOR_EHIP;
   if (!hip_ok(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate")) {
     (void)hipGraphDestroy(g);
     return THOR_EHIP;
   }
   (void)hipGraphDestroy(g);
-  s->graphs[n] = ex;
+  s->graphs[key] = ex;
   *out = ex;
   return THOR_OK;
+}
+
+void drop_graphs(thor_state *s) {
+  for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+  s->graphs.clear();
+}
+
+// Mean duration [ms] of one kernel family over the launches recorded while
+// timing was on.
+double family_mean(thor_state *s, const char *name, int *count) {
+  double sum = 0.0;
+  int n = 0;
+  for (auto &t : s->timed)
+    if (t.family == name) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, t.start, t.stop) != hipSuccess) continue;
+      sum += ms;
+      ++n;
+    }
+  if (count) *count = n;
+  return n ? sum / n : 0.0;
 }
 
 template <typename H>
@@ -473,24 +520,78 @@ int thor_step(thor_state *s, int n_large, int n_acoustic) {
   if (!s) { set_error("thor_step: NULL state"); return THOR_EINVAL; }
   if (n_large < 0) { set_error("thor_step: n_large must be >= 0"); return THOR_EINVAL; }
   if (n_acoustic < 2 || (n_acoustic & 1)) { set_error("thor_step: n_acoustic must be even and >= 2"); return THOR_EINVAL; }
+  if (s->in_batch) { set_error("thor_step: this state is an ensemble member; use thor_batch_step"); return THOR_EINVAL; }
   if (n_large == 0) return THOR_OK;
   if (s->timing) {
-    for (int i = 0; i < n_large; ++i) enqueue(s, n_acoustic, s->stream);
+    for (int i = 0; i < n_large; ++i) {
+      enqueue(s, n_acoustic, s->parity, s->stream);
+      s->parity ^= 1;
+    }
     return hip_ok(hipGetLastError(), "kernel launch") ? THOR_OK : THOR_EHIP;
   }
-  hipGraphExec_t ex;
-  int rc = graph_for(s, n_acoustic, &ex);
-  if (rc != THOR_OK) return rc;
-  for (int i = 0; i < n_large; ++i)
+  for (int i = 0; i < n_large; ++i) {
+    hipGraphExec_t ex;
+    int rc = graph_for(s, n_acoustic, s->parity, &ex);
+    if (rc != THOR_OK) return rc;
     if (!hip_ok(hipGraphLaunch(ex, s->stream), "graph launch")) return THOR_EHIP;
+    s->parity ^= 1;
+  }
+  return THOR_OK;
+}
+
+int thor_autotune(thor_state *s, int n_acoustic, int *iters_out) {
+  clear_error();
+  if (!s) { set_error("thor_autotune: NULL state"); return THOR_EINVAL; }
+  if (n_acoustic < 2 || (n_acoustic & 1)) { set_error("thor_autotune: n_acoustic must be even and >= 2"); return THOR_EINVAL; }
+  // Tune on real large steps (the kernels see the caches as in production),
+  // one family at a time, then restore the state from a checkpoint.
+  static const int cand[] = {1, 2, 4, 8};
+  std::vector<double> blob(thor_state_blob_bytes(s) / sizeof(double));
+  int rc = thor_diag(s, THOR_DIAG_STATE_EXPORT, 0, blob.data(), blob.size() * sizeof(double));
+  if (rc != THOR_OK && rc != THOR_ENONFINITE) return rc;
+  const int parity0 = s->parity;
+  const bool timing0 = s->timing;
+  for (int fam = 0; fam < FAM_COUNT; ++fam) {
+    double best = 1e30;
+    int best_it = s->wpb[fam];
+    for (int it : cand) {
+      s->wpb[fam] = it;
+      s->timing = true;
+      s->timed.clear();
+      s->next_event = 0;
+      enqueue(s, n_acoustic, s->parity, s->stream);
+      s->parity ^= 1;
+      s->timed.clear();   // first step warms up; time the second
+      s->next_event = 0;
+      enqueue(s, n_acoustic, s->parity, s->stream);
+      s->parity ^= 1;
+      if (!hip_ok(hipStreamSynchronize(s->stream), "autotune synchronize")) return THOR_EHIP;
+      int cnt = 0;
+      double ms = family_mean(s, kFamily[fam], &cnt);
+      if (cnt > 0 && ms < best) {
+        best = ms;
+        best_it = it;
+      }
+    }
+    s->wpb[fam] = best_it;
+  }
+  s->timing = timing0;
+  s->timed.clear();
+  s->next_event = 0;
+  drop_graphs(s);
+  s->parity = parity0;
+  rc = thor_state_import(s, blob.data(), blob.size() * sizeof(double));
+  if (rc != THOR_OK) return rc;
+  if (iters_out)
+    for (int k = 0; k < FAM_COUNT; ++k) iters_out[k] = s->wpb[k];
   return THOR_OK;
 }
 
 int thor_diag(thor_state *s, int kind, int field, void *host_out, size_t out_bytes) {
   clear_error();
   if (!s || !host_out) { set_error("thor_diag: NULL argument"); return THOR_EINVAL; }
-  return s->precision == THOR_MIXED ? diag_impl(s, s->f32, kind, field, host_out, out_bytes)
-                                    : diag_impl(s, s->f64, kind, field, host_out, out_bytes);
+  return s->precision == THOR_MIXED ? diag_impl(s, s->f32[s->parity], kind, field, host_out, out_bytes)
+                                    : diag_impl(s, s->f64[s->parity], kind, field, host_out, out_bytes);
 }
 
 size_t thor_state_blob_bytes(const thor_state *s) {
@@ -507,11 +608,11 @@ int thor_state_import(thor_state *s, const void *blob, size_t bytes) {
     return THOR_EINVAL;
   }
   const size_t NL = (size_t)s->c.N * s->c.L;
-  double *stage = s->precision == THOR_MIXED ? s->f32.diag : s->f64.diag;
+  double *stage = s->precision == THOR_MIXED ? s->f32[0].diag : s->f64[0].diag;
   if (!hip_ok(hipMemcpyAsync(stage, b + 4, 6 * NL * sizeof(double), hipMemcpyHostToDevice, s->stream), "copy blob"))
     return THOR_EHIP;
-  if (s->precision == THOR_MIXED) launch_to_state(s->f32, s->c, stage, s->stream);
-  else launch_to_state(s->f64, s->c, stage, s->stream);
+  if (s->precision == THOR_MIXED) launch_to_state(s->f32[s->parity], s->c, stage, s->stream);
+  else launch_to_state(s->f64[s->parity], s->c, stage, s->stream);
   return hip_ok(hipStreamSynchronize(s->stream), "import synchronize") ? THOR_OK : THOR_EHIP;
 }
 
@@ -528,31 +629,308 @@ int thor_set_timing(thor_state *s, int on) {
 int thor_kernel_time(thor_state *s, const char *name, double *mean_ms, int *count) {
   clear_error();
   if (!s || !name || !mean_ms || !count) { set_error("thor_kernel_time: NULL argument"); return THOR_EINVAL; }
-  static const char *known[] = {"large", "slow", "hmom", "vert", "graddiv", "newton"};
   bool ok = false;
-  for (auto k : known) ok = ok || std::strcmp(k, name) == 0;
+  for (auto k : kFamily) ok = ok || std::strcmp(k, name) == 0;
   if (!ok) { set_error("thor_kernel_time: unknown kernel family"); return THOR_EINVAL; }
   if (!hip_ok(hipStreamSynchronize(s->stream), "timing synchronize")) return THOR_EHIP;
-  double sum = 0.0;
-  int n = 0;
-  for (auto &t : s->timed)
-    if (t.family == name) {
-      float ms = 0.f;
-      if (!hip_ok(hipEventElapsedTime(&ms, t.start, t.stop), "event elapsed")) return THOR_EHIP;
-      sum += ms;
-      ++n;
-    }
-  *mean_ms = n ? sum / n : 0.0;
-  *count = n;
+  *mean_ms = family_mean(s, name, count);
   return THOR_OK;
 }
 
 void thor_state_free(thor_state *s) {
   if (!s) return;
-  for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+  drop_graphs(s);
   for (auto e : s->event_pool) (void)hipEventDestroy(e);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Ensembles: many planets, each its own grid level, level count and
+// constants, advanced together with one launch per phase (a tile table maps
+// every workgroup to a planet and a local workgroup), the whole large step
+// captured in one HIP graph.
+// ===========================================================================
+struct thor_batch {
+  int n = 0;
+  int precision = THOR_FP64;
+  std::vector<thor_state *> members;
+  std::vector<size_t> member_bytes;
+  void *tables = nullptr;          // device: Planet<H>[n], then FAM_COUNT tile tables
+  size_t tile_cap = 0;             // entries reserved per tile table
+  int n_tiles[FAM_COUNT] = {0, 0, 0, 0, 0};
+  int wpb[FAM_COUNT] = {4, 4, 4, 4, 4};
+  int parity = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::map<int, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+size_t batch_tile_cap(int n, const thor_grid *const *grids, const thor_vertical *v) {
+  size_t cap = kXcds;
+  for (int i = 0; i < n; ++i) {
+    const size_t cpw = 64 / v[i].n_lev;
+    cap += (grids[i]->g.n + cpw - 1) / cpw;   // one-wavefront workgroups at most
+  }
+  return cap;
+}
+
+template <typename H>
+size_t planet_table_bytes(int n) { return align256(sizeof(Planet<H>) * n); }
+
+template <typename H>
+Planet<H> *planet_table(thor_batch *b) { return reinterpret_cast<Planet<H> *>(b->tables); }
+
+int2 *tile_table(thor_batch *b, int fam, size_t planet_bytes) {
+  char *base = reinterpret_cast<char *>(b->tables) + planet_bytes;
+  return reinterpret_cast<int2 *>(base) + (size_t)fam * b->tile_cap;
+}
+
+// (planet, local workgroup) of every logical workgroup, padded with (-1, 0)
+// to a multiple of kXcds; planets are laid out one after the other so each
+// XCD gets a contiguous run of columns.
+int upload_tiles(thor_batch *b, size_t planet_bytes) {
+  for (int fam = 0; fam < FAM_COUNT; ++fam) {
+    std::vector<int2> t;
+    for (int i = 0; i < b->n; ++i) {
+      const Consts &c = b->members[i]->c;
+      const long waves = (c.N + c.cpw - 1) / c.cpw;
+      const long wg = (waves + b->wpb[fam] - 1) / b->wpb[fam];
+      for (long k = 0; k < wg; ++k) t.push_back(make_int2(i, (int)k));
+    }
+    while (t.size() % kXcds) t.push_back(make_int2(-1, 0));
+    if (t.size() > b->tile_cap) { set_error("thor_batch: tile table overflow"); return THOR_EINVAL; }
+    b->n_tiles[fam] = (int)t.size();
+    if (!hip_ok(hipMemcpyAsync(tile_table(b, fam, planet_bytes), t.data(), t.size() * sizeof(int2),
+                               hipMemcpyHostToDevice, b->stream), "copy tiles"))
+      return THOR_EHIP;
+  }
+  return hip_ok(hipStreamSynchronize(b->stream), "tiles synchronize") ? THOR_OK : THOR_EHIP;
+}
+
+template <typename H>
+void enqueue_batch_step(thor_batch *b, int n, int parity, hipStream_t st) {
+  const size_t pb = planet_table_bytes<H>(b->n);
+  const Planet<H> *P = planet_table<H>(b);
+  auto L = [&](int fam, BatchOp op, int a0, int a1) {
+    launch_batch<H>(P, tile_table(b, fam, pb), b->n_tiles[fam], b->wpb[fam], parity, op, a0, a1, st);
+  };
+  L(FAM_LARGE, BatchOp::Large, 0, 0);
+  const int ns[3] = {1, n / 2, n};
+  const int div[3] = {3, n, n};
+  for (int stage = 0; stage < 3; ++stage) {
+    L(FAM_SLOW, BatchOp::Slow, stage == 0, 0);
+    for (int i = 0; i < ns[stage]; ++i) {
+      const bool first = i == 0, last = stage == 2 && i + 1 == ns[stage];
+      L(FAM_HMOM, BatchOp::Hmom, div[stage], first);
+      L(FAM_VERT, last ? BatchOp::VertLast : BatchOp::Vert, div[stage], first);
+      if (i + 1 < ns[stage]) L(FAM_GRADDIV, BatchOp::Graddiv, 0, 0);
+    }
+  }
+}
+
+void batch_enqueue(thor_batch *b, int n, int parity, hipStream_t st) {
+  if (b->precision == THOR_MIXED) enqueue_batch_step<float>(b, n, parity, st);
+  else enqueue_batch_step<double>(b, n, parity, st);
+}
+
+void batch_flip(thor_batch *b) {
+  b->parity ^= 1;
+  for (auto m : b->members) m->parity = b->parity;
+}
+
+void batch_drop_graphs(thor_batch *b) {
+  for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int thor_batch_bytes(int n, const thor_grid *const *grids, const thor_vertical *v,
+                     const thor_numerics *num, size_t *bytes) {
+  clear_error();
+  if (n < 1 || !grids || !v || !num || !bytes) { set_error("thor_batch_bytes: bad argument"); return THOR_EINVAL; }
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!grids[i]) { set_error("thor_batch_bytes: NULL grid"); return THOR_EINVAL; }
+    if (num[i].precision != num[0].precision) { set_error("thor_batch_bytes: mixed precisions"); return THOR_EINVAL; }
+    size_t b = 0;
+    int rc = thor_state_bytes(grids[i], &v[i], &num[i], &b);
+    if (rc != THOR_OK) return rc;
+    total += align256(b);
+  }
+  const size_t pb = num[0].precision == THOR_MIXED ? planet_table_bytes<float>(n) : planet_table_bytes<double>(n);
+  total += pb + align256(FAM_COUNT * batch_tile_cap(n, grids, v) * sizeof(int2));
+  *bytes = total;
+  return THOR_OK;
+}
+
+int thor_batch_init(int n, const thor_grid *const *grids, const thor_planet *pl, const thor_vertical *v,
+                    const thor_numerics *num, const thor_forcing *fo, const thor_init *in,
+                    void *dev_buf, size_t dev_bytes, void *hip_stream, thor_batch **out) {
+  clear_error();
+  if (!out || !dev_buf || !pl || !fo || !in) { set_error("thor_batch_init: NULL argument"); return THOR_EINVAL; }
+  *out = nullptr;
+  size_t need = 0;
+  int rc = thor_batch_bytes(n, grids, v, num, &need);
+  if (rc != THOR_OK) return rc;
+  if (dev_bytes < need) { set_error("thor_batch_init: dev_bytes smaller than thor_batch_bytes"); return THOR_ENOMEM; }
+  for (int i = 0; i < n; ++i)
+    if (!validate(&pl[i], &v[i], &num[i], &fo[i], &in[i])) return THOR_EINVAL;
+  thor_batch *b = new (std::nothrow) thor_batch;
+  if (!b) { set_error("thor_batch_init: out of host memory"); return THOR_ENOMEM; }
+  b->n = n;
+  b->precision = num[0].precision;
+  b->stream = (hipStream_t)hip_stream;
+  char *base = (char *)dev_buf;
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    size_t bytes = 0;
+    thor_state_bytes(grids[i], &v[i], &num[i], &bytes);
+    thor_state *m = nullptr;
+    rc = thor_state_init(grids[i], &pl[i], &v[i], &num[i], &fo[i], &in[i], base + off, bytes, hip_stream, &m);
+    if (rc != THOR_OK) {
+      thor_batch_free(b);
+      return rc;
+    }
+    m->in_batch = true;
+    b->members.push_back(m);
+    off += align256(bytes);
+  }
+  b->tables = base + off;
+  b->tile_cap = batch_tile_cap(n, grids, v);
+  size_t pb;
+  bool ok;
+  if (b->precision == THOR_MIXED) {
+    std::vector<Planet<float>> P(n);
+    for (int i = 0; i < n; ++i) {
+      P[i].f[0] = b->members[i]->f32[0];
+      P[i].f[1] = b->members[i]->f32[1];
+      P[i].c = b->members[i]->c;
+    }
+    pb = planet_table_bytes<float>(n);
+    ok = hip_ok(hipMemcpyAsync(b->tables, P.data(), sizeof(Planet<float>) * n, hipMemcpyHostToDevice, b->stream), "copy planets");
+  } else {
+    std::vector<Planet<double>> P(n);
+    for (int i = 0; i < n; ++i) {
+      P[i].f[0] = b->members[i]->f64[0];
+      P[i].f[1] = b->members[i]->f64[1];
+      P[i].c = b->members[i]->c;
+    }
+    pb = planet_table_bytes<double>(n);
+    ok = hip_ok(hipMemcpyAsync(b->tables, P.data(), sizeof(Planet<double>) * n, hipMemcpyHostToDevice, b->stream), "copy planets");
+  }
+  if (!ok || !hip_ok(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "capture stream")) {
+    thor_batch_free(b);
+    return THOR_EHIP;
+  }
+  rc = upload_tiles(b, pb);
+  if (rc != THOR_OK) {
+    thor_batch_free(b);
+    return rc;
+  }
+  *out = b;
+  return THOR_OK;
+}
+
+int thor_batch_step(thor_batch *b, int n_large, int n_acoustic) {
+  clear_error();
+  if (!b) { set_error("thor_batch_step: NULL batch"); return THOR_EINVAL; }
+  if (n_large < 0) { set_error("thor_batch_step: n_large must be >= 0"); return THOR_EINVAL; }
+  if (n_acoustic < 2 || (n_acoustic & 1)) { set_error("thor_batch_step: n_acoustic must be even and >= 2"); return THOR_EINVAL; }
+  for (int i = 0; i < n_large; ++i) {
+    const int key = 2 * n_acoustic + b->parity;
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+      hipGraph_t g = nullptr;
+      hipGraphExec_t ex = nullptr;
+      if (!hip_ok(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed), "graph capture")) return THOR_EHIP;
+      batch_enqueue(b, n_acoustic, b->parity, b->cap_stream);
+      if (!hip_ok(hipStreamEndCapture(b->cap_stream, &g), "graph end capture")) return THOR_EHIP;
+      if (!hip_ok(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate")) {
+        (void)hipGraphDestroy(g);
+        return THOR_EHIP;
+      }
+      (void)hipGraphDestroy(g);
+      it = b->graphs.emplace(key, ex).first;
+    }
+    if (!hip_ok(hipGraphLaunch(it->second, b->stream), "graph launch")) return THOR_EHIP;
+    batch_flip(b);
+  }
+  return THOR_OK;
+}
+
+int thor_batch_member(thor_batch *b, int i, thor_state **out) {
+  clear_error();
+  if (!b || !out || i < 0 || i >= b->n) { set_error("thor_batch_member: bad argument"); return THOR_EINVAL; }
+  *out = b->members[i];
+  return THOR_OK;
+}
+
+int thor_batch_autotune(thor_batch *b, int n_acoustic, int *wpb_out) {
+  clear_error();
+  if (!b) { set_error("thor_batch_autotune: NULL batch"); return THOR_EINVAL; }
+  if (n_acoustic < 2 || (n_acoustic & 1)) { set_error("thor_batch_autotune: n_acoustic must be even and >= 2"); return THOR_EINVAL; }
+  static const int cand[] = {1, 2, 4, 8};
+  std::vector<std::vector<double>> blobs(b->n);
+  for (int i = 0; i < b->n; ++i) {
+    blobs[i].resize(thor_state_blob_bytes(b->members[i]) / sizeof(double));
+    int rc = thor_diag(b->members[i], THOR_DIAG_STATE_EXPORT, 0, blobs[i].data(), blobs[i].size() * sizeof(double));
+    if (rc != THOR_OK && rc != THOR_ENONFINITE) return rc;
+  }
+  const size_t pb = b->precision == THOR_MIXED ? planet_table_bytes<float>(b->n) : planet_table_bytes<double>(b->n);
+  hipEvent_t e0, e1;
+  if (!hip_ok(hipEventCreate(&e0), "event") || !hip_ok(hipEventCreate(&e1), "event")) return THOR_EHIP;
+  // time whole eager large steps for each candidate of one family at a time
+  for (int fam = 0; fam < FAM_COUNT; ++fam) {
+    double best = 1e30;
+    int best_w = b->wpb[fam];
+    for (int w : cand) {
+      b->wpb[fam] = w;
+      int rc = upload_tiles(b, pb);
+      if (rc != THOR_OK) return rc;
+      batch_enqueue(b, n_acoustic, b->parity, b->stream);   // warm-up
+      batch_flip(b);
+      (void)hipEventRecord(e0, b->stream);
+      batch_enqueue(b, n_acoustic, b->parity, b->stream);
+      batch_flip(b);
+      (void)hipEventRecord(e1, b->stream);
+      if (!hip_ok(hipEventSynchronize(e1), "autotune synchronize")) return THOR_EHIP;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        best_w = w;
+      }
+    }
+    b->wpb[fam] = best_w;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  int rc = upload_tiles(b, pb);
+  if (rc != THOR_OK) return rc;
+  batch_drop_graphs(b);
+  for (int i = 0; i < b->n; ++i) {
+    rc = thor_state_import(b->members[i], blobs[i].data(), blobs[i].size() * sizeof(double));
+    if (rc != THOR_OK) return rc;
+  }
+  if (wpb_out)
+    for (int k = 0; k < FAM_COUNT; ++k) wpb_out[k] = b->wpb[k];
+  return THOR_OK;
+}
+
+void thor_batch_free(thor_batch *b) {
+  if (!b) return;
+  batch_drop_graphs(b);
+  for (auto m : b->members) thor_state_free(m);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  delete b;
 }
 
 }  // extern "C"

@@ -23,7 +23,9 @@ FIELDS = {"T": 0, "u": 1, "v": 2, "w": 3, "p": 4, "rho": 5, "rhotheta": 6,
 EXPORTED = ["thor_last_error", "thor_grid_params_default", "thor_grid_build", "thor_grid_info",
             "thor_grid_export", "thor_grid_coefficients", "thor_grid_free", "thor_state_bytes",
             "thor_state_init", "thor_step", "thor_diag", "thor_state_blob_bytes",
-            "thor_state_import", "thor_set_timing", "thor_kernel_time", "thor_state_free"]
+            "thor_state_import", "thor_set_timing", "thor_kernel_time", "thor_state_free",
+            "thor_autotune", "thor_batch_bytes", "thor_batch_init", "thor_batch_step",
+            "thor_batch_member", "thor_batch_autotune", "thor_batch_free"]
 
 
 class ThorError(RuntimeError):
@@ -99,8 +101,19 @@ def lib():
     L.thor_state_import.argtypes = [vp, vp, ctypes.c_size_t]
     L.thor_set_timing.argtypes = [vp, ctypes.c_int]
     L.thor_kernel_time.argtypes = [vp, ctypes.c_char_p, dp, ip]
+    L.thor_autotune.argtypes = [vp, ctypes.c_int, ip]
     L.thor_state_free.argtypes = [vp]
     L.thor_state_free.restype = None
+    L.thor_batch_bytes.argtypes = [ctypes.c_int, vp, ctypes.POINTER(Vertical), ctypes.POINTER(Numerics),
+                                   ctypes.POINTER(ctypes.c_size_t)]
+    L.thor_batch_init.argtypes = [ctypes.c_int, vp, ctypes.POINTER(Planet), ctypes.POINTER(Vertical),
+                                  ctypes.POINTER(Numerics), ctypes.POINTER(Forcing), ctypes.POINTER(Init),
+                                  vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.thor_batch_step.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.thor_batch_member.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp)]
+    L.thor_batch_autotune.argtypes = [vp, ctypes.c_int, ip]
+    L.thor_batch_free.argtypes = [vp]
+    L.thor_batch_free.restype = None
     _lib = L
     return L
 
@@ -194,8 +207,65 @@ def thor_kernel_time(sh, name):
     return ms.value, cnt.value
 
 
+def thor_autotune(sh, n_acoustic):
+    """Returns the chosen wavefronts per workgroup per kernel family."""
+    out = (ctypes.c_int * 5)()
+    _check(lib().thor_autotune(sh, n_acoustic, out))
+    return dict(zip(("large", "slow", "hmom", "vert", "graddiv"), list(out)))
+
+
 def thor_state_free(sh):
     lib().thor_state_free(sh)
+
+
+def _arrays(structs_per_member):
+    cols = list(zip(*structs_per_member))
+    out = []
+    for col in cols:
+        T = type(col[0]) * len(col)
+        out.append(T(*col))
+    return out
+
+
+def thor_batch_bytes(grid_handles, verts, nums):
+    n = len(grid_handles)
+    gh = (ctypes.c_void_p * n)(*[g.value for g in grid_handles])
+    V = (Vertical * n)(*verts)
+    N = (Numerics * n)(*nums)
+    out = ctypes.c_size_t()
+    _check(lib().thor_batch_bytes(n, gh, V, N, ctypes.byref(out)))
+    return out.value
+
+
+def thor_batch_init(grid_handles, members, dev_ptr, dev_bytes, stream_ptr):
+    """members: list of (planet, vert, num, forcing, init) structs."""
+    n = len(grid_handles)
+    gh = (ctypes.c_void_p * n)(*[g.value for g in grid_handles])
+    P, V, N, F, I = _arrays(members)
+    h = ctypes.c_void_p()
+    _check(lib().thor_batch_init(n, gh, P, V, N, F, I, ctypes.c_void_p(dev_ptr), dev_bytes,
+                                 ctypes.c_void_p(stream_ptr), ctypes.byref(h)))
+    return h
+
+
+def thor_batch_step(bh, n_large, n_acoustic):
+    _check(lib().thor_batch_step(bh, n_large, n_acoustic))
+
+
+def thor_batch_member(bh, i):
+    h = ctypes.c_void_p()
+    _check(lib().thor_batch_member(bh, i, ctypes.byref(h)))
+    return h
+
+
+def thor_batch_autotune(bh, n_acoustic):
+    out = (ctypes.c_int * 5)()
+    _check(lib().thor_batch_autotune(bh, n_acoustic, out))
+    return dict(zip(("large", "slow", "hmom", "vert", "graddiv"), list(out)))
+
+
+def thor_batch_free(bh):
+    lib().thor_batch_free(bh)
 
 
 # ---------------------------------------------------------------------------
@@ -280,6 +350,50 @@ class State:
         try:
             if getattr(self, "handle", None):
                 thor_state_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+class Member:
+    """A member of an ensemble seen as a state (diagnostics only)."""
+
+    def __init__(self, batch, i, n_col, n_lev):
+        self.batch, self.handle, self.n_col, self.n_lev = batch, thor_batch_member(batch.handle, i), n_col, n_lev
+
+    field = State.field
+    mass = State.mass
+    scalars = State.scalars
+    export = State.export
+
+    def __del__(self):
+        pass
+
+
+class Batch:
+    """An ensemble of planets in one torch-owned device buffer."""
+
+    def __init__(self, grids, members, device="cuda:0", stream=None):
+        self.grids = grids
+        verts = [m[1] for m in members]
+        nums = [m[2] for m in members]
+        nbytes = thor_batch_bytes([g.handle for g in grids], verts, nums)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.buf.device)
+        self.handle = thor_batch_init([g.handle for g in grids], members, self.buf.data_ptr(), nbytes,
+                                      self.stream.cuda_stream)
+        self.members = [Member(self, i, g.n, v.n_lev) for i, (g, v) in enumerate(zip(grids, verts))]
+
+    def step(self, n_large, n_acoustic):
+        thor_batch_step(self.handle, n_large, n_acoustic)
+
+    def autotune(self, n_acoustic):
+        return thor_batch_autotune(self.handle, n_acoustic)
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                thor_batch_free(self.handle)
                 self.handle = None
         except Exception:
             pass

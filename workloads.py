@@ -104,3 +104,32 @@ def gas_giant_c3():
 def small_gas_giant(glevel=3, n_lev=12, seed=7, n_large=3):
     """Small gas-giant case for fast parity tests of the forcing path."""
     return gas_giant(glevel, n_lev, seed, n_large, dt=300.0 * 2 ** (6 - glevel), n_acoustic=8)
+
+
+def ensemble(n=64, seed=4, glevels=(4, 5, 6), levels=(20, 32, 48), n_acoustic=8):
+    """Ensemble of planets: grid level and layer count drawn uniformly from the
+    given sets, radius log-uniform in [3e6, 1e8] m, rotation log-uniform in
+    [1e-6, 1e-4] 1/s, isothermal 200-1500 K with +/-0.1 K noise; Earth air
+    (Rd 287, cp 1005), gravity 9.8, surface pressure 1e5 Pa, lid at
+    ln(100) scale heights.  Time step per planet:
+    min(n floor(0.1 dbar / c_s), 0.25 / Omega, 1800 s), i.e. an acoustic
+    Courant number <= 0.1 per substep and 2 Omega dt <= 0.5."""
+    import numpy as np
+    rs = np.random.default_rng(seed)
+    out = []
+    Rd, Cp, g = 287.0, 1005.0, 9.8
+    gamma = Cp / (Cp - Rd)
+    for i in range(n):
+        gl = int(rs.choice(glevels))
+        L = int(rs.choice(levels))
+        A = float(np.exp(rs.uniform(np.log(3e6), np.log(1e8))))
+        om = float(np.exp(rs.uniform(np.log(1e-6), np.log(1e-4))))
+        T0 = float(rs.uniform(200.0, 1500.0))
+        dbar = math.sqrt(2 * math.pi / 5) * A / 2 ** gl
+        cs = math.sqrt(gamma * Rd * T0)
+        dt = min(n_acoustic * math.floor(0.1 * dbar / cs), 0.25 / om, 1800.0)
+        z_top = Rd * T0 / g * math.log(100.0)
+        out.append(Workload(f"member{i}-g{gl}L{L}", gl, L, z_top, A, om, g, Rd, Cp, 1.0e5,
+                            dt, n_acoustic, 1, D_EARTH, True, T0, 1.0e5, 0.1,
+                            seed * 1000 + i))
+    return out
