@@ -72,6 +72,47 @@ def run_gpu(w, precision, steps, warmup):
     return T, kt, sc, tuned
 
 
+def run_ensemble(steps, warmup):
+    """The 64-planet ensemble advanced with one launch per phase, against the
+    same planets advanced one after the other with the single-planet path."""
+    import torch
+    import workloads
+    from paper_1607_05535_amd import thor
+    ws = workloads.ensemble()
+    grids = {}
+    members = []
+    for i, w in enumerate(ws):
+        grids.setdefault(w.glevel, thor.Grid(w.glevel))
+        pl, v, num, fo, ini = thor.structs_from_workload(w)
+        ini.planet_index = i
+        members.append((pl, v, num, fo, ini))
+    updates = sum(w.cells * w.substeps_per_large for w in ws) * steps
+    b = thor.Batch([grids[w.glevel] for w in ws], members)
+    wpb = b.autotune(8)
+    b.step(warmup, 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps, 8)
+    torch.cuda.synchronize()
+    Tb = time.perf_counter() - t0
+    del b
+    torch.cuda.empty_cache()
+    Ts = 0.0
+    for i, w in enumerate(ws):
+        st = thor.State(grids[w.glevel], *members[i])
+        st.step(warmup, 8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.step(steps, 8)
+        torch.cuda.synchronize()
+        Ts += time.perf_counter() - t0
+        del st
+    return {"value": updates / Tb, "unit": "cell-updates/s", "planets": len(ws),
+            "cells": sum(w.cells for w in ws), "ms_per_step": Tb / steps * 1e3,
+            "one_by_one_value": updates / Ts, "speedup_vs_one_by_one": Ts / Tb,
+            "autotuned_wavefronts_per_workgroup": wpb}
+
+
 def cpu_baseline(w):
     """The FP64 oracle on the host: one large step's worth estimated from a
     bounded sample (the per-step terms, one RK stage of slow terms and two
@@ -126,6 +167,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -178,6 +220,8 @@ def main():
                         "speedup_vs_fp64": T64 / T32,
                         "vert_achieved_GBs": vb32 / vm / 1e9 if vm > 0 else 0.0,
                         "kernel_ms": {k: v[0] for k, v in kt32.items()}}
+    if not args.no_ensemble:
+        out["ensemble"] = run_ensemble(max(1, args.steps // 10), 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -267,6 +267,106 @@ int thor_batch_autotune(thor_batch *b, int n_acoustic, int *wpb_out);
 
 void thor_batch_free(thor_batch *b);   /* frees the members; never frees dev_buf */
 
+/* ---------------------------------------------------------------------------
+ * Per-column corrector network: a multilayer perceptron with GELU hidden
+ * layers, z = W h + b, W [out][in] row-major.  Operands are BF16 and products
+ * accumulate in FP32 on the matrix cores; master weights, gradients and the
+ * Adam moments are FP32.  Widths must be multiples of 32.  All device
+ * pointers below are caller-owned device memory; the object lives in the
+ * caller's buffer of thor_mlp_bytes bytes and enqueues on hip_stream.
+ * ------------------------------------------------------------------------- */
+typedef struct thor_mlp thor_mlp;
+
+/* widths[0] = inputs, widths[n_layers] = outputs; max_batch rows per call. */
+int thor_mlp_bytes(int n_layers, const int *widths, int max_batch, size_t *bytes);
+
+/* He-normal weights from a SplitMix64 stream of `seed`, zero biases.
+ * EINVAL: bad shape.  ENOMEM: dev_bytes too small.  Synchronises. */
+int thor_mlp_init(int n_layers, const int *widths, int max_batch, uint64_t seed,
+                  void *dev_buf, size_t dev_bytes, void *hip_stream, thor_mlp **out);
+
+/* Number of FP32 parameters, packed as W1, b1, W2, b2, ... */
+size_t thor_mlp_param_count(const thor_mlp *m);
+int thor_mlp_set_params(thor_mlp *m, const float *host_params);   /* resets Adam; synchronises */
+int thor_mlp_get_params(thor_mlp *m, float *host_params);         /* synchronises */
+
+/* y[B][out] (device, FP32) = network(x[B][in] device BF16).  Asynchronous.
+ * EINVAL: B outside 1..max_batch. */
+int thor_mlp_forward(thor_mlp *m, const void *x_bf16, int B, float *y);
+
+/* Mean-squared loss sum (y - t)^2 / (B out) and, if grad_host is not NULL,
+ * its gradient packed like the parameters (host FP32).  B % 32 == 0.
+ * Synchronises. */
+int thor_mlp_loss_grad(thor_mlp *m, const void *x_bf16, const float *t, int B,
+                       double *loss, float *grad_host);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean-squared loss of a
+ * batch (B % 32 == 0).  Asynchronous. */
+int thor_mlp_train_step(thor_mlp *m, const void *x_bf16, const float *t, int B, float lr);
+
+void thor_mlp_free(thor_mlp *m);   /* never frees dev_buf */
+
+/* ---------------------------------------------------------------------------
+ * Learned per-column corrector of a coarse run toward a fine run.
+ *
+ * Restriction (fine grid -> coarse grid, same levels): every fine column goes
+ * to the coarse column whose point is nearest (largest dot product, ties to
+ * the lower id); T and p are area-weighted means over a coarse column's fine
+ * columns, the velocity is the mass-weighted mean of the Cartesian velocity
+ * projected on the coarse tangent plane; the coarse prognostic state is
+ * rebuilt from them (rho = p / Rd T, rho theta from p, M = rho v,
+ * W = interface mean of rho w).
+ * ------------------------------------------------------------------------- */
+typedef struct thor_restriction thor_restriction;
+typedef struct thor_corrector thor_corrector;
+
+int thor_restriction_bytes(const thor_grid *fine, const thor_grid *coarse, size_t *bytes);
+/* Builds the map on the host and uploads it into dev_buf.  Synchronises.
+ * EINVAL: fine coarser than coarse, or a coarse column left empty. */
+int thor_restriction_build(const thor_grid *fine, const thor_grid *coarse, void *dev_buf,
+                           size_t dev_bytes, void *hip_stream, thor_restriction **out);
+int thor_restriction_export(const thor_restriction *r, int32_t *coarse_of_fine /*[n_fine]*/);
+void thor_restriction_free(thor_restriction *r);
+
+/* Overwrite coarse's state with the restriction of fine's (same levels,
+ * lid and precision).  Waits for fine's stream, then enqueues on coarse's. */
+int thor_restrict(thor_state *fine, thor_state *coarse, const thor_restriction *r);
+
+/* (T, u, v, w, p) of every cell as FP32 [5][n_col][n_lev] into device memory.
+ * Asynchronous. */
+int thor_state_fields32(thor_state *s, float *dev_out);
+
+/* Per-field mean and standard deviation (host out: 5 means then 5 spreads)
+ * over n_arrays field arrays [5][n_col][n_lev] spaced `stride` floats apart,
+ * of C itself or, if Fn is not NULL, of Fn - C.  FP64 sums.  Scratch: at
+ * least n_arrays * 640 doubles of device memory.  Synchronises. */
+int thor_field_stats(const float *C, const float *Fn, int n_arrays, size_t stride, int n_col,
+                     int n_lev, void *dev_scratch, size_t scratch_bytes, void *hip_stream,
+                     double *mean_std_host);
+
+/* A corrector of state s by network net (35 n_lev inputs, 5 n_lev outputs,
+ * max_batch >= n_col; n_lev a multiple of 32).  norm_host: 20 floats, the
+ * input field means and spreads, then those of the targets (fine - coarse).
+ * A column is corrected only while every normalised output stays within
+ * `bound` (else it keeps the plain coarse state). */
+int thor_corrector_bytes(const thor_state *s, size_t *bytes);
+int thor_corrector_init(thor_state *s, thor_mlp *net, const float *norm_host, float bound,
+                        void *dev_buf, size_t dev_bytes, thor_corrector **out);
+
+/* Training batch from stored pairs (device arrays): row b is column cols[b]
+ * of pair pairs[b]; inputs from coarse_fields, targets the normalised
+ * fine_fields - coarse_fields of that column; pairs are pair_stride floats
+ * apart.  x_bf16 [B][35 n_lev], target [B][5 n_lev].  Asynchronous. */
+int thor_corrector_batch(thor_corrector *c, const float *coarse_fields, const float *fine_fields,
+                         size_t pair_stride, const int32_t *pairs, const int32_t *cols, int B,
+                         void *x_bf16, float *target);
+
+/* Apply the network to the state once (fields, inputs, forward, bounded
+ * update).  n_applied (may be NULL; then asynchronous) receives the number
+ * of corrected columns. */
+int thor_corrector_apply(thor_corrector *c, int *n_applied);
+void thor_corrector_free(thor_corrector *c);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,13 @@ EXPORTED = ["thor_last_error", "thor_grid_params_default", "thor_grid_build", "t
             "thor_state_init", "thor_step", "thor_diag", "thor_state_blob_bytes",
             "thor_state_import", "thor_set_timing", "thor_kernel_time", "thor_state_free",
             "thor_autotune", "thor_batch_bytes", "thor_batch_init", "thor_batch_step",
-            "thor_batch_member", "thor_batch_autotune", "thor_batch_free"]
+            "thor_batch_member", "thor_batch_autotune", "thor_batch_free",
+            "thor_mlp_bytes", "thor_mlp_init", "thor_mlp_param_count", "thor_mlp_set_params",
+            "thor_mlp_get_params", "thor_mlp_forward", "thor_mlp_loss_grad", "thor_mlp_train_step",
+            "thor_mlp_free", "thor_restriction_bytes", "thor_restriction_build",
+            "thor_restriction_export", "thor_restriction_free", "thor_restrict", "thor_state_fields32",
+            "thor_field_stats", "thor_corrector_bytes", "thor_corrector_init", "thor_corrector_batch",
+            "thor_corrector_apply", "thor_corrector_free"]
 
 
 class ThorError(RuntimeError):
@@ -114,6 +120,34 @@ def lib():
     L.thor_batch_autotune.argtypes = [vp, ctypes.c_int, ip]
     L.thor_batch_free.argtypes = [vp]
     L.thor_batch_free.restype = None
+    L.thor_mlp_bytes.argtypes = [ctypes.c_int, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    L.thor_mlp_init.argtypes = [ctypes.c_int, vp, ctypes.c_int, ctypes.c_uint64, vp, ctypes.c_size_t, vp,
+                                ctypes.POINTER(vp)]
+    L.thor_mlp_param_count.argtypes = [vp]
+    L.thor_mlp_param_count.restype = ctypes.c_size_t
+    L.thor_mlp_set_params.argtypes = [vp, vp]
+    L.thor_mlp_get_params.argtypes = [vp, vp]
+    L.thor_mlp_forward.argtypes = [vp, vp, ctypes.c_int, vp]
+    L.thor_mlp_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int, dp, vp]
+    L.thor_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_float]
+    L.thor_mlp_free.argtypes = [vp]
+    L.thor_mlp_free.restype = None
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    L.thor_restriction_bytes.argtypes = [vp, vp, szp]
+    L.thor_restriction_build.argtypes = [vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.thor_restriction_export.argtypes = [vp, vp]
+    L.thor_restriction_free.argtypes = [vp]
+    L.thor_restriction_free.restype = None
+    L.thor_restrict.argtypes = [vp, vp, vp]
+    L.thor_state_fields32.argtypes = [vp, vp]
+    L.thor_field_stats.argtypes = [vp, vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, vp,
+                                   ctypes.c_size_t, vp, dp]
+    L.thor_corrector_bytes.argtypes = [vp, szp]
+    L.thor_corrector_init.argtypes = [vp, vp, vp, ctypes.c_float, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.thor_corrector_batch.argtypes = [vp, vp, vp, ctypes.c_size_t, vp, vp, ctypes.c_int, vp, vp]
+    L.thor_corrector_apply.argtypes = [vp, ip]
+    L.thor_corrector_free.argtypes = [vp]
+    L.thor_corrector_free.restype = None
     _lib = L
     return L
 
@@ -394,6 +428,157 @@ class Batch:
         try:
             if getattr(self, "handle", None):
                 thor_batch_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Corrector network
+# ---------------------------------------------------------------------------
+def thor_mlp_bytes(widths, max_batch):
+    w = (ctypes.c_int * len(widths))(*widths)
+    out = ctypes.c_size_t()
+    _check(lib().thor_mlp_bytes(len(widths) - 1, w, max_batch, ctypes.byref(out)))
+    return out.value
+
+
+def thor_mlp_init(widths, max_batch, seed, dev_ptr, dev_bytes, stream_ptr):
+    w = (ctypes.c_int * len(widths))(*widths)
+    h = ctypes.c_void_p()
+    _check(lib().thor_mlp_init(len(widths) - 1, w, max_batch, seed, ctypes.c_void_p(dev_ptr), dev_bytes,
+                               ctypes.c_void_p(stream_ptr), ctypes.byref(h)))
+    return h
+
+
+class MLP:
+    """Corrector network in a torch-owned device buffer.  Inputs are bf16
+    device tensors [B, in]; targets and outputs fp32 device tensors."""
+
+    def __init__(self, widths, max_batch, seed=0, device="cuda:0"):
+        self.widths = list(widths)
+        nbytes = thor_mlp_bytes(self.widths, max_batch)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream(self.buf.device)
+        self.handle = thor_mlp_init(self.widths, max_batch, seed, self.buf.data_ptr(), nbytes,
+                                    self.stream.cuda_stream)
+        self.n_params = lib().thor_mlp_param_count(self.handle)
+
+    def get_params(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().thor_mlp_get_params(self.handle, out.ctypes.data))
+        return out
+
+    def set_params(self, host):
+        host = np.ascontiguousarray(host, dtype=np.float32)
+        assert host.size == self.n_params
+        _check(lib().thor_mlp_set_params(self.handle, host.ctypes.data))
+
+    def unpack(self, flat):
+        """Packed parameters -> [(W[out, in], b[out])]."""
+        out, off = [], 0
+        for i, o in zip(self.widths[:-1], self.widths[1:]):
+            W = flat[off:off + i * o].reshape(o, i)
+            off += i * o
+            b = flat[off:off + o]
+            off += o
+            out.append((W, b))
+        return out
+
+    def forward(self, x, y):
+        _check(lib().thor_mlp_forward(self.handle, x.data_ptr(), x.shape[0], y.data_ptr()))
+
+    def loss_grad(self, x, t, want_grad=True):
+        loss = ctypes.c_double()
+        g = np.empty(self.n_params, dtype=np.float32) if want_grad else None
+        _check(lib().thor_mlp_loss_grad(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0], ctypes.byref(loss),
+                                        g.ctypes.data if want_grad else None))
+        return loss.value, g
+
+    def train_step(self, x, t, lr):
+        _check(lib().thor_mlp_train_step(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0], lr))
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().thor_mlp_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Restriction and corrector
+# ---------------------------------------------------------------------------
+class Restriction:
+    def __init__(self, fine_grid, coarse_grid, device="cuda:0"):
+        nbytes = ctypes.c_size_t()
+        _check(lib().thor_restriction_bytes(fine_grid.handle, coarse_grid.handle, ctypes.byref(nbytes)))
+        self.buf = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+        self.n_fine = fine_grid.n
+        h = ctypes.c_void_p()
+        _check(lib().thor_restriction_build(fine_grid.handle, coarse_grid.handle, self.buf.data_ptr(), nbytes.value,
+                                            torch.cuda.current_stream(self.buf.device).cuda_stream, ctypes.byref(h)))
+        self.handle = h
+
+    def coarse_of_fine(self):
+        out = np.empty(self.n_fine, dtype=np.int32)
+        _check(lib().thor_restriction_export(self.handle, out.ctypes.data))
+        return out
+
+    def __call__(self, fine_state, coarse_state):
+        _check(lib().thor_restrict(fine_state.handle, coarse_state.handle, self.handle))
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().thor_restriction_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+def thor_state_fields32(state, out):
+    """(T, u, v, w, p) FP32 [5, n_col, n_lev] into the device tensor out."""
+    _check(lib().thor_state_fields32(state.handle, out.data_ptr()))
+
+
+def thor_field_stats(C, Fn, n_arrays, stride, n_col, n_lev):
+    scratch = torch.empty(n_arrays * 640, dtype=torch.float64, device=C.device)
+    out = np.empty(10)
+    _check(lib().thor_field_stats(C.data_ptr(), Fn.data_ptr() if Fn is not None else None, n_arrays, stride,
+                                  n_col, n_lev, scratch.data_ptr(), scratch.numel() * 8,
+                                  torch.cuda.current_stream(C.device).cuda_stream,
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+class Corrector:
+    def __init__(self, state, net, norm, bound=5.0):
+        nbytes = ctypes.c_size_t()
+        _check(lib().thor_corrector_bytes(state.handle, ctypes.byref(nbytes)))
+        self.buf = torch.empty(nbytes.value, dtype=torch.uint8, device=state.buf.device)
+        self.state, self.net = state, net
+        norm = np.ascontiguousarray(norm, dtype=np.float32)
+        assert norm.size == 20
+        h = ctypes.c_void_p()
+        _check(lib().thor_corrector_init(state.handle, net.handle, norm.ctypes.data, bound, self.buf.data_ptr(),
+                                         nbytes.value, ctypes.byref(h)))
+        self.handle = h
+
+    def batch(self, C, F, pair_stride, pairs, cols, x, t):
+        _check(lib().thor_corrector_batch(self.handle, C.data_ptr(), F.data_ptr(), pair_stride, pairs.data_ptr(),
+                                          cols.data_ptr(), pairs.numel(), x.data_ptr(), t.data_ptr()))
+
+    def apply(self, count=True):
+        n = ctypes.c_int()
+        _check(lib().thor_corrector_apply(self.handle, ctypes.byref(n) if count else None))
+        return n.value if count else None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().thor_corrector_free(self.handle)
                 self.handle = None
         except Exception:
             pass

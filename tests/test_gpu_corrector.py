@@ -1,0 +1,76 @@
+"""Learned corrector pipeline: restriction, bounded application and the gain
+of a trained network over the plain coarse step, judged by the restricted
+fine run (small grids)."""
+import numpy as np
+import pytest
+
+import workloads
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_restriction_map_is_nearest_point():
+    from paper_1607_05535_amd import thor
+    fg, cg = thor.Grid(4), thor.Grid(2)
+    r = thor.Restriction(fg, cg)
+    m = r.coarse_of_fine()
+    _, xf, _ = fg.export()
+    _, xc, _ = cg.export()
+    dots = xf @ xc.T
+    ref = np.argmax(dots, axis=1)
+    assert np.array_equal(m, ref)
+    assert len(np.unique(m)) == cg.n
+
+
+def test_restriction_of_a_uniform_rest_state():
+    """Every fine column of a resting isothermal state is the same column:
+    the restriction reproduces it on the coarse grid, whatever was there."""
+    import torch
+    from paper_1607_05535_amd import thor
+    fw, cw = workloads.corrector_pair(4, 2, dt_coarse=2400.0)
+    fw.noise_amp = 0.0
+    cw.T0 = 900.0                       # a different state to overwrite
+    fg, cg = thor.Grid(4), thor.Grid(2)
+    fine = thor.State(fg, *thor.structs_from_workload(fw))
+    coarse = thor.State(cg, *thor.structs_from_workload(cw))
+    ref = {k: fine.field(k)[0][0] for k in ("T", "p", "rho", "rhotheta")}
+    thor.Restriction(fg, cg)(fine, coarse)
+    torch.cuda.synchronize()
+    for k, v in ref.items():
+        got = coarse.field(k)[0]
+        assert np.abs(got / v[None, :] - 1).max() < 1e-12, k
+    for k in ("u", "v", "w"):
+        assert np.abs(coarse.field(k)[0]).max() < 1e-12
+
+
+def _pipeline():
+    from paper_1607_05535_amd import learned
+    fw, cw = workloads.corrector_pair(4, 3, dt_coarse=4800.0)
+    return learned.Pipeline(fw, cw, ratio=4)
+
+
+def test_bound_zero_keeps_the_plain_coarse_state():
+    from paper_1607_05535_amd import thor, learned
+    P = _pipeline()
+    C, F = P.make_pairs([7], spinup=4, pairs_per_seed=2)
+    norm = P.norm(C, F)
+    net = thor.MLP(learned.widths_for(P.L), P.N, seed=1)
+    corr = thor.Corrector(P.work, net, norm, bound=0.0)
+    before = P.work.export()[0]
+    assert corr.apply() == 0
+    assert np.array_equal(P.work.export()[0], before)
+
+
+def test_trained_corrector_beats_plain_coarse_step():
+    P = _pipeline()
+    say("[corrector] g4 fine / g3 coarse, L32")
+    C, F = P.make_pairs([11, 12, 13, 14], spinup=20, pairs_per_seed=24, log=say)
+    norm = P.norm(C, F)
+    net, corr, losses = P.train(C, F, norm, steps=600, batch=1024, lr=2e-3, seed=3, log=say)
+    assert losses[-1][1] < 0.5 * losses[0][1]
+    res = P.evaluate(corr, [99], spinup=20, pairs_per_seed=8)
+    say(f"           held-out {res}")
+    assert res["columns_corrected_fraction"] > 0.5
+    for k in ("T", "p"):
+        assert res[k]["rms_corrected"] < res[k]["rms_plain"], k

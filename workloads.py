@@ -133,3 +133,16 @@ def ensemble(n=64, seed=4, glevels=(4, 5, 6), levels=(20, 32, 48), n_acoustic=8)
                             dt, n_acoustic, 1, D_EARTH, True, T0, 1.0e5, 0.1,
                             seed * 1000 + i))
     return out
+
+
+def corrector_pair(fine_glevel=7, coarse_glevel=5, n_lev=32, dt_coarse=600.0, ratio=4, base_seed=1000):
+    """Coarse and fine gas-giant runs for the learned corrector: same planet,
+    levels, forcing (substellar longitude from base_seed) and noise recipe;
+    the fine step is dt_coarse / ratio.  Seeds of individual trajectories are
+    set by the caller."""
+    from copy import copy
+    fine = gas_giant(fine_glevel, n_lev, base_seed, 1, dt=dt_coarse / ratio)
+    coarse = copy(fine)
+    coarse.glevel, coarse.dt = coarse_glevel, dt_coarse
+    coarse.name = f"g{coarse_glevel}L{n_lev}-gasgiant"
+    return fine, coarse
