@@ -41,10 +41,39 @@ def vert_bytes_per_cell(L, mixed):
 
 
 def hmom_bytes_per_cell(L, mixed):
+    """Algorithmic bytes of one acoustic phase-M launch per cell: M, S_M, p*
+    and D read, M written, plus per column the neighbour ids, the 7 gradient
+    coefficient vectors, the radial unit vector and the two-ring damping
+    stencil (18 ids and 18 weight vectors)."""
     h = 4 if mixed else 8
-    fields = 13 * h              # M in (3), S_M (3), p* (1), G (3), M out (3)
-    geom = 6 * 4 + 18 * h + 6 * h + 3 * h
+    fields = 11 * h              # M in (3), S_M (3), p* (1), D (1), M out (3)
+    geom = 6 * 4 + 21 * h + 3 * h + 18 * 4 + 54 * h
     return fields + geom / L
+
+
+def achieved_gbs(w, kt, mixed):
+    """Algorithmic GB/s of the two acoustic kernels from their mean launch
+    times (ms)."""
+    out = {}
+    for name, per_cell in (("vert", vert_bytes_per_cell), ("hmom", hmom_bytes_per_cell)):
+        t = kt[name][0] * 1e-3
+        out[name] = per_cell(w.n_lev, mixed) * w.cells / t / 1e9 if t > 0 else 0.0
+    return out
+
+
+def counter_traffic():
+    """HBM bytes per phase-V launch from the committed FETCH_SIZE/WRITE_SIZE
+    counter summary (scaled by the copy-kernel calibration), if it was taken
+    on the kernels as they are now; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "vert_g6L32_counters.json")
+    src = os.path.join(ROOT, "paper_1607_05535_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return rec["hbm_bytes_per_launch"] if rec.get("kernels_hip_sha256") == sha else None
 
 
 def run_gpu(w, precision, steps, warmup):
@@ -66,10 +95,43 @@ def run_gpu(w, precision, steps, warmup):
     # kernel durations with HIP events on the state's stream
     thor.thor_set_timing(st.handle, 1)
     st.step(steps, n)
-    kt = {k: thor.thor_kernel_time(st.handle, k) for k in ("vert", "hmom", "graddiv", "slow", "large")}
+    kt = {k: thor.thor_kernel_time(st.handle, k) for k in ("vert", "hmom", "slow", "large")}
     thor.thor_set_timing(st.handle, 0)
     torch.cuda.synchronize()
     return T, kt, sc, tuned
+
+
+def mixed_one_day():
+    """FP64 and mixed precision on the g7 (163842 columns) x 48 level gas
+    giant for one Earth day (288 steps of 300 s): per-field relative L2
+    difference of the mixed form against FP64 on the same GPU, and the time
+    of each."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1607_05535_amd import thor
+    w = workloads.gas_giant_c3()
+    g = thor.Grid(w.glevel)
+    out, fields, times = {}, {}, {}
+    for prec in (0, 1):
+        st = thor.State(g, *thor.structs_from_workload(w, prec), device="cuda:0")
+        thor.thor_autotune(st.handle, w.n_acoustic)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.step(w.n_large, w.n_acoustic)
+        torch.cuda.synchronize()
+        times[prec] = time.perf_counter() - t0
+        fields[prec] = {k: st.field(k)[0] for k in ("T", "u", "v", "w", "p")}
+        del st
+        torch.cuda.empty_cache()
+    a, b = fields[0], fields[1]
+    speed = np.sqrt(a["u"] ** 2 + a["v"] ** 2 + a["w"] ** 2)
+    for k in ("T", "u", "v", "w", "p"):
+        den = np.linalg.norm(speed) if k in ("u", "v", "w") else np.linalg.norm(a[k])
+        out[k] = float(np.linalg.norm(b[k] - a[k]) / den)
+    return {"workload": "gas giant g7 (163842 columns) x 48 levels, 288 steps of 300 s (one day)",
+            "rel_l2_vs_fp64": out, "max_speed_fp64": float(speed.max()),
+            "seconds_fp64": times[0], "seconds_mixed": times[1], "speedup": times[0] / times[1]}
 
 
 def run_ensemble(steps, warmup):
@@ -168,6 +230,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-one-day", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -207,19 +270,21 @@ def main():
                    "n_col": w.n_col, "n_lev": w.n_lev, "substeps_per_step": subs},
         "roofline": {"bound": "hbm", "kernel": "vert (acoustic phase V)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(),
                      "bytes_per_launch": vb, "mean_launch_ms": kt64["vert"][0]},
         "kernel_ms": {k: v[0] for k, v in kt64.items()},
+        "achieved_GBs": achieved_gbs(w, kt64, False),
         "autotuned_wavefronts_per_workgroup": tuned64,
     }
     if not args.no_mixed:
         T32, kt32, sc32, tuned32 = run_gpu(w, 1, args.steps, args.warmup)
-        vm = kt32["vert"][0] * 1e-3
-        vb32 = vert_bytes_per_cell(w.n_lev, True) * w.cells
-        out["mixed"] = {"value": updates / T32, "ms_per_step": T32 / args.steps * 1e3,
+        out["mixed"] = {"dtype": "f32 horizontal / f64 vertical", "value": updates / T32,
+                        "ms_per_step": T32 / args.steps * 1e3,
                         "speedup_vs_fp64": T64 / T32,
-                        "vert_achieved_GBs": vb32 / vm / 1e9 if vm > 0 else 0.0,
+                        "achieved_GBs": achieved_gbs(w, kt32, True),
                         "kernel_ms": {k: v[0] for k, v in kt32.items()}}
+        if not args.no_one_day:
+            out["mixed"]["one_day"] = mixed_one_day()
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble(max(1, args.steps // 10), 2)
     if not args.no_cpu_baseline:

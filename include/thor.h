@@ -105,6 +105,12 @@ int thor_grid_export(const thor_grid *g, int32_t *nbr, double *xyz, double *area
  *                            triangle-gradient Laplacian of Sec. 4 */
 int thor_grid_coefficients(const thor_grid *g, double *div_coef, double *lap_coef);
 
+/* The divergence-damping operator lap(grad D) of Sec. 4 folded over the
+ * two-ring of each column (host buffers, NULL ok):
+ *   idx[n_col * 18]   two-ring column ids, -1 pads
+ *   w[n_col * 18 * 3] lap(grad D) = (1/r^3) sum_m w_m (D_idx_m - D_0) */
+int thor_grid_damping_coefficients(const thor_grid *g, int32_t *idx, double *w);
+
 void thor_grid_free(thor_grid *g);
 
 /* ---------------------------------------------------------------------------
@@ -212,12 +218,12 @@ size_t thor_state_blob_bytes(const thor_state *s);
  * Synchronises.  EINVAL: wrong size or header. */
 int thor_state_import(thor_state *s, const void *blob, size_t bytes);
 
-/* Autotuner: for each kernel family ("large", "slow", "hmom", "vert",
- * "graddiv") time the candidate workgroup sizes (1, 2, 4 or 8 wavefronts,
+/* Autotuner: for each kernel family ("large", "slow", "hmom", "vert")
+ * time the candidate workgroup sizes (1, 2, 4 or 8 wavefronts,
  * i.e. column groups of 1-8 x floor(64 / n_lev) columns) inside real large
  * steps with n_acoustic substeps on this state, keep the fastest, and restore
  * the state from a checkpoint taken before tuning (the state is unchanged).
- * Synchronises.  wpb_out (5 ints, may be NULL) receives the choice in the
+ * Synchronises.  wpb_out (4 ints, may be NULL) receives the choice in the
  * order above.  EINVAL: n_acoustic < 2 or odd. */
 int thor_autotune(thor_state *s, int n_acoustic, int *wpb_out);
 
@@ -321,8 +327,10 @@ typedef struct thor_restriction thor_restriction;
 typedef struct thor_corrector thor_corrector;
 
 int thor_restriction_bytes(const thor_grid *fine, const thor_grid *coarse, size_t *bytes);
-/* Builds the map on the host and uploads it into dev_buf.  Synchronises.
- * EINVAL: fine coarser than coarse, or a coarse column left empty. */
+/* Builds the map on the host and uploads it into dev_buf (dev_buf NULL: a
+ * host-only map that can be exported but not used by thor_restrict).
+ * Synchronises.  EINVAL: fine coarser than coarse, or a coarse column left
+ * empty. */
 int thor_restriction_build(const thor_grid *fine, const thor_grid *coarse, void *dev_buf,
                            size_t dev_bytes, void *hip_stream, thor_restriction **out);
 int thor_restriction_export(const thor_restriction *r, int32_t *coarse_of_fine /*[n_fine]*/);
@@ -336,17 +344,19 @@ int thor_restrict(thor_state *fine, thor_state *coarse, const thor_restriction *
  * Asynchronous. */
 int thor_state_fields32(thor_state *s, float *dev_out);
 
-/* Per-field mean and standard deviation (host out: 5 means then 5 spreads)
- * over n_arrays field arrays [5][n_col][n_lev] spaced `stride` floats apart,
- * of C itself or, if Fn is not NULL, of Fn - C.  FP64 sums.  Scratch: at
- * least n_arrays * 640 doubles of device memory.  Synchronises. */
+/* Mean and standard deviation per (field, level) (host out: 5 n_lev means
+ * then 5 n_lev spreads, [f][k]) over n_arrays field arrays [5][n_col][n_lev]
+ * spaced `stride` floats apart, of C itself or, if Fn is not NULL, of
+ * Fn - C.  FP64 sums; n_lev must divide 256.  Scratch: at least
+ * n_arrays * 320 * n_lev doubles of device memory.  Synchronises. */
 int thor_field_stats(const float *C, const float *Fn, int n_arrays, size_t stride, int n_col,
                      int n_lev, void *dev_scratch, size_t scratch_bytes, void *hip_stream,
                      double *mean_std_host);
 
 /* A corrector of state s by network net (35 n_lev inputs, 5 n_lev outputs,
- * max_batch >= n_col; n_lev a multiple of 32).  norm_host: 20 floats, the
- * input field means and spreads, then those of the targets (fine - coarse).
+ * max_batch >= n_col; n_lev a multiple of 32).  norm_host: 20 n_lev floats
+ * [4][5][n_lev]: input means and spreads per (field, level), then those of
+ * the targets (fine - coarse).
  * A column is corrected only while every normalised output stays within
  * `bound` (else it keeps the plain coarse state). */
 int thor_corrector_bytes(const thor_state *s, size_t *bytes);

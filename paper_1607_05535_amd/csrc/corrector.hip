@@ -6,7 +6,7 @@
 //
 // Network input of column c: x[(s * 5 + f) * L + k], s = 0 the column, s = 1..6
 // its neighbours (a pentagon repeats itself in slot 6), f over (T, u, v, w, p),
-// k over levels, each normalised by a per-field mean and spread.  Output:
+// k over levels, each normalised by a mean and spread per (field, level).  Output:
 // y[f * L + k], the normalised correction of field f at level k.
 #include <hip/hip_runtime.h>
 
@@ -155,7 +155,8 @@ __global__ void k_features(const float *F, const int32_t *nbr, const float *norm
   const int s = r / (kF * L), f = (r / L) % kF, k = r % L;
   const int src = slot_col(nbr, col, s);
   const float v = F[((size_t)f * N + src) * L + k];
-  X[i] = (__bf16)((v - norm[f]) / norm[kF + f]);
+  const int q = f * L + k;
+  X[i] = (__bf16)((v - norm[q]) / norm[kF * L + q]);
 }
 
 // Training batch: row b is column cols[b] of pair pairs[b]; inputs from the
@@ -174,32 +175,44 @@ __global__ void k_batch(const float *C, const float *Fn, size_t pair_stride, con
     const int s = r / (kF * L), f = (r / L) % kF, k = r % L;
     const int src = slot_col(nbr, col, s);
     const float v = C[base + ((size_t)f * N + src) * L + k];
-    X[(size_t)b * n_in + r] = (__bf16)((v - norm[f]) / norm[kF + f]);
+    const int q = f * L + k;
+    X[(size_t)b * n_in + r] = (__bf16)((v - norm[q]) / norm[kF * L + q]);
   } else {
     const int q = r - (int)n_in, f = q / L, k = q % L;
     const size_t j = base + ((size_t)f * N + col) * L + k;
-    T[(size_t)b * n_out + q] = ((Fn[j] - C[j]) - norm[2 * kF + f]) / norm[3 * kF + f];
+    T[(size_t)b * n_out + q] = ((Fn[j] - C[j]) - norm[2 * kF * L + q]) / norm[3 * kF * L + q];
   }
 }
 
 // Bounded correction of the state's *_t buffers from network outputs Y
 // [col][f * L + k]: a column whose largest |y| exceeds `bound` (or whose
-// corrected pressure would not stay positive) is left unchanged.  The
-// pressure correction sets rho theta at fixed density (T follows), u and v
-// change the horizontal momentum, w the interface vertical momentum.
+// corrected temperature or pressure would not stay positive) is left
+// unchanged.  Otherwise the cell is rebuilt the way a restriction builds it:
+// density from the corrected p and T through the gas law, rho theta from the
+// corrected p, horizontal momentum from the corrected velocity at the new
+// density, and interface vertical momentum rescaled to the new interface
+// density plus the centre increments rho' dw averaged onto the interface.
 template <typename H>
 __global__ __launch_bounds__(256) void k_apply(Fields<H> f, Consts c, const float *Y, const float *norm, float bound,
                                                int *applied) {
   const CLane ln = clane(c.N, c.L);
   const int L = c.L;
-  const size_t idx = (size_t)ln.col * L + ln.lev;
+  const int k = ln.lev;
+  const int lm = ln.lane > 0 ? ln.lane - 1 : 0;
+  const size_t idx = (size_t)ln.col * L + k;
   const float *y = Y + (size_t)ln.col * kF * L;
-  const float yu = y[L + ln.lev], yv = y[2 * L + ln.lev], yw = y[3 * L + ln.lev], yp = y[4 * L + ln.lev];
-  float m = fmaxf(fmaxf(fabsf(y[ln.lev]), fabsf(yu)), fmaxf(fmaxf(fabsf(yv), fabsf(yw)), fabsf(yp)));
+  const float yT = y[k], yu = y[L + k], yv = y[2 * L + k], yw = y[3 * L + k], yp = y[4 * L + k];
+  float m = fmaxf(fmaxf(fabsf(yT), fabsf(yu)), fmaxf(fmaxf(fabsf(yv), fabsf(yw)), fabsf(yp)));
   const double rho = f.rho_t[idx];
   const double p = c.p_ref * pow(c.Rd * f.rth_t[idx] / c.p_ref, c.gamma);
-  const double dp = (double)(yp * norm[3 * kF + 4] + norm[2 * kF + 4]);
-  if (!(p + dp > 0.0)) m = INFINITY;
+  const float *mo = norm + 2 * kF * L, *so = norm + 3 * kF * L;   // output mean, spread [f][k]
+  const double dT = (double)(yT * so[k] + mo[k]);
+  const double du = (double)(yu * so[L + k] + mo[L + k]);
+  const double dv = (double)(yv * so[2 * L + k] + mo[2 * L + k]);
+  const double dw = (double)(yw * so[3 * L + k] + mo[3 * L + k]);
+  const double dp = (double)(yp * so[4 * L + k] + mo[4 * L + k]);
+  const double p1 = p + dp, T1 = p / (rho * c.Rd) + dT;
+  if (!(p1 > 0.0 && T1 > 0.0)) m = INFINITY;
   // largest |y| over the column's lanes
   const int cpw = 64 / L, cw = ln.lane / L;
   for (int s = 1; s < 64; s <<= 1) {
@@ -207,36 +220,39 @@ __global__ __launch_bounds__(256) void k_apply(Fields<H> f, Consts c, const floa
     const int other = (ln.lane ^ s) / L;
     if (other == cw && (ln.lane ^ s) < cpw * L) m = fmaxf(m, o);
   }
-  const double du = (double)(yu * norm[3 * kF + 1] + norm[2 * kF + 1]);
-  const double dv = (double)(yv * norm[3 * kF + 2] + norm[2 * kF + 2]);
-  const double dw = (double)(yw * norm[3 * kF + 3] + norm[2 * kF + 3]);
-  const double rdw = rho * dw;
-  const double rdw_m = __shfl(rdw, ln.lane > 0 ? ln.lane - 1 : 0, 64);
   const bool ok = m <= bound;
+  const double rho1 = ok ? p1 / (c.Rd * T1) : rho;
+  const double rdw = rho1 * dw;
+  const double rdw_m = __shfl(rdw, lm, 64);
+  const double rho_m = __shfl(rho, lm, 64), rho1_m = __shfl(rho1, lm, 64);
   if (!ln.store) return;
-  if (ln.lev == 0 && applied) applied[ln.col] = ok ? 1 : 0;
+  if (k == 0 && applied) applied[ln.col] = ok ? 1 : 0;
   if (!ok) return;
   const H *rh = f.rhat + (size_t)ln.col * 3;
   double e[3], n[3];
   east_north(rh[0], rh[1], rh[2], e, n);
-  f.Mx_t[idx] = (H)((double)f.Mx_t[idx] + rho * (du * e[0] + dv * n[0]));
-  f.My_t[idx] = (H)((double)f.My_t[idx] + rho * (du * e[1] + dv * n[1]));
-  f.Mz_t[idx] = (H)((double)f.Mz_t[idx] + rho * (du * e[2] + dv * n[2]));
-  if (ln.lev > 0) f.W_t[idx] += 0.5 * (rdw_m + rdw);
-  f.rth_t[idx] = c.p_ref / c.Rd * pow((p + dp) / c.p_ref, 1.0 / c.gamma);
+  const double r = rho1 / rho;
+  f.Mx_t[idx] = (H)(r * (double)f.Mx_t[idx] + rho1 * (du * e[0] + dv * n[0]));
+  f.My_t[idx] = (H)(r * (double)f.My_t[idx] + rho1 * (du * e[1] + dv * n[1]));
+  f.Mz_t[idx] = (H)(r * (double)f.Mz_t[idx] + rho1 * (du * e[2] + dv * n[2]));
+  if (k > 0) f.W_t[idx] = f.W_t[idx] * (rho1_m + rho1) / (rho_m + rho) + 0.5 * (rdw_m + rdw);
+  f.rho_t[idx] = rho1;
+  f.rth_t[idx] = c.p_ref / c.Rd * pow(p1 / c.p_ref, 1.0 / c.gamma);
 }
 
-// Per-field sum and sum of squares over n arrays [f][col][lev] (or of the
-// differences Fn - C when Fn is given): one workgroup per (array, field, chunk).
-__global__ __launch_bounds__(256) void k_stats(const float *C, const float *Fn, size_t stride, size_t NL,
+// Per (field, level) sum and sum of squares over n arrays [f][col][lev] (or
+// of the differences Fn - C when Fn is given).  Workgroup (chunk, f, a) runs
+// over a range of columns with thread t on level t % L (L divides 256).
+__global__ __launch_bounds__(256) void k_stats(const float *C, const float *Fn, size_t stride, int N, int L,
                                                double *partial, int chunks) {
   __shared__ double s1[256], s2[256];
   const int chunk = blockIdx.x, f = blockIdx.y, a = blockIdx.z;
-  const size_t per = (NL + chunks - 1) / chunks;
-  const size_t lo = chunk * per, hi = std::min(NL, lo + per);
+  const int per = (N + chunks - 1) / chunks;
+  const int lo = chunk * per, hi = min(N, lo + per);
+  const int k = threadIdx.x % L, c0 = threadIdx.x / L, cstep = 256 / L;
   double x1 = 0, x2 = 0;
-  for (size_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const size_t j = (size_t)a * stride + (size_t)f * NL + i;
+  for (int col = lo + c0; col < hi; col += cstep) {
+    const size_t j = (size_t)a * stride + ((size_t)f * N + col) * L + k;
     const double v = Fn ? (double)Fn[j] - (double)C[j] : (double)C[j];
     x1 += v;
     x2 += v * v;
@@ -244,17 +260,15 @@ __global__ __launch_bounds__(256) void k_stats(const float *C, const float *Fn, 
   s1[threadIdx.x] = x1;
   s2[threadIdx.x] = x2;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      s1[threadIdx.x] += s1[threadIdx.x + s];
-      s2[threadIdx.x] += s2[threadIdx.x + s];
+  if ((int)threadIdx.x < L) {
+    double t1 = 0, t2 = 0;
+    for (int i = threadIdx.x; i < 256; i += L) {
+      t1 += s1[i];
+      t2 += s2[i];
     }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const size_t o = (((size_t)a * kF + f) * chunks + chunk) * 2;
-    partial[o] = s1[0];
-    partial[o + 1] = s2[0];
+    const size_t o = ((((size_t)a * kF + f) * chunks + chunk) * L + threadIdx.x) * 2;
+    partial[o] = t1;
+    partial[o + 1] = t2;
   }
 }
 
@@ -279,7 +293,7 @@ struct thor_corrector {
   thor_state *s = nullptr;
   thor_mlp *net = nullptr;
   float bound = 5.f;
-  float *norm = nullptr;     // device: mu_in[5], sd_in[5], mu_out[5], sd_out[5]
+  float *norm = nullptr;     // device [4][5][L]: input mean, spread; target mean, spread
   float *F = nullptr;        // device fields [5][N][L]
   __bf16 *X = nullptr;       // device inputs [N][35 L]
   float *Y = nullptr;        // device outputs [N][5 L]
@@ -298,11 +312,11 @@ int thor_restriction_bytes(const thor_grid *fine, const thor_grid *coarse, size_
 int thor_restriction_build(const thor_grid *fine, const thor_grid *coarse, void *dev_buf, size_t dev_bytes,
                            void *hip_stream, thor_restriction **out) {
   clear_error();
-  if (!fine || !coarse || !dev_buf || !out) { set_error("thor_restriction_build: NULL argument"); return THOR_EINVAL; }
+  if (!fine || !coarse || !out) { set_error("thor_restriction_build: NULL argument"); return THOR_EINVAL; }
   *out = nullptr;
   size_t need = 0;
   thor_restriction_bytes(fine, coarse, &need);
-  if (dev_bytes < need) { set_error("thor_restriction_build: dev_bytes too small"); return THOR_ENOMEM; }
+  if (dev_buf && dev_bytes < need) { set_error("thor_restriction_build: dev_bytes too small"); return THOR_ENOMEM; }
   const Grid &F = fine->g, &C = coarse->g;
   if (F.glevel < C.glevel) { set_error("thor_restriction_build: fine grid is coarser"); return THOR_EINVAL; }
   thor_restriction *r = new (std::nothrow) thor_restriction;
@@ -355,6 +369,10 @@ int thor_restriction_build(const thor_grid *fine, const thor_grid *coarse, void 
       set_error("thor_restriction_build: a coarse column received no fine column");
       return THOR_EINVAL;
     }
+  if (!dev_buf) {   // host-only map (export works, thor_restrict does not)
+    *out = r;
+    return THOR_OK;
+  }
   char *base = (char *)dev_buf;
   r->off = (int32_t *)base;
   r->list = (int32_t *)(base + ((size_t)(C.n + 1) * 4 + 255) / 256 * 256);
@@ -381,6 +399,7 @@ void thor_restriction_free(thor_restriction *r) { delete r; }
 int thor_restrict(thor_state *fine, thor_state *coarse, const thor_restriction *r) {
   clear_error();
   if (!fine || !coarse || !r) { set_error("thor_restrict: NULL argument"); return THOR_EINVAL; }
+  if (!r->off) { set_error("thor_restrict: the restriction was built without device memory"); return THOR_EINVAL; }
   if (fine->c.N != r->n_fine || coarse->c.N != r->n_coarse || fine->c.L != coarse->c.L ||
       fine->precision != coarse->precision || fine->c.dz != coarse->c.dz) {
     set_error("thor_restrict: states do not match the restriction (grids, levels, precision)");
@@ -411,34 +430,35 @@ int thor_state_fields32(thor_state *s, float *dev_out) {
 int thor_field_stats(const float *C, const float *Fn, int n_arrays, size_t stride, int n_col, int n_lev,
                      void *dev_scratch, size_t scratch_bytes, void *hip_stream, double *mean_std_host) {
   clear_error();
-  if (!C || !dev_scratch || !mean_std_host || n_arrays < 1 || n_col < 1 || n_lev < 1) {
-    set_error("thor_field_stats: bad argument");
+  if (!C || !dev_scratch || !mean_std_host || n_arrays < 1 || n_col < 1 || n_lev < 1 || 256 % n_lev) {
+    set_error("thor_field_stats: bad argument (n_lev must divide 256)");
     return THOR_EINVAL;
   }
-  const int chunks = 64;
-  const size_t np = (size_t)n_arrays * kF * chunks * 2;
+  const int chunks = 32;
+  const size_t np = (size_t)n_arrays * kF * chunks * n_lev * 2;
   if (scratch_bytes < np * sizeof(double)) { set_error("thor_field_stats: scratch too small"); return THOR_ENOMEM; }
   hipStream_t st = (hipStream_t)hip_stream;
-  const size_t NL = (size_t)n_col * n_lev;
-  hipLaunchKernelGGL(k_stats, dim3(chunks, kF, n_arrays), dim3(256), 0, st, C, Fn, stride, NL,
+  hipLaunchKernelGGL(k_stats, dim3(chunks, kF, n_arrays), dim3(256), 0, st, C, Fn, stride, n_col, n_lev,
                      (double *)dev_scratch, chunks);
   std::vector<double> part(np);
   if (!ok_hip(hipMemcpyAsync(part.data(), dev_scratch, np * sizeof(double), hipMemcpyDeviceToHost, st), "copy stats") ||
       !ok_hip(hipStreamSynchronize(st), "stats synchronize"))
     return THOR_EHIP;
-  for (int f = 0; f < kF; ++f) {
-    double s1 = 0, s2 = 0;
-    for (int a = 0; a < n_arrays; ++a)
-      for (int ch = 0; ch < chunks; ++ch) {
-        const size_t o = (((size_t)a * kF + f) * chunks + ch) * 2;
-        s1 += part[o];
-        s2 += part[o + 1];
-      }
-    const double n = (double)n_arrays * NL;
-    const double mu = s1 / n;
-    mean_std_host[f] = mu;
-    mean_std_host[kF + f] = std::sqrt(std::max(s2 / n - mu * mu, 0.0));
-  }
+  const int L = n_lev;
+  for (int f = 0; f < kF; ++f)
+    for (int k = 0; k < L; ++k) {
+      double s1 = 0, s2 = 0;
+      for (int a = 0; a < n_arrays; ++a)
+        for (int ch = 0; ch < chunks; ++ch) {
+          const size_t o = ((((size_t)a * kF + f) * chunks + ch) * L + k) * 2;
+          s1 += part[o];
+          s2 += part[o + 1];
+        }
+      const double n = (double)n_arrays * n_col;
+      const double mu = s1 / n;
+      mean_std_host[f * L + k] = mu;
+      mean_std_host[kF * L + f * L + k] = std::sqrt(std::max(s2 / n - mu * mu, 0.0));
+    }
   return THOR_OK;
 }
 
@@ -447,7 +467,7 @@ int thor_corrector_bytes(const thor_state *s, size_t *bytes) {
   if (!s || !bytes) { set_error("thor_corrector_bytes: NULL argument"); return THOR_EINVAL; }
   const size_t N = s->c.N, L = s->c.L;
   auto a = [](size_t x) { return (x + 255) / 256 * 256; };
-  *bytes = a(4 * kF * 4) + a(kF * N * L * 4) + a(N * 7 * kF * L * 2) + a(N * kF * L * 4) + a(N * 4);
+  *bytes = a(4 * kF * L * 4) + a(kF * N * L * 4) + a(N * 7 * kF * L * 2) + a(N * kF * L * 4) + a(N * 4);
   return THOR_OK;
 }
 
@@ -460,8 +480,8 @@ int thor_corrector_init(thor_state *s, thor_mlp *net, const float *norm_host, fl
   size_t need = 0;
   thor_corrector_bytes(s, &need);
   if (dev_bytes < need) { set_error("thor_corrector_init: dev_bytes too small"); return THOR_ENOMEM; }
-  for (int f = 0; f < kF; ++f)
-    if (!(norm_host[kF + f] > 0) || !(norm_host[3 * kF + f] > 0)) {
+  for (size_t q = 0; q < (size_t)kF * s->c.L; ++q)
+    if (!(norm_host[kF * s->c.L + q] > 0) || !(norm_host[3 * kF * s->c.L + q] > 0)) {
       set_error("thor_corrector_init: spreads must be positive");
       return THOR_EINVAL;
     }
@@ -471,7 +491,7 @@ int thor_corrector_init(thor_state *s, thor_mlp *net, const float *norm_host, fl
   auto a = [](size_t x) { return (x + 255) / 256 * 256; };
   char *base = (char *)dev_buf;
   c->norm = (float *)base;
-  base += a(4 * kF * 4);
+  base += a(4 * kF * L * 4);
   c->F = (float *)base;
   base += a(kF * N * L * 4);
   c->X = (__bf16 *)base;
@@ -482,7 +502,7 @@ int thor_corrector_init(thor_state *s, thor_mlp *net, const float *norm_host, fl
   c->s = s;
   c->net = net;
   c->bound = bound;
-  if (!ok_hip(hipMemcpyAsync(c->norm, norm_host, 4 * kF * 4, hipMemcpyHostToDevice, s->stream), "copy norm") ||
+  if (!ok_hip(hipMemcpyAsync(c->norm, norm_host, 4 * kF * L * 4, hipMemcpyHostToDevice, s->stream), "copy norm") ||
       !ok_hip(hipStreamSynchronize(s->stream), "corrector synchronize")) {
     delete c;
     return THOR_EHIP;

@@ -344,6 +344,44 @@ int build_grid(const thor_grid_params &p, Grid &G) {
       lc[j] = dot(h[j], bj[(cslot[c][j] + 1) % 3]) + dot(h[jm], bm[(cslot[c][jm] + 2) % 3]);
     }
   }
+  // Divergence damping acts as lap(grad D): fold the two stencils into one
+  // over the two-ring of each column (at most 18 other columns):
+  //   lap(grad D)(c) = (1/r^3) sum_m w_m (D_m - D_c).
+  G.dd_idx.assign((size_t)n * kRing2, -1);
+  G.dd_w.assign((size_t)n * kRing2 * 3, 0.0);
+  for (int64_t c = 0; c < n; ++c) {
+    int32_t *idx = &G.dd_idx[(size_t)c * kRing2];
+    double *wv = &G.dd_w[(size_t)c * kRing2 * 3];
+    int cnt = 0;
+    auto slot = [&](int64_t m) -> int {
+      for (int q = 0; q < cnt; ++q)
+        if (idx[q] == m) return q;
+      idx[cnt] = (int32_t)m;
+      return cnt++;
+    };
+    // weight of D_m in G(y) = sum_i e^y_i (D(n^y_i) - D(y)), scaled by s
+    auto add_grad = [&](int64_t y, double s) {
+      const double *dc = &G.div_coef[(size_t)y * 21];
+      for (int i = 0; i < G.deg[y]; ++i) {
+        const int64_t m = G.nbr[(size_t)y * 6 + i];
+        const double *e = dc + 3 * (i + 1);
+        if (m != c) {
+          const int q = slot(m);
+          for (int k = 0; k < 3; ++k) wv[3 * q + k] += s * e[k];
+        }
+        if (y != c) {
+          const int q = slot(y);
+          for (int k = 0; k < 3; ++k) wv[3 * q + k] -= s * e[k];
+        }
+      }
+    };
+    const double *lc = &G.lap_coef[(size_t)c * 6];
+    for (int j = 0; j < G.deg[c]; ++j) add_grad(G.nbr[(size_t)c * 6 + j], lc[j]);
+    double lsum = 0.0;
+    for (int j = 0; j < G.deg[c]; ++j) lsum += lc[j];
+    add_grad(c, -lsum);
+    if (cnt > kRing2) return THOR_EINVAL;
+  }
   return THOR_OK;
 }
 
@@ -376,7 +414,11 @@ int thor_grid_build(const thor_grid_params *p, thor_grid **out) {
   thor_grid *g = new (std::nothrow) thor_grid;
   if (!g) { thor::set_error("thor_grid_build: out of host memory"); return THOR_ENOMEM; }
   try {
-    thor::build_grid(*p, g->g);
+    if (thor::build_grid(*p, g->g) != THOR_OK) {
+      delete g;
+      thor::set_error("thor_grid_build: two-ring stencil larger than expected");
+      return THOR_EINVAL;
+    }
   } catch (const std::bad_alloc &) {
     delete g;
     thor::set_error("thor_grid_build: out of host memory");
@@ -423,6 +465,14 @@ int thor_grid_coefficients(const thor_grid *g, double *div_coef, double *lap_coe
   if (!g) { thor::set_error("thor_grid_coefficients: NULL grid"); return THOR_EINVAL; }
   if (div_coef) std::copy(g->g.div_coef.begin(), g->g.div_coef.end(), div_coef);
   if (lap_coef) std::copy(g->g.lap_coef.begin(), g->g.lap_coef.end(), lap_coef);
+  return THOR_OK;
+}
+
+int thor_grid_damping_coefficients(const thor_grid *g, int32_t *idx, double *w) {
+  thor::clear_error();
+  if (!g) { thor::set_error("thor_grid_damping_coefficients: NULL grid"); return THOR_EINVAL; }
+  if (idx) std::copy(g->g.dd_idx.begin(), g->g.dd_idx.end(), idx);
+  if (w) std::copy(g->g.dd_w.begin(), g->g.dd_w.end(), w);
   return THOR_OK;
 }
 

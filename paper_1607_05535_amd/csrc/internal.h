@@ -9,6 +9,8 @@
 
 namespace thor {
 
+constexpr int kRing2 = 18;   // columns of the two-ring around a column, at most
+
 struct Vec3 {
   double x, y, z;
 };
@@ -26,7 +28,11 @@ struct Grid {
   std::vector<double> area;      // control-volume area (unit sphere)
   std::vector<double> div_coef;  // [n][7][3]
   std::vector<double> lap_coef;  // [n][6]
+  std::vector<int32_t> dd_idx;   // [n][18] two-ring columns, -1 pad
+  std::vector<double> dd_w;      // [n][18][3] lap(grad .) weights
 };
+
+int build_grid(const thor_grid_params &p, Grid &G);
 
 void set_error(const std::string &msg);
 void clear_error();

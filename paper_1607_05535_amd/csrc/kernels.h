@@ -27,6 +27,8 @@ struct Fields {
   const H *dc;            // [N][21] divergence/gradient coefficient vectors
   const H *lc;            // [N][6]  Laplacian neighbour weights
   const H *rhat;          // [N][3]
+  const int32_t *ddi;     // [N][18] two-ring columns (-1 pad)
+  const H *ddw;           // [N][18][3] lap(grad .) weights
   const double *area;     // [N]
   const double *teq;      // [N] Newtonian target temperature
 
@@ -46,8 +48,8 @@ struct Fields {
   double *SW;
   H *thL, *Gam;           // linearisation theta and gamma p / rho theta
   // divergence damping
-  H *D, *Gx, *Gy, *Gz;    // 3D divergence of the small-step state and its gradient
-  H *Dt, *GDx, *GDy, *GDz;
+  H *D;                   // 3D divergence of the small-step state
+  H *Dt;                  // and of Phi[t]
   // large-step temporaries
   double *T, *vx, *vy, *vz, *wI;
   double *Xrho, *Xvx, *Xvy, *Xvz, *Xw, *XT;
@@ -91,8 +93,6 @@ template <typename H>
 void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, bool last,
                  hipStream_t s);
 template <typename H>
-void launch_graddiv(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s);
-template <typename H>
 void launch_slow(const Fields<H> &f, const Consts &c, int wpb, bool from_t, hipStream_t s);
 template <typename H>
 void launch_large(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s);
@@ -110,7 +110,7 @@ struct Planet {
   Consts c;
 };
 
-enum class BatchOp { Large, Slow, Hmom, Vert, VertLast, Graddiv };
+enum class BatchOp { Large, Slow, Hmom, Vert, VertLast };
 
 // Every member of an ensemble in one launch per phase.  arg0/arg1: Slow:
 // from_t; Hmom/Vert: div, first.

@@ -20,6 +20,7 @@
 
 #include <cmath>
 
+#include "internal.h"
 #include "kernels.h"
 
 namespace thor {
@@ -123,14 +124,23 @@ __device__ __forceinline__ void b_hmom(const Fields<H> &f, const Consts &c, cons
   if (!first) grad_at(f.ps, nb, dc, L, lev, idx, ir, gx, gy, gz);
   H ddx = 0, ddy = 0, ddz = 0;
   if (c.div_damp) {
-    const H *lc = f.lc + (size_t)col * 6;
-    const H *Gx = first ? f.GDx : f.Gx;
-    const H *Gy = first ? f.GDy : f.Gy;
-    const H *Gz = first ? f.GDz : f.Gz;
-    const H s = (H)(-c.Kd) * ir * ir;
-    ddx = s * lap_at(Gx, nb, lc, L, lev, idx);
-    ddy = s * lap_at(Gy, nb, lc, L, lev, idx);
-    ddz = s * lap_at(Gz, nb, lc, L, lev, idx);
+    // -Kd lap(grad D) over the two-ring, D of the current small-step state
+    const H *D = first ? f.Dt : f.D;
+    const int32_t *di = f.ddi + (size_t)col * kRing2;
+    const H *dw = f.ddw + (size_t)col * kRing2 * 3;
+    const H d0 = D[idx];
+#pragma unroll 6
+    for (int m = 0; m < kRing2; ++m) {
+      const int cm = di[m] < 0 ? col : di[m];
+      const H dd = D[(size_t)cm * L + lev] - d0;
+      ddx += dw[3 * m] * dd;
+      ddy += dw[3 * m + 1] * dd;
+      ddz += dw[3 * m + 2] * dd;
+    }
+    const H s = (H)(-c.Kd) * ir * ir * ir;
+    ddx *= s;
+    ddy *= s;
+    ddz *= s;
   }
   const H *Mx = first ? f.Mx_t : f.Mx;
   const H *My = first ? f.My_t : f.My;
@@ -265,21 +275,6 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
   }
 }
 
-// G = grad D for the next substep's divergence damping.
-template <typename H>
-__device__ __forceinline__ void b_graddiv(const Fields<H> &f, const Consts &c, const Lane &ln) {
-  if (!ln.store) return;
-  const int L = c.L, lev = ln.lev, col = ln.col;
-  const size_t idx = (size_t)col * L + lev;
-  int nb[6];
-  load_nbr(f.nbr, col, nb);
-  H gx, gy, gz;
-  grad_at(f.D, nb, f.dc + (size_t)col * 21, L, lev, idx, (H)1 / (H)radius_c(c, lev), gx, gy, gz);
-  f.Gx[idx] = gx;
-  f.Gy[idx] = gy;
-  f.Gz[idx] = gz;
-}
-
 // ---------------------------------------------------------------------------
 // Slow terms of one RK stage at the previous stage state: advection of the
 // full Cartesian momentum, Coriolis, projections (Eqs. mom, proj_h, proj_r),
@@ -321,7 +316,7 @@ __device__ __forceinline__ void b_slow(const Fields<H> &f, const Consts &c, cons
     Ay = vy0 * t;
     Az = vz0 * t;
   }
-#pragma unroll
+#pragma unroll 2
   for (int j = 0; j < 6; ++j) {
     const size_t nj = (size_t)nb[j] * L + lev;
     const double wn = lev == 0 ? 0.0 : W[nj];
@@ -482,11 +477,6 @@ __device__ __forceinline__ void b_large2(const Fields<H> &f, const Consts &c, co
   if (lev > 0) f.FW[idx] += -lap_at(f.Xw, nb, lch, L, lev, idx) / (rI * rI);
   const double rth = f.rth_t[idx], p = f.p_t[idx];
   f.Hrth[idx] = rth / (c.gamma * p) * (-c.Rd * irc2 * lap_at(f.XT, nb, lch, L, lev, idx));
-  H gx, gy, gz;
-  grad_at(f.Dt, nb, f.dc + (size_t)col * 21, L, lev, idx, (H)(1.0 / rC), gx, gy, gz);
-  f.GDx[idx] = gx;
-  f.GDy[idx] = gy;
-  f.GDz[idx] = gz;
 }
 
 // Diagnostic field into f.diag (FP64, canonical layout).
@@ -605,8 +595,7 @@ __device__ __forceinline__ void b_import(const Fields<H> &f, const Consts &c, co
   }
 #define COMMA ,
 THOR_KERNEL(hmom, 6, COMMA int div COMMA int first, COMMA c.dt / div COMMA first)
-THOR_KERNEL(graddiv, 8, , )
-THOR_KERNEL(slow, 3, COMMA int from_t, COMMA from_t)
+THOR_KERNEL(slow, 4, COMMA int from_t, COMMA from_t)
 THOR_KERNEL(large0, 8, , )
 THOR_KERNEL(large1, 4, , )
 THOR_KERNEL(large2, 5, , )
@@ -642,10 +631,6 @@ void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool fir
     hipLaunchKernelGGL((k_vert<H, true>), dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c, div, (int)first);
   else
     hipLaunchKernelGGL((k_vert<H, false>), dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c, div, (int)first);
-}
-template <typename H>
-void launch_graddiv(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s) {
-  hipLaunchKernelGGL(k_graddiv<H>, dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c);
 }
 template <typename H>
 void launch_slow(const Fields<H> &f, const Consts &c, int wpb, bool from_t, hipStream_t s) {
@@ -695,16 +680,12 @@ void launch_batch(const Planet<H> *P, const int2 *tiles, int n_tiles, int wpb, i
     case BatchOp::VertLast:
       hipLaunchKernelGGL((kb_vert<H, true>), g, b, 0, s, P, tiles, parity, arg0, arg1);
       break;
-    case BatchOp::Graddiv:
-      hipLaunchKernelGGL(kb_graddiv<H>, g, b, 0, s, P, tiles, parity);
-      break;
   }
 }
 
 #define THOR_INSTANTIATE(H)                                                                          \
   template void launch_hmom<H>(const Fields<H> &, const Consts &, int, int, bool, hipStream_t);      \
   template void launch_vert<H>(const Fields<H> &, const Consts &, int, int, bool, bool, hipStream_t); \
-  template void launch_graddiv<H>(const Fields<H> &, const Consts &, int, hipStream_t);              \
   template void launch_slow<H>(const Fields<H> &, const Consts &, int, bool, hipStream_t);           \
   template void launch_large<H>(const Fields<H> &, const Consts &, int, hipStream_t);                \
   template void launch_diag_field<H>(const Fields<H> &, const Consts &, int, hipStream_t);           \

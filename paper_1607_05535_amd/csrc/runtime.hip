@@ -54,6 +54,8 @@ void carve(Carver &cv, Fields<H> &f, size_t N, size_t L) {
   f.dc = cv.take<H>(N * 21);
   f.lc = cv.take<H>(N * 6);
   f.rhat = cv.take<H>(N * 3);
+  f.ddi = cv.take<int32_t>(N * kRing2);
+  f.ddw = cv.take<H>(N * kRing2 * 3);
   f.area = cv.take<double>(N);
   f.teq = cv.take<double>(N);
   f.rho = cv.take<double>(NL);
@@ -83,13 +85,7 @@ void carve(Carver &cv, Fields<H> &f, size_t N, size_t L) {
   f.thL = cv.take<H>(NL);
   f.Gam = cv.take<H>(NL);
   f.D = cv.take<H>(NL);
-  f.Gx = cv.take<H>(NL);
-  f.Gy = cv.take<H>(NL);
-  f.Gz = cv.take<H>(NL);
   f.Dt = cv.take<H>(NL);
-  f.GDx = cv.take<H>(NL);
-  f.GDy = cv.take<H>(NL);
-  f.GDz = cv.take<H>(NL);
   f.T = cv.take<double>(NL);
   f.vx = cv.take<double>(NL);
   f.vy = cv.take<double>(NL);
@@ -196,6 +192,7 @@ int upload(thor_state *s, const Grid &G, const thor_planet *pl, const thor_verti
   std::vector<H> dc(G.div_coef.begin(), G.div_coef.end());
   std::vector<H> lc(G.lap_coef.begin(), G.lap_coef.end());
   std::vector<H> rh(N * 3);
+  std::vector<H> ddw(G.dd_w.begin(), G.dd_w.end());
   std::vector<double> teq(N);
   for (size_t i = 0; i < N; ++i) {
     const Vec3 p = G.pos[i];
@@ -229,6 +226,8 @@ int upload(thor_state *s, const Grid &G, const thor_planet *pl, const thor_verti
             hip_ok(hipMemcpyAsync((void *)f.dc, dc.data(), dc.size() * sizeof(H), hipMemcpyHostToDevice, st), "copy dc") &&
             hip_ok(hipMemcpyAsync((void *)f.lc, lc.data(), lc.size() * sizeof(H), hipMemcpyHostToDevice, st), "copy lc") &&
             hip_ok(hipMemcpyAsync((void *)f.rhat, rh.data(), rh.size() * sizeof(H), hipMemcpyHostToDevice, st), "copy rhat") &&
+            hip_ok(hipMemcpyAsync((void *)f.ddi, G.dd_idx.data(), G.dd_idx.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy ddi") &&
+            hip_ok(hipMemcpyAsync((void *)f.ddw, ddw.data(), ddw.size() * sizeof(H), hipMemcpyHostToDevice, st), "copy ddw") &&
             hip_ok(hipMemcpyAsync((void *)f.area, G.area.data(), N * sizeof(double), hipMemcpyHostToDevice, st), "copy area") &&
             hip_ok(hipMemcpyAsync((void *)f.teq, teq.data(), N * sizeof(double), hipMemcpyHostToDevice, st), "copy teq") &&
             hip_ok(hipMemcpyAsync(f.rho_t, rho.data(), NL * sizeof(double), hipMemcpyHostToDevice, st), "copy rho") &&
@@ -278,8 +277,6 @@ void enqueue_large_step(thor_state *s, const Fields<H> &f, int n, hipStream_t st
       const bool first = i == 0, last = stage == 2 && i + 1 == ns[stage];
       timed(s, st, "hmom", [&] { launch_hmom(f, c, it[FAM_HMOM], div[stage], first, st); });
       timed(s, st, "vert", [&] { launch_vert(f, c, it[FAM_VERT], div[stage], first, last, st); });
-      if (c.div_damp && i + 1 < ns[stage])
-        timed(s, st, "graddiv", [&] { launch_graddiv(f, c, it[FAM_GRADDIV], st); });
     }
   }
 }
@@ -531,10 +528,12 @@ int thor_autotune(thor_state *s, int n_acoustic, int *iters_out) {
       s->next_event = 0;
       enqueue(s, n_acoustic, s->parity, s->stream);
       s->parity ^= 1;
-      s->timed.clear();   // first step warms up; time the second
+      s->timed.clear();   // first step warms up; time the next two
       s->next_event = 0;
-      enqueue(s, n_acoustic, s->parity, s->stream);
-      s->parity ^= 1;
+      for (int r = 0; r < 2; ++r) {
+        enqueue(s, n_acoustic, s->parity, s->stream);
+        s->parity ^= 1;
+      }
       if (!hip_ok(hipStreamSynchronize(s->stream), "autotune synchronize")) return THOR_EHIP;
       int cnt = 0;
       double ms = family_mean(s, kFamily[fam], &cnt);
@@ -630,8 +629,8 @@ struct thor_batch {
   std::vector<size_t> member_bytes;
   void *tables = nullptr;          // device: Planet<H>[n], then FAM_COUNT tile tables
   size_t tile_cap = 0;             // entries reserved per tile table
-  int n_tiles[FAM_COUNT] = {0, 0, 0, 0, 0};
-  int wpb[FAM_COUNT] = {4, 4, 4, 4, 4};
+  int n_tiles[FAM_COUNT] = {0, 0, 0, 0};
+  int wpb[FAM_COUNT] = {4, 4, 4, 4};
   int parity = 0;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -698,7 +697,6 @@ void enqueue_batch_step(thor_batch *b, int n, int parity, hipStream_t st) {
       const bool first = i == 0, last = stage == 2 && i + 1 == ns[stage];
       L(FAM_HMOM, BatchOp::Hmom, div[stage], first);
       L(FAM_VERT, last ? BatchOp::VertLast : BatchOp::Vert, div[stage], first);
-      if (i + 1 < ns[stage]) L(FAM_GRADDIV, BatchOp::Graddiv, 0, 0);
     }
   }
 }
@@ -868,8 +866,10 @@ int thor_batch_autotune(thor_batch *b, int n_acoustic, int *wpb_out) {
       batch_enqueue(b, n_acoustic, b->parity, b->stream);   // warm-up
       batch_flip(b);
       (void)hipEventRecord(e0, b->stream);
-      batch_enqueue(b, n_acoustic, b->parity, b->stream);
-      batch_flip(b);
+      for (int r = 0; r < 2; ++r) {
+        batch_enqueue(b, n_acoustic, b->parity, b->stream);
+        batch_flip(b);
+      }
       (void)hipEventRecord(e1, b->stream);
       if (!hip_ok(hipEventSynchronize(e1), "autotune synchronize")) return THOR_EHIP;
       float ms = 0.f;

@@ -15,8 +15,8 @@ struct TimedLaunch {
 };
 
 // Kernel families with a tuned workgroup size (wavefronts per workgroup).
-enum { FAM_LARGE = 0, FAM_SLOW, FAM_HMOM, FAM_VERT, FAM_GRADDIV, FAM_COUNT };
-static const char *const kFamily[FAM_COUNT] = {"large", "slow", "hmom", "vert", "graddiv"};
+enum { FAM_LARGE = 0, FAM_SLOW, FAM_HMOM, FAM_VERT, FAM_COUNT };
+static const char *const kFamily[FAM_COUNT] = {"large", "slow", "hmom", "vert"};
 
 struct thor_state {
   int precision = THOR_FP64;
@@ -27,7 +27,7 @@ struct thor_state {
   thor::Fields<double> f64[2]{};
   thor::Fields<float> f32[2]{};
   int parity = 0;
-  int wpb[FAM_COUNT] = {4, 4, 4, 4, 4};
+  int wpb[FAM_COUNT] = {4, 4, 4, 4};
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
   std::map<int, hipGraphExec_t> graphs;   // key: n_acoustic * 2 + parity

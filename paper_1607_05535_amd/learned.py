@@ -68,13 +68,13 @@ class Pipeline:
         return C, F
 
     def norm(self, C, F):
+        """Means and spreads per (field, level) of the inputs and targets."""
         per = N_FIELDS * self.N * self.L
         a = thor.thor_field_stats(C, None, C.shape[0], per, self.N, self.L)
         b = thor.thor_field_stats(C, F, C.shape[0], per, self.N, self.L)
-        # a zero spread (a field without variation) is replaced by 1
-        a[5:] = np.where(a[5:] > 0, a[5:], 1.0)
-        b[5:] = np.where(b[5:] > 0, b[5:], 1.0)
-        return np.concatenate([a, b]).astype(np.float32)
+        for m in (a, b):   # a spread of zero (no variation) is replaced by 1
+            m[1] = np.where(m[1] > 0, m[1], 1.0)
+        return np.concatenate([a.reshape(-1), b.reshape(-1)]).astype(np.float32)
 
     def train(self, C, F, norm, steps, batch=4096, lr=1e-3, seed=0, log=None, hidden=256):
         net = thor.MLP(widths_for(self.L, hidden), max(batch, self.N), seed=seed, device=self.device)

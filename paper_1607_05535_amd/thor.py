@@ -21,7 +21,7 @@ FIELDS = {"T": 0, "u": 1, "v": 2, "w": 3, "p": 4, "rho": 5, "rhotheta": 6,
           "Mx": 7, "My": 8, "Mz": 9, "W": 10}
 
 EXPORTED = ["thor_last_error", "thor_grid_params_default", "thor_grid_build", "thor_grid_info",
-            "thor_grid_export", "thor_grid_coefficients", "thor_grid_free", "thor_state_bytes",
+            "thor_grid_export", "thor_grid_coefficients", "thor_grid_damping_coefficients", "thor_grid_free", "thor_state_bytes",
             "thor_state_init", "thor_step", "thor_diag", "thor_state_blob_bytes",
             "thor_state_import", "thor_set_timing", "thor_kernel_time", "thor_state_free",
             "thor_autotune", "thor_batch_bytes", "thor_batch_init", "thor_batch_step",
@@ -93,6 +93,7 @@ def lib():
     L.thor_grid_info.argtypes = [vp, i64p, ip, ip]
     L.thor_grid_export.argtypes = [vp, vp, vp, vp]
     L.thor_grid_coefficients.argtypes = [vp, vp, vp]
+    L.thor_grid_damping_coefficients.argtypes = [vp, vp, vp]
     L.thor_grid_free.argtypes = [vp]
     L.thor_grid_free.restype = None
     L.thor_state_bytes.argtypes = [vp, ctypes.POINTER(Vertical), ctypes.POINTER(Numerics),
@@ -243,9 +244,9 @@ def thor_kernel_time(sh, name):
 
 def thor_autotune(sh, n_acoustic):
     """Returns the chosen wavefronts per workgroup per kernel family."""
-    out = (ctypes.c_int * 5)()
+    out = (ctypes.c_int * 4)()
     _check(lib().thor_autotune(sh, n_acoustic, out))
-    return dict(zip(("large", "slow", "hmom", "vert", "graddiv"), list(out)))
+    return dict(zip(("large", "slow", "hmom", "vert"), list(out)))
 
 
 def thor_state_free(sh):
@@ -293,9 +294,9 @@ def thor_batch_member(bh, i):
 
 
 def thor_batch_autotune(bh, n_acoustic):
-    out = (ctypes.c_int * 5)()
+    out = (ctypes.c_int * 4)()
     _check(lib().thor_batch_autotune(bh, n_acoustic, out))
-    return dict(zip(("large", "slow", "hmom", "vert", "graddiv"), list(out)))
+    return dict(zip(("large", "slow", "hmom", "vert"), list(out)))
 
 
 def thor_batch_free(bh):
@@ -320,6 +321,12 @@ class Grid:
 
     def coefficients(self):
         return thor_grid_coefficients(self.handle, self.n)
+
+    def damping_coefficients(self):
+        idx = np.empty((self.n, 18), dtype=np.int32)
+        w = np.empty((self.n, 18, 3))
+        _check(lib().thor_grid_damping_coefficients(self.handle, idx.ctypes.data, w.ctypes.data))
+        return idx, w
 
     def __del__(self):
         try:
@@ -511,14 +518,21 @@ class MLP:
 # Restriction and corrector
 # ---------------------------------------------------------------------------
 class Restriction:
+    """device=None builds a host-only map (for inspection)."""
+
     def __init__(self, fine_grid, coarse_grid, device="cuda:0"):
         nbytes = ctypes.c_size_t()
         _check(lib().thor_restriction_bytes(fine_grid.handle, coarse_grid.handle, ctypes.byref(nbytes)))
-        self.buf = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
         self.n_fine = fine_grid.n
         h = ctypes.c_void_p()
-        _check(lib().thor_restriction_build(fine_grid.handle, coarse_grid.handle, self.buf.data_ptr(), nbytes.value,
-                                            torch.cuda.current_stream(self.buf.device).cuda_stream, ctypes.byref(h)))
+        if device is None:
+            self.buf = None
+            _check(lib().thor_restriction_build(fine_grid.handle, coarse_grid.handle, None, 0, None, ctypes.byref(h)))
+        else:
+            self.buf = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+            _check(lib().thor_restriction_build(fine_grid.handle, coarse_grid.handle, self.buf.data_ptr(),
+                                                nbytes.value, torch.cuda.current_stream(self.buf.device).cuda_stream,
+                                                ctypes.byref(h)))
         self.handle = h
 
     def coarse_of_fine(self):
@@ -544,13 +558,14 @@ def thor_state_fields32(state, out):
 
 
 def thor_field_stats(C, Fn, n_arrays, stride, n_col, n_lev):
-    scratch = torch.empty(n_arrays * 640, dtype=torch.float64, device=C.device)
-    out = np.empty(10)
+    """Means and spreads per (field, level): array [2, 5, n_lev]."""
+    scratch = torch.empty(n_arrays * 320 * n_lev, dtype=torch.float64, device=C.device)
+    out = np.empty(10 * n_lev)
     _check(lib().thor_field_stats(C.data_ptr(), Fn.data_ptr() if Fn is not None else None, n_arrays, stride,
                                   n_col, n_lev, scratch.data_ptr(), scratch.numel() * 8,
                                   torch.cuda.current_stream(C.device).cuda_stream,
                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-    return out
+    return out.reshape(2, 5, n_lev)
 
 
 class Corrector:
@@ -560,7 +575,7 @@ class Corrector:
         self.buf = torch.empty(nbytes.value, dtype=torch.uint8, device=state.buf.device)
         self.state, self.net = state, net
         norm = np.ascontiguousarray(norm, dtype=np.float32)
-        assert norm.size == 20
+        assert norm.size == 20 * state.n_lev
         h = ctypes.c_void_p()
         _check(lib().thor_corrector_init(state.handle, net.handle, norm.ctypes.data, bound, self.buf.data_ptr(),
                                          nbytes.value, ctypes.byref(h)))

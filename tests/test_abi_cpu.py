@@ -121,3 +121,39 @@ def test_state_bytes_and_config_errors():
     with pytest.raises(thor.ThorError) as e:
         thor.thor_state_init(G.handle, planet, v, num, forcing, init, addr, 512, 0)
     assert e.value.code == thor.THOR_ENOMEM
+
+
+@pytest.mark.parametrize("g,smooth", [(3, True), (4, False)])
+def test_two_ring_damping_stencil_equals_lap_of_grad(g, smooth):
+    """The folded divergence-damping stencil reproduces the oracle's
+    lap(grad D) per Cartesian component (Sec. 4 operator order)."""
+    thor = _thor()
+    G = thor.Grid(g, smooth=smooth)
+    O = oracle_grid(g, smooth=smooth)
+    idx, w = G.damping_coefficients()
+    D = np.random.default_rng(4).normal(size=G.n)
+    nb = np.where(idx >= 0, idx, np.arange(G.n)[:, None])
+    got = np.einsum("imk,im->ik", w, D[nb] - D[:, None])
+    gd = op.grad(O, D)
+    ref = np.stack([op.lap(O, gd[:, q]) for q in range(3)], axis=1)
+    assert np.abs(got - ref).max() < 1e-10 * np.abs(ref).max()
+    assert np.all(w[idx < 0] == 0)
+    ring = (idx >= 0).sum(1)
+    assert ring.max() == 18 and ring.min() >= 14
+
+
+def test_restriction_map_is_nearest_point():
+    """Every fine column goes to the coarse column with the largest dot
+    product (up to rounding of near-ties); every coarse column gets some."""
+    thor = _thor()
+    fg, cg = thor.Grid(4), thor.Grid(2)
+    r = thor.Restriction(fg, cg, device=None)
+    m = r.coarse_of_fine()
+    _, xf, _ = fg.export()
+    _, xc, _ = cg.export()
+    dots = xf @ xc.T
+    best = dots.max(axis=1)
+    assert np.all(dots[np.arange(fg.n), m] >= best - 1e-14)
+    assert len(np.unique(m)) == cg.n
+    ties = np.sum(m != np.argmax(dots, axis=1))
+    assert ties < 0.01 * fg.n

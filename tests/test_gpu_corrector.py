@@ -10,19 +10,6 @@ from tests.gpu_util import say
 pytestmark = pytest.mark.gpu
 
 
-def test_restriction_map_is_nearest_point():
-    from paper_1607_05535_amd import thor
-    fg, cg = thor.Grid(4), thor.Grid(2)
-    r = thor.Restriction(fg, cg)
-    m = r.coarse_of_fine()
-    _, xf, _ = fg.export()
-    _, xc, _ = cg.export()
-    dots = xf @ xc.T
-    ref = np.argmax(dots, axis=1)
-    assert np.array_equal(m, ref)
-    assert len(np.unique(m)) == cg.n
-
-
 def test_restriction_of_a_uniform_rest_state():
     """Every fine column of a resting isothermal state is the same column:
     the restriction reproduces it on the coarse grid, whatever was there."""
