@@ -358,7 +358,12 @@ int thor_field_stats(const float *C, const float *Fn, int n_arrays, size_t strid
  * [4][5][n_lev]: input means and spreads per (field, level), then those of
  * the targets (fine - coarse).
  * A column is corrected only while every normalised output stays within
- * `bound` (else it keeps the plain coarse state). */
+ * `bound` and the corrected T and p stay positive (else it keeps the plain
+ * coarse state).  A corrected cell is rebuilt the way the restriction builds
+ * one: rho' = p' / (Rd T'), rho theta from p', M = rho' (v + du e + dv n)
+ * with e, n the east and north unit vectors, and W rescaled to the new
+ * interface density plus the interface mean of rho' dw.  The correction
+ * therefore changes the mass like the restriction does. */
 int thor_corrector_bytes(const thor_state *s, size_t *bytes);
 int thor_corrector_init(thor_state *s, thor_mlp *net, const float *norm_host, float bound,
                         void *dev_buf, size_t dev_bytes, thor_corrector **out);

@@ -12,7 +12,10 @@ LIB = os.path.join(HERE, "libthor.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
-HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+# -ffp-contract=on: a multiply and an add are fused only inside one source
+# expression, so every kernel that runs the same device code (a planet alone
+# or inside an ensemble) rounds identically whatever code surrounds it.
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=on",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 SOURCES = ["grid.cpp", "kernels.hip", "runtime.hip", "mlp.hip", "corrector.hip"]

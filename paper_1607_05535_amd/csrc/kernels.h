@@ -1,11 +1,10 @@
 // Device data layout and kernel launchers of the HEVI step (gfx950).
 //
 // Every field is stored [col][lev] with the levels of one column contiguous.
-// A wavefront of 64 lanes covers cpw = floor(64 / L) whole columns, lane =
-// col_in_wave * L + lev, so a neighbour gather reads one contiguous run of
-// L values and the vertical solve of a column stays inside one wavefront.
 // Interface fields (W) use the same layout: slot j holds interface j
 // (0 = ground, always 0); the lid value (j = L) is 0 and not stored.
+// Launch geometry: see n_blocks (lanes = levels, cpw columns per wavefront)
+// and n_blocks_h (kHq levels per lane, hcpw columns per wavefront).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -60,6 +59,7 @@ struct Fields {
 
 struct Consts {
   int N, L, cpw;          // columns, levels, columns per wavefront
+  int hlpc, hcpw;         // phase-M mapping: lanes per column, columns per wavefront
   double radius, omega, grav, Rd, Cp, Cv, gamma, p_ref;
   double dz, Kd;
   double dt;
@@ -74,11 +74,21 @@ constexpr int kXcds = 8;   // MI355X: 8 accelerator complex dies, one L2 each
 
 // Launched workgroups of `wpb` wavefronts (a multiple of kXcds; surplus
 // workgroups store nothing).
-inline int n_blocks(const Consts &c, int wpb) {
-  long waves = (c.N + c.cpw - 1) / c.cpw;
+inline int n_blocks_for(long n_col, int cols_per_wave, int wpb) {
+  long waves = (n_col + cols_per_wave - 1) / cols_per_wave;
   long wg = (waves + wpb - 1) / wpb;
   return (int)((wg + kXcds - 1) / kXcds * kXcds);
 }
+inline int n_blocks(const Consts &c, int wpb) { return n_blocks_for(c.N, c.cpw, wpb); }
+
+// Kernels dominated by horizontal gathers (acoustic phase M, slow terms) use
+// a second mapping: each lane owns kHq consecutive levels of one column,
+// hlpc = ceil(L / kHq) lanes per column and hcpw = floor(64 / hlpc) columns
+// per wavefront.  Per-column stencil weights are then loaded once per kHq
+// cells, rows move in 16-byte loads, and a vertical neighbour is a register
+// or, across a lane boundary, one shuffle.
+constexpr int kHq = 4;
+inline int n_blocks_h(const Consts &c, int wpb) { return n_blocks_for(c.N, c.hcpw, wpb); }
 
 // Launchers.  `wpb` = wavefronts per workgroup (tuned per kernel family).
 // The prognostic state between large steps lives in the *_t buffers; a large

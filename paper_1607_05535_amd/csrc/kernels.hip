@@ -2,14 +2,21 @@
 //
 // Paper: Mendonca et al. 2016 (arXiv:1607.05535), Sec. 2-5.
 //
-// Work mapping (all kernels): a 256-thread block is 4 wavefronts; wavefront
-// w covers columns [w * cpw, w * cpw + cpw) with lane = (col - w cpw) * L + lev.
-// Column data is contiguous in memory, so every neighbour gather is one
-// coalesced run of L values per column, and the lanes of one column can
-// exchange vertical neighbours with cross-lane shuffles.  The vertical
-// implicit system of a column is solved entirely in registers by cyclic
-// reduction across those lanes (ceil(log2 L) shuffle rounds), which is an
-// exact direct solver of the same tridiagonal the Thomas algorithm solves.
+// Work mappings.  Column data is contiguous in memory ([col][lev]).
+//  * Gather kernels (acoustic phase M, the gather half of phase V, slow
+//    terms, per-large-step terms): a lane owns kHq = 4 consecutive levels of
+//    one column, ceil(L / 4) lanes per column.  A neighbour row is read with
+//    16-byte loads, per-column stencil weights are loaded once per 4 cells,
+//    and a vertical neighbour is a register or, across a lane boundary, one
+//    cross-lane shuffle.
+//  * Vertical solve (phase V): a wavefront covers cpw = floor(64 / L) whole
+//    columns with lane = (col - first col) * L + lev, so the implicit system
+//    of a column is solved in registers by cyclic reduction across its lanes
+//    (ceil(log2 L) shuffle rounds), an exact direct solver of the same
+//    tridiagonal the Thomas algorithm solves.  Its horizontal divergences
+//    are gathered with the same mapping: staging them through LDS from the
+//    gather mapping leaves 4x fewer wavefronts, each solving 4 column groups
+//    in turn, and measured slower.
 //
 // Horizontal stencils use folded coefficients built on the host:
 //   div F = (1/r) sum_{j=0..6} c_j . F_j                   (Eqs. flx_div, int_grid, div_gauss)
@@ -22,6 +29,11 @@
 
 #include "internal.h"
 #include "kernels.h"
+
+// Wavefronts per SIMD that the phase-M kernel is compiled for (register cap
+// 512 / n): its two-ring gathers need many loads in flight per wavefront.
+#define HMOM_OCC_D 2
+#define HMOM_OCC_F 4
 
 namespace thor {
 namespace {
@@ -77,84 +89,187 @@ __device__ __forceinline__ void load_nbr(const int32_t *nbr, int col, int nb[6])
   }
 }
 
-// (1/r) sum_j c_j (s_j - s_0): Eq. grad with folded coefficients.
-template <typename H>
-__device__ __forceinline__ void grad_at(const H *s, const int nb[6], const H *dc, int L, int lev,
-                                        size_t idx, H ir, H &gx, H &gy, H &gz) {
-  H s0 = s[idx];
-  H x = 0, y = 0, z = 0;
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    H d = s[(size_t)nb[j] * L + lev] - s0;
-    x += dc[3 * (j + 1) + 0] * d;
-    y += dc[3 * (j + 1) + 1] * d;
-    z += dc[3 * (j + 1) + 2] * d;
-  }
-  gx = x * ir;
-  gy = y * ir;
-  gz = z * ir;
-}
-
-// sum_j l_j (s_j - s_0): the Laplacian without its 1/r^2.
-template <typename T, typename H>
-__device__ __forceinline__ T lap_at(const T *s, const int nb[6], const H *lc, int L, int lev, size_t idx) {
-  T s0 = s[idx];
-  T acc = 0;
-#pragma unroll
-  for (int j = 0; j < 6; ++j) acc += (T)lc[j] * (s[(size_t)nb[j] * L + lev] - s0);
-  return acc;
-}
-
 // ---------------------------------------------------------------------------
 // Acoustic phase H: explicit horizontal momentum (Eq. mom2) with the
 // deviation-pressure gradient, slow forcing and divergence damping, then the
 // horizontal projection (Eq. proj_h).
 // ---------------------------------------------------------------------------
-template <typename H>
-__device__ __forceinline__ void b_hmom(const Fields<H> &f, const Consts &c, const Lane &ln, double dtau, int first) {
-  if (!ln.store) return;
-  const int L = c.L, lev = ln.lev, col = ln.col;
-  const size_t idx = (size_t)col * L + lev;
+// Lane of the phase-M mapping: kHq consecutive levels [lev0, lev0 + nv) of
+// one column.
+struct HLane {
+  int col, lev0, nv;
+  bool store;
+};
+
+__device__ __forceinline__ HLane map_hlane(const Consts &c, int lb) {
+  HLane r;
+  const int lane = threadIdx.x & 63;
+  const int wave = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int cw = lane / c.hlpc;
+  const int sub = lane - cw * c.hlpc;
+  const int col = wave * c.hcpw + cw;
+  r.lev0 = sub * kHq;
+  r.nv = min(kHq, c.L - r.lev0);
+  r.store = cw < c.hcpw && col < c.N && r.nv > 0;
+  r.col = col < c.N ? col : c.N - 1;
+  return r;
+}
+
+// kHq consecutive values starting at p.  VEC: p is 16-byte aligned and all
+// kHq are valid (L a multiple of kHq); else only the first nv are read.
+template <bool VEC>
+__device__ __forceinline__ void ld4(const double *p, int nv, double v[kHq]) {
+  if (VEC) {
+    const double2 a = *reinterpret_cast<const double2 *>(p);
+    const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  } else {
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) v[q] = q < nv ? p[q] : 0.0;
+  }
+}
+template <bool VEC>
+__device__ __forceinline__ void ld4(const float *p, int nv, float v[kHq]) {
+  if (VEC) {
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  } else {
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) v[q] = q < nv ? p[q] : 0.0f;
+  }
+}
+template <bool VEC>
+__device__ __forceinline__ void st4(double *p, int nv, const double v[kHq]) {
+  if (VEC) {
+    *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < kHq; ++q)
+      if (q < nv) p[q] = v[q];
+  }
+}
+template <bool VEC>
+__device__ __forceinline__ void st4(float *p, int nv, const float v[kHq]) {
+  if (VEC) {
+    *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < kHq; ++q)
+      if (q < nv) p[q] = v[q];
+  }
+}
+
+template <typename H, bool VEC>
+__device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, const HLane &ln, double dtau,
+                                           int first) {
+  const int L = c.L, col = ln.col, nv = ln.nv;
+  const size_t idx = (size_t)col * L + ln.lev0;
   int nb[6];
   load_nbr(f.nbr, col, nb);
   const H *dc = f.dc + (size_t)col * 21;
-  const H r = (H)radius_c(c, lev);
-  const H ir = (H)1 / r;
-  H gx = 0, gy = 0, gz = 0;
-  if (!first) grad_at(f.ps, nb, dc, L, lev, idx, ir, gx, gy, gz);
-  H ddx = 0, ddy = 0, ddz = 0;
+  H ir[kHq];
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) ir[q] = (H)1 / (H)radius_c(c, ln.lev0 + q);
+  H gx[kHq], gy[kHq], gz[kHq];
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) gx[q] = gy[q] = gz[q] = 0;
+  if (!first) {
+    // (1/r) sum_j c_j (p*_j - p*_0)
+    H s0[kHq];
+    ld4<VEC>(f.ps + idx, nv, s0);
+#pragma unroll 2
+    for (int j = 0; j < 6; ++j) {
+      H sj[kHq];
+      ld4<VEC>(f.ps + (size_t)nb[j] * L + ln.lev0, nv, sj);
+      const H cx = dc[3 * (j + 1)], cy = dc[3 * (j + 1) + 1], cz = dc[3 * (j + 1) + 2];
+#pragma unroll
+      for (int q = 0; q < kHq; ++q) {
+        const H d = sj[q] - s0[q];
+        gx[q] += cx * d;
+        gy[q] += cy * d;
+        gz[q] += cz * d;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      gx[q] *= ir[q];
+      gy[q] *= ir[q];
+      gz[q] *= ir[q];
+    }
+  }
+  H ddx[kHq], ddy[kHq], ddz[kHq];
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) ddx[q] = ddy[q] = ddz[q] = 0;
   if (c.div_damp) {
     // -Kd lap(grad D) over the two-ring, D of the current small-step state
     const H *D = first ? f.Dt : f.D;
     const int32_t *di = f.ddi + (size_t)col * kRing2;
     const H *dw = f.ddw + (size_t)col * kRing2 * 3;
-    const H d0 = D[idx];
+    // all ring ids first, so that the row loads below are independent
+    int ring[kRing2];
+#pragma unroll
+    for (int m = 0; m < kRing2; ++m) {
+      const int v = di[m];
+      ring[m] = v < 0 ? col : v;
+    }
+    H d0[kHq];
+    ld4<VEC>(D + idx, nv, d0);
 #pragma unroll 6
     for (int m = 0; m < kRing2; ++m) {
-      const int cm = di[m] < 0 ? col : di[m];
-      const H dd = D[(size_t)cm * L + lev] - d0;
-      ddx += dw[3 * m] * dd;
-      ddy += dw[3 * m + 1] * dd;
-      ddz += dw[3 * m + 2] * dd;
+      const int cm = ring[m];
+      H dm[kHq];
+      ld4<VEC>(D + (size_t)cm * L + ln.lev0, nv, dm);
+      const H wx = dw[3 * m], wy = dw[3 * m + 1], wz = dw[3 * m + 2];
+#pragma unroll
+      for (int q = 0; q < kHq; ++q) {
+        const H dd = dm[q] - d0[q];
+        ddx[q] += wx * dd;
+        ddy[q] += wy * dd;
+        ddz[q] += wz * dd;
+      }
     }
-    const H s = (H)(-c.Kd) * ir * ir * ir;
-    ddx *= s;
-    ddy *= s;
-    ddz *= s;
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const H s = (H)(-c.Kd) * ir[q] * ir[q] * ir[q];
+      ddx[q] *= s;
+      ddy[q] *= s;
+      ddz[q] *= s;
+    }
   }
-  const H *Mx = first ? f.Mx_t : f.Mx;
-  const H *My = first ? f.My_t : f.My;
-  const H *Mz = first ? f.Mz_t : f.Mz;
-  const H dt = (H)dtau;
-  H mx = Mx[idx] + dt * (-gx + f.SMx[idx] + ddx);
-  H my = My[idx] + dt * (-gy + f.SMy[idx] + ddy);
-  H mz = Mz[idx] + dt * (-gz + f.SMz[idx] + ddz);
   const H *rh = f.rhat + (size_t)col * 3;
   const H rx = rh[0], ry = rh[1], rz = rh[2];
-  const H mr = mx * rx + my * ry + mz * rz;
-  f.Mx[idx] = mx - mr * rx;
-  f.My[idx] = my - mr * ry;
-  f.Mz[idx] = mz - mr * rz;
+  const H dt = (H)dtau;
+  H mx[kHq], my[kHq], mz[kHq], sx[kHq], sy[kHq], sz[kHq];
+  ld4<VEC>((first ? f.Mx_t : f.Mx) + idx, nv, mx);
+  ld4<VEC>((first ? f.My_t : f.My) + idx, nv, my);
+  ld4<VEC>((first ? f.Mz_t : f.Mz) + idx, nv, mz);
+  ld4<VEC>(f.SMx + idx, nv, sx);
+  ld4<VEC>(f.SMy + idx, nv, sy);
+  ld4<VEC>(f.SMz + idx, nv, sz);
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) {
+    const H ax = mx[q] + dt * (-gx[q] + sx[q] + ddx[q]);
+    const H ay = my[q] + dt * (-gy[q] + sy[q] + ddy[q]);
+    const H az = mz[q] + dt * (-gz[q] + sz[q] + ddz[q]);
+    const H mr = ax * rx + ay * ry + az * rz;
+    mx[q] = ax - mr * rx;
+    my[q] = ay - mr * ry;
+    mz[q] = az - mr * rz;
+  }
+  st4<VEC>(f.Mx + idx, nv, mx);
+  st4<VEC>(f.My + idx, nv, my);
+  st4<VEC>(f.Mz + idx, nv, mz);
+}
+
+template <typename H>
+__device__ __forceinline__ void b_hmom(const Fields<H> &f, const Consts &c, const HLane &ln, double dtau,
+                                       int first) {
+  if (!ln.store) return;
+  if ((c.L % kHq) == 0)
+    hmom_cells<H, true>(f, c, ln, dtau, first);
+  else
+    hmom_cells<H, false>(f, c, ln, dtau, first);
 }
 
 // ---------------------------------------------------------------------------
@@ -280,12 +395,13 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
 // full Cartesian momentum, Coriolis, projections (Eqs. mom, proj_h, proj_r),
 // and the linearisation coefficients theta_L and gamma p / (rho theta).
 // ---------------------------------------------------------------------------
-template <typename H>
-__device__ __forceinline__ void b_slow(const Fields<H> &f, const Consts &c, const Lane &ln, int from_t) {
-  const int L = c.L, lev = ln.lev, col = ln.col;
-  const size_t idx = (size_t)col * L + lev;
-  const int lm = ln.lane > 0 ? ln.lane - 1 : 0;
-  const int lp = ln.lane < 63 ? ln.lane + 1 : 63;
+template <typename H, bool VEC>
+__device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, const HLane &ln, int from_t) {
+  const int L = c.L, col = ln.col, nv = ln.nv, lev0 = ln.lev0;
+  const int lane = threadIdx.x & 63;
+  const int lm = lane > 0 ? lane - 1 : 0;
+  const int lp = lane < 63 ? lane + 1 : 63;
+  const size_t idx = (size_t)col * L + lev0;
   const double *rho = from_t ? f.rho_t : f.rho;
   const double *rth = from_t ? f.rth_t : f.rth;
   const double *W = from_t ? f.W_t : f.W;
@@ -299,73 +415,139 @@ __device__ __forceinline__ void b_slow(const Fields<H> &f, const Consts &c, cons
   const H rx = rh[0], ry = rh[1], rz = rh[2];
 
   // own column: full momentum m = M + Wbar rhat and velocity m / rho
-  const double Wk = lev == 0 ? 0.0 : W[idx];
-  double Wk1 = shfl(Wk, lp);
-  if (lev == L - 1) Wk1 = 0.0;
-  const H wbar = (H)(0.5 * (Wk + Wk1));
-  const H rho0 = (H)rho[idx];
-  const H mx0 = Mx[idx], my0 = My[idx], mz0 = Mz[idx];
-  const H fx = mx0 + wbar * rx, fy = my0 + wbar * ry, fz = mz0 + wbar * rz;
-  const H irho0 = (H)1 / rho0;
-  const H vx0 = fx * irho0, vy0 = fy * irho0, vz0 = fz * irho0;
-  // horizontal flux divergence of v_q M
-  H Ax, Ay, Az;
+  double Wk[kHq], rho0[kHq];
+  H fx[kHq], fy[kHq], fz[kHq], vx0[kHq], vy0[kHq], vz0[kHq];
+  H Ax[kHq], Ay[kHq], Az[kHq];
   {
-    H t = dc[0] * mx0 + dc[1] * my0 + dc[2] * mz0;
-    Ax = vx0 * t;
-    Ay = vy0 * t;
-    Az = vz0 * t;
+    ld4<VEC>(W + idx, nv, Wk);
+    if (lev0 == 0) Wk[0] = 0.0;
+    const double Wn = shfl(Wk[0], lp);   // interface lev0 + kHq: first value of the next lane
+    ld4<VEC>(rho + idx, nv, rho0);
+    H mx0[kHq], my0[kHq], mz0[kHq];
+    ld4<VEC>(Mx + idx, nv, mx0);
+    ld4<VEC>(My + idx, nv, my0);
+    ld4<VEC>(Mz + idx, nv, mz0);
+    const H d0x = dc[0], d0y = dc[1], d0z = dc[2];
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const double up = lev0 + q == L - 1 ? 0.0 : (q + 1 < kHq ? Wk[q + 1] : Wn);
+      const H wbar = (H)(0.5 * (Wk[q] + up));
+      fx[q] = mx0[q] + wbar * rx;
+      fy[q] = my0[q] + wbar * ry;
+      fz[q] = mz0[q] + wbar * rz;
+      const H irho0 = (H)1 / (H)rho0[q];
+      vx0[q] = fx[q] * irho0;
+      vy0[q] = fy[q] * irho0;
+      vz0[q] = fz[q] * irho0;
+      // horizontal flux divergence of v_q M: own-column term
+      const H t = d0x * mx0[q] + d0y * my0[q] + d0z * mz0[q];
+      Ax[q] = vx0[q] * t;
+      Ay[q] = vy0[q] * t;
+      Az[q] = vz0[q] * t;
+    }
   }
-#pragma unroll 2
+#pragma unroll 1
   for (int j = 0; j < 6; ++j) {
-    const size_t nj = (size_t)nb[j] * L + lev;
-    const double wn = lev == 0 ? 0.0 : W[nj];
-    double wn1 = shfl(wn, lp);
-    if (lev == L - 1) wn1 = 0.0;
-    const H wb = (H)(0.5 * (wn + wn1));
+    const size_t nj = (size_t)nb[j] * L + lev0;
+    double wn[kHq], rj[kHq];
+    H mxj[kHq], myj[kHq], mzj[kHq];
+    ld4<VEC>(W + nj, nv, wn);
+    if (lev0 == 0) wn[0] = 0.0;
+    const double wnn = shfl(wn[0], lp);
+    ld4<VEC>(rho + nj, nv, rj);
+    ld4<VEC>(Mx + nj, nv, mxj);
+    ld4<VEC>(My + nj, nv, myj);
+    ld4<VEC>(Mz + nj, nv, mzj);
     const H *rn = f.rhat + (size_t)nb[j] * 3;
-    const H mxj = Mx[nj], myj = My[nj], mzj = Mz[nj];
-    const H t = (dc[3 * (j + 1)] * mxj + dc[3 * (j + 1) + 1] * myj + dc[3 * (j + 1) + 2] * mzj) /
-                (H)rho[nj];
-    Ax += (mxj + wb * rn[0]) * t;
-    Ay += (myj + wb * rn[1]) * t;
-    Az += (mzj + wb * rn[2]) * t;
+    const H rnx = rn[0], rny = rn[1], rnz = rn[2];
+    const H cx = dc[3 * (j + 1)], cy = dc[3 * (j + 1) + 1], cz = dc[3 * (j + 1) + 2];
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const double up = lev0 + q == L - 1 ? 0.0 : (q + 1 < kHq ? wn[q + 1] : wnn);
+      const H wb = (H)(0.5 * (wn[q] + up));
+      const H t = (cx * mxj[q] + cy * myj[q] + cz * mzj[q]) / (H)rj[q];
+      Ax[q] += (mxj[q] + wb * rnx) * t;
+      Ay[q] += (myj[q] + wb * rny) * t;
+      Az[q] += (mzj[q] + wb * rnz) * t;
+    }
   }
-  const H rC = (H)radius_c(c, lev);
-  Ax /= rC;
-  Ay /= rC;
-  Az /= rC;
   // vertical flux divergence: r^2 W v_q at the interfaces
+  H Fx[kHq], Fy[kHq], Fz[kHq];
   {
-    const H rI = (H)radius_i(c, lev);
-    const H w2 = (H)Wk * rI * rI * (H)0.5;
-    const H vxm = shfl(vx0, lm), vym = shfl(vy0, lm), vzm = shfl(vz0, lm);
-    const H Fx = lev == 0 ? (H)0 : w2 * (vxm + vx0);
-    const H Fy = lev == 0 ? (H)0 : w2 * (vym + vy0);
-    const H Fz = lev == 0 ? (H)0 : w2 * (vzm + vz0);
-    H Fx1 = shfl(Fx, lp), Fy1 = shfl(Fy, lp), Fz1 = shfl(Fz, lp);
-    if (lev == L - 1) Fx1 = Fy1 = Fz1 = 0;
-    const H s = (H)1 / (rC * rC * (H)c.dz);
-    Ax += (Fx1 - Fx) * s;
-    Ay += (Fy1 - Fy) * s;
-    Az += (Fz1 - Fz) * s;
+    const H vxm = shfl(vx0[kHq - 1], lm), vym = shfl(vy0[kHq - 1], lm), vzm = shfl(vz0[kHq - 1], lm);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const int lev = lev0 + q;
+      const H rI = (H)radius_i(c, lev);
+      const H w2 = (H)Wk[q] * rI * rI * (H)0.5;
+      const H px = q ? vx0[q - 1] : vxm, py = q ? vy0[q - 1] : vym, pz = q ? vz0[q - 1] : vzm;
+      Fx[q] = lev == 0 ? (H)0 : w2 * (px + vx0[q]);
+      Fy[q] = lev == 0 ? (H)0 : w2 * (py + vy0[q]);
+      Fz[q] = lev == 0 ? (H)0 : w2 * (pz + vz0[q]);
+    }
   }
-  // Coriolis 2 Omega zhat x m
-  const H om2 = (H)(2.0 * c.omega);
-  const H ACx = Ax - om2 * fy, ACy = Ay + om2 * fx, ACz = Az;
-  const H acr = ACx * rx + ACy * ry + ACz * rz;
-  const H acr_m = shfl(acr, lm);
-  // linearisation coefficients
-  const double rth0 = rth[idx];
-  const double p0 = f.p_t[idx] + (from_t ? 0.0 : (double)f.ps[idx]);
-  if (ln.store) {
-    f.SMx[idx] = f.FMx[idx] - (ACx - acr * rx);
-    f.SMy[idx] = f.FMy[idx] - (ACy - acr * ry);
-    f.SMz[idx] = f.FMz[idx] - (ACz - acr * rz);
-    f.SW[idx] = lev == 0 ? 0.0 : f.FW[idx] - 0.5 * ((double)acr_m + (double)acr);
-    f.thL[idx] = (H)(rth0 / (double)rho[idx]);
-    f.Gam[idx] = (H)(c.gamma * p0 / rth0);
+  H acr[kHq];
+  {
+    const H nx = shfl(Fx[0], lp), ny = shfl(Fy[0], lp), nz = shfl(Fz[0], lp);
+    const H om2 = (H)(2.0 * c.omega);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const int lev = lev0 + q;
+      const H rC = (H)radius_c(c, lev);
+      H Fx1 = q + 1 < kHq ? Fx[q + 1] : nx, Fy1 = q + 1 < kHq ? Fy[q + 1] : ny,
+        Fz1 = q + 1 < kHq ? Fz[q + 1] : nz;
+      if (lev == L - 1) Fx1 = Fy1 = Fz1 = 0;
+      Ax[q] /= rC;
+      Ay[q] /= rC;
+      Az[q] /= rC;
+      const H s = (H)1 / (rC * rC * (H)c.dz);
+      Ax[q] += (Fx1 - Fx[q]) * s;
+      Ay[q] += (Fy1 - Fy[q]) * s;
+      Az[q] += (Fz1 - Fz[q]) * s;
+      // Coriolis 2 Omega zhat x m
+      Ax[q] -= om2 * fy[q];
+      Ay[q] += om2 * fx[q];
+      acr[q] = Ax[q] * rx + Ay[q] * ry + Az[q] * rz;
+    }
   }
+  const H acr_m = shfl(acr[kHq - 1], lm);
+  if (!ln.store) return;
+  H smx[kHq], smy[kHq], smz[kHq], thl[kHq], gam[kHq];
+  double sw[kHq], fw[kHq], rth0[kHq], pt[kHq];
+  H ps[kHq];
+  ld4<VEC>(f.FMx + idx, nv, smx);
+  ld4<VEC>(f.FMy + idx, nv, smy);
+  ld4<VEC>(f.FMz + idx, nv, smz);
+  ld4<VEC>(f.FW + idx, nv, fw);
+  ld4<VEC>(rth + idx, nv, rth0);
+  ld4<VEC>(f.p_t + idx, nv, pt);
+  if (!from_t) ld4<VEC>(f.ps + idx, nv, ps);
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) {
+    smx[q] -= Ax[q] - acr[q] * rx;
+    smy[q] -= Ay[q] - acr[q] * ry;
+    smz[q] -= Az[q] - acr[q] * rz;
+    const H am = q ? acr[q - 1] : acr_m;
+    sw[q] = lev0 + q == 0 ? 0.0 : fw[q] - 0.5 * ((double)am + (double)acr[q]);
+    // linearisation coefficients
+    const double p0 = pt[q] + (from_t ? 0.0 : (double)ps[q]);
+    thl[q] = (H)(rth0[q] / rho0[q]);
+    gam[q] = (H)(c.gamma * p0 / rth0[q]);
+  }
+  st4<VEC>(f.SMx + idx, nv, smx);
+  st4<VEC>(f.SMy + idx, nv, smy);
+  st4<VEC>(f.SMz + idx, nv, smz);
+  st4<VEC>(f.SW + idx, nv, sw);
+  st4<VEC>(f.thL + idx, nv, thl);
+  st4<VEC>(f.Gam + idx, nv, gam);
+}
+
+template <typename H>
+__device__ __forceinline__ void b_slow(const Fields<H> &f, const Consts &c, const HLane &ln, int from_t) {
+  if ((c.L % kHq) == 0)
+    slow_cells<H, true>(f, c, ln, from_t);
+  else
+    slow_cells<H, false>(f, c, ln, from_t);
 }
 
 // ---------------------------------------------------------------------------
@@ -374,110 +556,263 @@ __device__ __forceinline__ void b_slow(const Fields<H> &f, const Consts &c, cons
 // grad p[t], the [t] vertical imbalance and the divergence-damping terms of
 // Phi[t].
 // ---------------------------------------------------------------------------
-template <typename H>
-__device__ __forceinline__ void b_large0(const Fields<H> &f, const Consts &c, const Lane &ln) {
-  const int L = c.L, lev = ln.lev, col = ln.col;
-  const size_t idx = (size_t)col * L + lev;
-  const int lm = ln.lane > 0 ? ln.lane - 1 : 0;
-  const double rho = f.rho_t[idx], rth = f.rth_t[idx];
-  const double W = lev == 0 ? 0.0 : f.W_t[idx];
-  const double rho_m = shfl(rho, lm);
-  const double p = c.p_ref * pow(c.Rd * rth / c.p_ref, c.gamma);
+template <typename H, bool VEC>
+__device__ __forceinline__ void large0_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
+  const int L = c.L, lev0 = ln.lev0, nv = ln.nv;
+  const size_t idx = (size_t)ln.col * L + lev0;
+  const int lane = threadIdx.x & 63;
+  const int lm = lane > 0 ? lane - 1 : 0;
+  double rho[kHq], rth[kHq], W[kHq];
+  ld4<VEC>(f.rho_t + idx, nv, rho);
+  ld4<VEC>(f.rth_t + idx, nv, rth);
+  ld4<VEC>(f.W_t + idx, nv, W);
+  const double rho_m = shfl(rho[kHq - 1], lm);
   if (!ln.store) return;
-  const double irho = 1.0 / rho;
-  f.p_t[idx] = p;
-  f.T[idx] = p * irho / c.Rd;
-  f.vx[idx] = (double)f.Mx_t[idx] * irho;
-  f.vy[idx] = (double)f.My_t[idx] * irho;
-  f.vz[idx] = (double)f.Mz_t[idx] * irho;
-  f.wI[idx] = lev == 0 ? 0.0 : W / (0.5 * (rho_m + rho));
+  H mx[kHq], my[kHq], mz[kHq];
+  ld4<VEC>(f.Mx_t + idx, nv, mx);
+  ld4<VEC>(f.My_t + idx, nv, my);
+  ld4<VEC>(f.Mz_t + idx, nv, mz);
+  double p[kHq], T[kHq], vx[kHq], vy[kHq], vz[kHq], wI[kHq];
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) {
+    p[q] = c.p_ref * pow(c.Rd * rth[q] / c.p_ref, c.gamma);
+    const double irho = 1.0 / rho[q];
+    T[q] = p[q] * irho / c.Rd;
+    vx[q] = (double)mx[q] * irho;
+    vy[q] = (double)my[q] * irho;
+    vz[q] = (double)mz[q] * irho;
+    const double rm = q ? rho[q - 1] : rho_m;
+    wI[q] = lev0 + q == 0 ? 0.0 : W[q] / (0.5 * (rm + rho[q]));
+  }
+  st4<VEC>(f.p_t + idx, nv, p);
+  st4<VEC>(f.T + idx, nv, T);
+  st4<VEC>(f.vx + idx, nv, vx);
+  st4<VEC>(f.vy + idx, nv, vy);
+  st4<VEC>(f.vz + idx, nv, vz);
+  st4<VEC>(f.wI + idx, nv, wI);
 }
 
-template <typename H>
-__device__ __forceinline__ void b_large1(const Fields<H> &f, const Consts &c, const Lane &ln) {
-  const int L = c.L, lev = ln.lev, col = ln.col;
-  const size_t idx = (size_t)col * L + lev;
-  const int lm = ln.lane > 0 ? ln.lane - 1 : 0;
-  const int lp = ln.lane < 63 ? ln.lane + 1 : 63;
+// sum_j l_j (s_j - s_0) at kHq consecutive levels: the Laplacian without
+// its 1/r^2.
+template <bool VEC, typename T, typename H>
+__device__ __forceinline__ void lap4(const T *s, const int nb[6], const H *lc, int L, int lev0, int nv, size_t idx,
+                                     T out[kHq]) {
+  T s0[kHq];
+  ld4<VEC>(s + idx, nv, s0);
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) out[q] = 0;
+#pragma unroll 2
+  for (int j = 0; j < 6; ++j) {
+    T sj[kHq];
+    ld4<VEC>(s + (size_t)nb[j] * L + lev0, nv, sj);
+    const T w = (T)lc[j];
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) out[q] += w * (sj[q] - s0[q]);
+  }
+}
+
+template <typename H, bool VEC>
+__device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
+  const int L = c.L, lev0 = ln.lev0, nv = ln.nv, col = ln.col;
+  const size_t idx = (size_t)col * L + lev0;
+  const int lane = threadIdx.x & 63;
+  const int lm = lane > 0 ? lane - 1 : 0;
+  const int lp = lane < 63 ? lane + 1 : 63;
+  double rho[kHq], p[kHq], W[kHq];
+  ld4<VEC>(f.rho_t + idx, nv, rho);
+  ld4<VEC>(f.p_t + idx, nv, p);
+  ld4<VEC>(f.W_t + idx, nv, W);
+  const double rho_m = shfl(rho[kHq - 1], lm), p_m = shfl(p[kHq - 1], lm), W_n = shfl(W[0], lp);
+  if (!ln.store) return;
   int nb[6];
   load_nbr(f.nbr, col, nb);
   const H *dch = f.dc + (size_t)col * 21;
   const H *lch = f.lc + (size_t)col * 6;
-  const double rho = f.rho_t[idx];
-  const double rho_m = shfl(rho, lm);
-  const double p = f.p_t[idx];
-  const double p_m = shfl(p, lm);
-  const double W = f.W_t[idx];
-  double W1 = shfl(W, lp);
-  if (lev == L - 1) W1 = 0.0;
-  if (!ln.store) return;
-  const double rC = radius_c(c, lev), rI = radius_i(c, lev);
   const double Kd = c.Kd;
-  const double irc2 = 1.0 / (rC * rC);
-  f.Xrho[idx] = irc2 * lap_at(f.rho_t, nb, lch, L, lev, idx);
-  f.Xvx[idx] = rho * Kd * irc2 * lap_at(f.vx, nb, lch, L, lev, idx);
-  f.Xvy[idx] = rho * Kd * irc2 * lap_at(f.vy, nb, lch, L, lev, idx);
-  f.Xvz[idx] = rho * Kd * irc2 * lap_at(f.vz, nb, lch, L, lev, idx);
-  f.XT[idx] = rho * Kd * irc2 * lap_at(f.T, nb, lch, L, lev, idx);
-  f.Xw[idx] = lev == 0 ? 0.0
-                       : 0.5 * (rho_m + rho) * Kd / (rI * rI) * lap_at(f.wI, nb, lch, L, lev, idx);
-  // grad p[t] (in double: full pressure), projected
-  double gx = 0, gy = 0, gz = 0;
+  double irc2[kHq];
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) {
+    const double rC = radius_c(c, lev0 + q);
+    irc2[q] = 1.0 / (rC * rC);
+  }
   {
-    const double *pp = f.p_t;
-    for (int j = 0; j < 6; ++j) {
-      double dp = pp[(size_t)nb[j] * L + lev] - p;
-      gx += (double)dch[3 * (j + 1)] * dp;
-      gy += (double)dch[3 * (j + 1) + 1] * dp;
-      gz += (double)dch[3 * (j + 1) + 2] * dp;
+    double l[kHq];
+    lap4<VEC>(f.rho_t, nb, lch, L, lev0, nv, idx, l);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) l[q] = irc2[q] * l[q];
+    st4<VEC>(f.Xrho + idx, nv, l);
+  }
+  const double *vsrc[4] = {f.vx, f.vy, f.vz, f.T};
+  double *vdst[4] = {f.Xvx, f.Xvy, f.Xvz, f.XT};
+#pragma unroll 1
+  for (int k = 0; k < 4; ++k) {
+    double l[kHq];
+    lap4<VEC>(vsrc[k], nb, lch, L, lev0, nv, idx, l);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) l[q] = rho[q] * Kd * irc2[q] * l[q];
+    st4<VEC>(vdst[k] + idx, nv, l);
+  }
+  {
+    double l[kHq];
+    lap4<VEC>(f.wI, nb, lch, L, lev0, nv, idx, l);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const int lev = lev0 + q;
+      const double rI = radius_i(c, lev);
+      const double rm = q ? rho[q - 1] : rho_m;
+      l[q] = lev == 0 ? 0.0 : 0.5 * (rm + rho[q]) * Kd / (rI * rI) * l[q];
     }
-    gx /= rC;
-    gy /= rC;
-    gz /= rC;
+    st4<VEC>(f.Xw + idx, nv, l);
   }
-  const H *rh = f.rhat + (size_t)col * 3;
-  const double rx = rh[0], ry = rh[1], rz = rh[2];
-  const double gr = gx * rx + gy * ry + gz * rz;
-  f.FMx[idx] = (H)(-(gx - gr * rx));
-  f.FMy[idx] = (H)(-(gy - gr * ry));
-  f.FMz[idx] = (H)(-(gz - gr * rz));
+  // grad p[t] (in double: full pressure), projected
+  {
+    double gx[kHq], gy[kHq], gz[kHq];
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) gx[q] = gy[q] = gz[q] = 0;
+#pragma unroll 2
+    for (int j = 0; j < 6; ++j) {
+      double pj[kHq];
+      ld4<VEC>(f.p_t + (size_t)nb[j] * L + lev0, nv, pj);
+      const double cx = dch[3 * (j + 1)], cy = dch[3 * (j + 1) + 1], cz = dch[3 * (j + 1) + 2];
+#pragma unroll
+      for (int q = 0; q < kHq; ++q) {
+        const double dp = pj[q] - p[q];
+        gx[q] += cx * dp;
+        gy[q] += cy * dp;
+        gz[q] += cz * dp;
+      }
+    }
+    const H *rh = f.rhat + (size_t)col * 3;
+    const double rx = rh[0], ry = rh[1], rz = rh[2];
+    H ox[kHq], oy[kHq], oz[kHq];
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const double rC = radius_c(c, lev0 + q);
+      const double x = gx[q] / rC, y = gy[q] / rC, z = gz[q] / rC;
+      const double gr = x * rx + y * ry + z * rz;
+      ox[q] = (H)(-(x - gr * rx));
+      oy[q] = (H)(-(y - gr * ry));
+      oz[q] = (H)(-(z - gr * rz));
+    }
+    st4<VEC>(f.FMx + idx, nv, ox);
+    st4<VEC>(f.FMy + idx, nv, oy);
+    st4<VEC>(f.FMz + idx, nv, oz);
+  }
   // 3D momentum divergence of Phi[t]
-  H dm = dch[0] * f.Mx_t[idx] + dch[1] * f.My_t[idx] + dch[2] * f.Mz_t[idx];
-  for (int j = 0; j < 6; ++j) {
-    size_t nj = (size_t)nb[j] * L + lev;
-    dm += dch[3 * (j + 1)] * f.Mx_t[nj] + dch[3 * (j + 1) + 1] * f.My_t[nj] +
-          dch[3 * (j + 1) + 2] * f.Mz_t[nj];
+  {
+    H mx[kHq], my[kHq], mz[kHq], dm[kHq];
+    ld4<VEC>(f.Mx_t + idx, nv, mx);
+    ld4<VEC>(f.My_t + idx, nv, my);
+    ld4<VEC>(f.Mz_t + idx, nv, mz);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) dm[q] = dch[0] * mx[q] + dch[1] * my[q] + dch[2] * mz[q];
+#pragma unroll 2
+    for (int j = 0; j < 6; ++j) {
+      const size_t nj = (size_t)nb[j] * L + lev0;
+      ld4<VEC>(f.Mx_t + nj, nv, mx);
+      ld4<VEC>(f.My_t + nj, nv, my);
+      ld4<VEC>(f.Mz_t + nj, nv, mz);
+      const H cx = dch[3 * (j + 1)], cy = dch[3 * (j + 1) + 1], cz = dch[3 * (j + 1) + 2];
+#pragma unroll
+      for (int q = 0; q < kHq; ++q) dm[q] += cx * mx[q] + cy * my[q] + cz * mz[q];
+    }
+    H Dt[kHq];
+    double FW[kHq];
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const int lev = lev0 + q;
+      const double rC = radius_c(c, lev), rI = radius_i(c, lev);
+      const double W1 = lev == L - 1 ? 0.0 : (q + 1 < kHq ? W[q + 1] : W_n);
+      const double Wl = lev == 0 ? 0.0 : W[q];
+      Dt[q] = (H)((double)dm[q] / rC + ((rI + c.dz) * (rI + c.dz) * W1 - rI * rI * Wl) / (rC * rC * c.dz));
+      // [t] vertical imbalance at interface lev
+      const double pm = q ? p[q - 1] : p_m, rm = q ? rho[q - 1] : rho_m;
+      FW[q] = lev == 0 ? 0.0 : -(p[q] - pm) / c.dz - 0.5 * c.grav * (rm + rho[q]);
+    }
+    st4<VEC>(f.Dt + idx, nv, Dt);
+    st4<VEC>(f.FW + idx, nv, FW);
   }
-  const double Wl = lev == 0 ? 0.0 : W;
-  f.Dt[idx] = (H)((double)dm / rC + ((rI + c.dz) * (rI + c.dz) * W1 - rI * rI * Wl) / (rC * rC * c.dz));
-  // [t] vertical imbalance at interface lev
-  f.FW[idx] = lev == 0 ? 0.0 : -(p - p_m) / c.dz - 0.5 * c.grav * (rho_m + rho);
 }
 
-template <typename H>
-__device__ __forceinline__ void b_large2(const Fields<H> &f, const Consts &c, const Lane &ln) {
+template <typename H, bool VEC>
+__device__ __forceinline__ void large2_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
   if (!ln.store) return;
-  const int L = c.L, lev = ln.lev, col = ln.col;
-  const size_t idx = (size_t)col * L + lev;
+  const int L = c.L, lev0 = ln.lev0, nv = ln.nv, col = ln.col;
+  const size_t idx = (size_t)col * L + lev0;
   int nb[6];
   load_nbr(f.nbr, col, nb);
   const H *lch = f.lc + (size_t)col * 6;
-  const double rC = radius_c(c, lev), rI = radius_i(c, lev);
-  const double irc2 = 1.0 / (rC * rC);
-  f.Hrho[idx] = -c.Kd * irc2 * lap_at(f.Xrho, nb, lch, L, lev, idx);
-  double hx = -irc2 * lap_at(f.Xvx, nb, lch, L, lev, idx);
-  double hy = -irc2 * lap_at(f.Xvy, nb, lch, L, lev, idx);
-  double hz = -irc2 * lap_at(f.Xvz, nb, lch, L, lev, idx);
-  const H *rh = f.rhat + (size_t)col * 3;
-  const double rx = rh[0], ry = rh[1], rz = rh[2];
-  const double hr = hx * rx + hy * ry + hz * rz;
-  f.FMx[idx] = (H)((double)f.FMx[idx] + (hx - hr * rx));
-  f.FMy[idx] = (H)((double)f.FMy[idx] + (hy - hr * ry));
-  f.FMz[idx] = (H)((double)f.FMz[idx] + (hz - hr * rz));
-  if (lev > 0) f.FW[idx] += -lap_at(f.Xw, nb, lch, L, lev, idx) / (rI * rI);
-  const double rth = f.rth_t[idx], p = f.p_t[idx];
-  f.Hrth[idx] = rth / (c.gamma * p) * (-c.Rd * irc2 * lap_at(f.XT, nb, lch, L, lev, idx));
+  double irc2[kHq];
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) {
+    const double rC = radius_c(c, lev0 + q);
+    irc2[q] = 1.0 / (rC * rC);
+  }
+  {
+    double l[kHq];
+    lap4<VEC>(f.Xrho, nb, lch, L, lev0, nv, idx, l);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) l[q] = -c.Kd * irc2[q] * l[q];
+    st4<VEC>(f.Hrho + idx, nv, l);
+  }
+  {
+    double hx[kHq], hy[kHq], hz[kHq];
+    lap4<VEC>(f.Xvx, nb, lch, L, lev0, nv, idx, hx);
+    lap4<VEC>(f.Xvy, nb, lch, L, lev0, nv, idx, hy);
+    lap4<VEC>(f.Xvz, nb, lch, L, lev0, nv, idx, hz);
+    const H *rh = f.rhat + (size_t)col * 3;
+    const double rx = rh[0], ry = rh[1], rz = rh[2];
+    H fx[kHq], fy[kHq], fz[kHq];
+    ld4<VEC>(f.FMx + idx, nv, fx);
+    ld4<VEC>(f.FMy + idx, nv, fy);
+    ld4<VEC>(f.FMz + idx, nv, fz);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const double x = -irc2[q] * hx[q], y = -irc2[q] * hy[q], z = -irc2[q] * hz[q];
+      const double hr = x * rx + y * ry + z * rz;
+      fx[q] = (H)((double)fx[q] + (x - hr * rx));
+      fy[q] = (H)((double)fy[q] + (y - hr * ry));
+      fz[q] = (H)((double)fz[q] + (z - hr * rz));
+    }
+    st4<VEC>(f.FMx + idx, nv, fx);
+    st4<VEC>(f.FMy + idx, nv, fy);
+    st4<VEC>(f.FMz + idx, nv, fz);
+  }
+  {
+    double l[kHq], fw[kHq];
+    lap4<VEC>(f.Xw, nb, lch, L, lev0, nv, idx, l);
+    ld4<VEC>(f.FW + idx, nv, fw);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const int lev = lev0 + q;
+      const double rI = radius_i(c, lev);
+      if (lev > 0) fw[q] += -l[q] / (rI * rI);
+    }
+    st4<VEC>(f.FW + idx, nv, fw);
+  }
+  {
+    double l[kHq], rth[kHq], p[kHq];
+    lap4<VEC>(f.XT, nb, lch, L, lev0, nv, idx, l);
+    ld4<VEC>(f.rth_t + idx, nv, rth);
+    ld4<VEC>(f.p_t + idx, nv, p);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) l[q] = rth[q] / (c.gamma * p[q]) * (-c.Rd * irc2[q] * l[q]);
+    st4<VEC>(f.Hrth + idx, nv, l);
+  }
 }
+
+#define THOR_HBODY(NAME)                                                                       \
+  template <typename H>                                                                      \
+  __device__ __forceinline__ void b_##NAME(const Fields<H> &f, const Consts &c, const HLane &ln) { \
+    if ((c.L % kHq) == 0)                                                                    \
+      NAME##_cells<H, true>(f, c, ln);                                                       \
+    else                                                                                     \
+      NAME##_cells<H, false>(f, c, ln);                                                      \
+  }
+THOR_HBODY(large0)
+THOR_HBODY(large1)
+THOR_HBODY(large2)
+#undef THOR_HBODY
 
 // Diagnostic field into f.diag (FP64, canonical layout).
 template <typename H>
@@ -578,11 +913,11 @@ __device__ __forceinline__ void b_import(const Fields<H> &f, const Consts &c, co
 // k_NAME: one planet; kb_NAME: an ensemble, where logical workgroup b runs
 // local workgroup tiles[b].y of planet tiles[b].x (x < 0: padding).  Both call
 // the same body, so a planet computes bit-identical results either way.
-#define THOR_KERNEL(NAME, OCC, PARAMS, ARGS)                                              \
+#define THOR_KERNEL(NAME, OCC, MAP, PARAMS, ARGS)                                              \
   template <typename H>                                                                   \
   __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(OCC)))       \
   void k_##NAME(Fields<H> f, Consts c PARAMS) {                                           \
-    b_##NAME(f, c, map_lane(c, xcd_block()) ARGS);                                        \
+    b_##NAME(f, c, MAP(c, xcd_block()) ARGS);                                        \
   }                                                                                       \
   template <typename H>                                                                   \
   __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(OCC)))       \
@@ -591,16 +926,29 @@ __device__ __forceinline__ void b_import(const Fields<H> &f, const Consts &c, co
     if (t.x < 0) return;                                                                  \
     const Fields<H> &f = P[t.x].f[parity];                                                \
     const Consts &c = P[t.x].c;                                                           \
-    b_##NAME(f, c, map_lane(c, t.y) ARGS);                                                \
+    b_##NAME(f, c, MAP(c, t.y) ARGS);                                                \
   }
 #define COMMA ,
-THOR_KERNEL(hmom, 6, COMMA int div COMMA int first, COMMA c.dt / div COMMA first)
-THOR_KERNEL(slow, 4, COMMA int from_t, COMMA from_t)
-THOR_KERNEL(large0, 8, , )
-THOR_KERNEL(large1, 4, , )
-THOR_KERNEL(large2, 5, , )
-THOR_KERNEL(diag, 8, COMMA int field, COMMA field)
-THOR_KERNEL(import, 8, COMMA const double *blob, COMMA blob)
+THOR_KERNEL(slow, sizeof(H) == 8 ? 2 : 4, map_hlane, COMMA int from_t, COMMA from_t)
+THOR_KERNEL(large0, 4, map_hlane, , )
+THOR_KERNEL(large1, sizeof(H) == 8 ? 3 : 4, map_hlane, , )
+THOR_KERNEL(large2, 5, map_hlane, , )
+THOR_KERNEL(diag, 8, map_lane, COMMA int field, COMMA field)
+THOR_KERNEL(import, 8, map_lane, COMMA const double *blob, COMMA blob)
+template <typename H>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? HMOM_OCC_D : HMOM_OCC_F)))
+void k_hmom(Fields<H> f, Consts c, int div, int first) {
+  b_hmom(f, c, map_hlane(c, xcd_block()), c.dt / div, first);
+}
+template <typename H>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? HMOM_OCC_D : HMOM_OCC_F)))
+void kb_hmom(const Planet<H> *P, const int2 *tiles, int parity, int div, int first) {
+  const int2 t = tiles[xcd_block()];
+  if (t.x < 0) return;
+  const Fields<H> &f = P[t.x].f[parity];
+  const Consts &c = P[t.x].c;
+  b_hmom(f, c, map_hlane(c, t.y), c.dt / div, first);
+}
 template <typename H, bool LAST>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void k_vert(Fields<H> f, Consts c, int div, int first) {
@@ -622,7 +970,7 @@ void kb_vert(const Planet<H> *P, const int2 *tiles, int parity, int div, int fir
 
 template <typename H>
 void launch_hmom(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, hipStream_t s) {
-  hipLaunchKernelGGL(k_hmom<H>, dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c, div, (int)first);
+  hipLaunchKernelGGL(k_hmom<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c, div, (int)first);
 }
 template <typename H>
 void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, bool last,
@@ -634,13 +982,13 @@ void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool fir
 }
 template <typename H>
 void launch_slow(const Fields<H> &f, const Consts &c, int wpb, bool from_t, hipStream_t s) {
-  hipLaunchKernelGGL(k_slow<H>, dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c, (int)from_t);
+  hipLaunchKernelGGL(k_slow<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c, (int)from_t);
 }
 template <typename H>
 void launch_large(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s) {
-  hipLaunchKernelGGL(k_large0<H>, dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c);
-  hipLaunchKernelGGL(k_large1<H>, dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c);
-  hipLaunchKernelGGL(k_large2<H>, dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c);
+  hipLaunchKernelGGL(k_large0<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c);
+  hipLaunchKernelGGL(k_large1<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c);
+  hipLaunchKernelGGL(k_large2<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c);
 }
 template <typename H>
 void launch_diag_field(const Fields<H> &f, const Consts &c, int field, hipStream_t s) {

@@ -446,6 +446,8 @@ int thor_state_init(const thor_grid *g, const thor_planet *pl, const thor_vertic
   c.N = (int)g->g.n;
   c.L = v->n_lev;
   c.cpw = 64 / v->n_lev;
+  c.hlpc = (v->n_lev + kHq - 1) / kHq;
+  c.hcpw = 64 / c.hlpc;
   c.radius = pl->radius;
   c.omega = pl->omega;
   c.grav = pl->gravity;
@@ -667,7 +669,8 @@ int upload_tiles(thor_batch *b, size_t planet_bytes) {
     std::vector<int2> t;
     for (int i = 0; i < b->n; ++i) {
       const Consts &c = b->members[i]->c;
-      const long waves = (c.N + c.cpw - 1) / c.cpw;
+      const int cols = fam == FAM_VERT ? c.cpw : c.hcpw;
+      const long waves = (c.N + cols - 1) / cols;
       const long wg = (waves + b->wpb[fam] - 1) / b->wpb[fam];
       for (long k = 0; k < wg; ++k) t.push_back(make_int2(i, (int)k));
     }
