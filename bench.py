@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E datasheet peak
+BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
 
 
 def vert_bytes_per_cell(L, mixed):
@@ -175,6 +176,46 @@ def run_ensemble(steps, warmup):
             "autotuned_wavefronts_per_workgroup": wpb}
 
 
+def run_corrector_mlp(reps=20):
+    """The corrector network at the g5 L32 shape (inputs 7 columns x 5 fields
+    x 32 levels, three hidden layers of 256, 160 outputs): one inference pass
+    over all 10242 coarse columns and one training step on 4096 columns, as
+    matrix-core FLOP/s against the dense BF16 peak."""
+    import torch
+    from paper_1607_05535_amd import thor
+    widths = [1120, 256, 256, 256, 160]
+    n_inf, n_train = 10242, 4096
+    net = thor.MLP(widths, n_inf, seed=1)
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    x = torch.randn(n_inf, widths[0], device="cuda:0", generator=g).to(torch.bfloat16)
+    y = torch.empty(n_inf, widths[-1], device="cuda:0")
+    t = torch.randn(n_train, widths[-1], device="cuda:0", generator=g)
+    pairs = list(zip(widths[:-1], widths[1:]))
+    f_fwd = sum(2.0 * i * o for i, o in pairs)                  # per row
+    f_train = 2 * f_fwd + sum(2.0 * i * o for i, o in pairs[1:])  # forward, dW, dH (no dX)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    t_inf = timed(lambda: net.forward(x, y))
+    t_tr = timed(lambda: net.train_step(x[:n_train], t, 1e-4))
+    return {"widths": widths,
+            "inference_rows": n_inf, "inference_ms": t_inf * 1e3,
+            "inference_TFLOPs": f_fwd * n_inf / t_inf / 1e12,
+            "train_rows": n_train, "train_step_ms": t_tr * 1e3,
+            "train_TFLOPs": f_train * n_train / t_tr / 1e12,
+            "peak_TFLOPs": BF16_PEAK_TFLOPS,
+            "inference_frac": f_fwd * n_inf / t_inf / 1e12 / BF16_PEAK_TFLOPS}
+
+
 def cpu_baseline(w):
     """The FP64 oracle on the host: one large step's worth estimated from a
     bounded sample (the per-step terms, one RK stage of slow terms and two
@@ -231,6 +272,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-one-day", action="store_true")
+    ap.add_argument("--no-corrector", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -287,6 +329,8 @@ def main():
             out["mixed"]["one_day"] = mixed_one_day()
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble(max(1, args.steps // 10), 2)
+    if not args.no_corrector:
+        out["corrector_mlp"] = run_corrector_mlp()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -277,7 +277,8 @@ void thor_batch_free(thor_batch *b);   /* frees the members; never frees dev_buf
  * Per-column corrector network: a multilayer perceptron with GELU hidden
  * layers, z = W h + b, W [out][in] row-major.  Operands are BF16 and products
  * accumulate in FP32 on the matrix cores; master weights, gradients and the
- * Adam moments are FP32.  Widths must be multiples of 32.  All device
+ * Adam moments are FP32.  Gradients are reproducible: the reductions over
+ * the batch use fixed chunks summed in a fixed order.  Widths must be multiples of 32.  All device
  * pointers below are caller-owned device memory; the object lives in the
  * caller's buffer of thor_mlp_bytes bytes and enqueues on hip_stream.
  * ------------------------------------------------------------------------- */

@@ -2,13 +2,15 @@
 // hidden layers, BF16 operands and FP32 accumulation on the matrix cores
 // (v_mfma_f32_16x16x32_bf16), forward, backward and Adam on the GPU.
 //
-// Layout: weights W[out][in] row-major with a transposed copy WT[in][out];
-// activations [batch][width] row-major with transposed copies where a
-// product reduces over the batch.  Every product is C[M][N] = A[M][K] B[N][K]^T
-// with both operands contiguous along K, so one GEMM kernel serves
-//   forward    Z  = H_prev W^T          (A = H_prev, B = W)
-//   input grad dH = dZ W                (A = dZ,     B = WT)
-//   weight grad dW = dZ^T H_prev         (A = dZT,    B = H_prevT)
+// Layout: weights W[out][in] and activations [batch][width], row-major.  One
+// GEMM kernel C[M][N] = sum_k A(m, k) B(n, k) reads either operand with k
+// contiguous (A[m][k], B[n][k]) or with k as the outer index (A[k][m],
+// B[k][n]) through LDS, so no transposed copies are kept:
+//   forward    Z  = H_prev W^T     A = H_prev [B][in],   B = W [out][in]
+//   input grad dH = dZ W           A = dZ [B][out],      B = W read as [k=out][n=in]
+//   weight grad dW = dZ^T H_prev   A = dZ read as [k=B][m=out], B = H_prev read as [k=B][n=in]
+// The weight gradient reduces over the batch in fixed chunks (split K) whose
+// partial sums are added in a fixed order, so results are reproducible.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,73 +27,147 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTile = 64;   // C tile per workgroup (4 wavefronts of 32 x 32)
+constexpr int kTile = 64;    // C tile per workgroup (4 wavefronts of 32 x 32)
+constexpr int kStepK = 32;   // k per MFMA step
+constexpr int kRow = kStepK + 8;   // LDS row of a staged tile (bf16), padded
+constexpr int kMaxSplit = 8;       // batch chunks of the weight gradient
+constexpr int kBiasSplit = 16;     // batch chunks of the bias gradient
 
-// C = A B^T (+ bias), A [M][K], B [N][K] bf16, K % 32 == 0, C fp32 [M][ldc].
-// Wavefront w of the workgroup owns rows m0 + 32 (w / 2) .. + 31 and columns
-// n0 + 32 (w % 2) .. + 31 as 2 x 2 MFMA tiles of 16 x 16.  In a tile, lane l
-// holds A[row l % 16][k0 + 8 (l / 16) .. + 7] and B[col l % 16][same k] and
-// accumulates D[4 (l / 16) + i][l % 16], i = 0..3.
-__global__ __launch_bounds__(256) void k_gemm_nt(const __bf16 *__restrict__ A, const __bf16 *__restrict__ B,
-                                                 float *__restrict__ C, const float *__restrict__ bias,
-                                                 int M, int N, int K, int ldc) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = blockIdx.x * kTile + 32 * (w >> 1);
-  const int n0 = blockIdx.y * kTile + 32 * (w & 1);
-  const int r = lane & 15, kq = (lane >> 4) * 8;
-  f32x4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const bf16x8 zero = {};
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    bf16x8 a[2], b[2];
-    for (int i = 0; i < 2; ++i) {
-      const int row = m0 + 16 * i + r;
-      a[i] = row < M ? *reinterpret_cast<const bf16x8 *>(A + (size_t)row * K + k0 + kq) : zero;
-      const int col = n0 + 16 * i + r;
-      b[i] = col < N ? *reinterpret_cast<const bf16x8 *>(B + (size_t)col * K + k0 + kq) : zero;
-    }
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-  }
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + 16 * j + r;
-      if (col >= N) continue;
-      const float bb = bias ? bias[col] : 0.f;
-      for (int q = 0; q < 4; ++q) {
-        const int row = m0 + 16 * i + (lane >> 4) * 4 + q;
-        if (row < M) C[(size_t)row * ldc + col] = acc[i][j][q] + bb;
-      }
-    }
-}
+enum Epilogue { EPI_STORE = 0, EPI_GELU = 1 };
 
 __device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad_f(float z) {
   return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
-// H = g(Z) (or Z for the output layer) as bf16 in both layouts.
-__global__ void k_activate(const float *Z, __bf16 *H, __bf16 *HT, int B, int N, int act) {
-  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (i >= (size_t)B * N) return;
-  const int b = (int)(i / N), n = (int)(i % N);
-  const float v = act ? gelu_f(Z[i]) : Z[i];
-  H[i] = (__bf16)v;
-  if (HT) HT[(size_t)n * B + b] = (__bf16)v;
+// One 16-byte piece of a 64 x 32 operand tile per thread (256 threads), read
+// from global memory: rows r0.. of an operand with `rows` rows.  KOUTER:
+// stored [k][row] with leading dimension ld, else [row][k].
+template <bool KOUTER>
+__device__ __forceinline__ bf16x8 tile_load(const __bf16 *P, int ld, int rows, int r0, int k0) {
+  const int t = threadIdx.x;
+  const bf16x8 zero = {};
+  if (!KOUTER) {
+    const int row = r0 + (t >> 2), kc = (t & 3) * 8;
+    return row < rows ? *reinterpret_cast<const bf16x8 *>(P + (size_t)row * ld + k0 + kc) : zero;
+  } else {
+    const int kr = t >> 3, rc = r0 + (t & 7) * 8;   // rows is a multiple of 8
+    return rc < rows ? *reinterpret_cast<const bf16x8 *>(P + (size_t)(k0 + kr) * ld + rc) : zero;
+  }
 }
 
-// Transposed bf16 copy: XT[k][b] = X[b][k].
-__global__ void k_transpose_bf16(const __bf16 *X, __bf16 *XT, int B, int K) {
+// The same piece into the LDS tile S[row][k] (rows of kRow values).
+template <bool KOUTER>
+__device__ __forceinline__ void tile_store(__bf16 *S, const bf16x8 v) {
+  const int t = threadIdx.x;
+  if (!KOUTER) {
+    *reinterpret_cast<bf16x8 *>(S + (t >> 2) * kRow + (t & 3) * 8) = v;
+  } else {
+    const int kr = t >> 3, rc = (t & 7) * 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) S[(rc + i) * kRow + kr] = v[i];
+  }
+}
+
+// C tile (m0, n0) of the product over k in [k_lo, k_hi), 4 wavefronts, LDS
+// double-buffered.  Wavefront w owns rows 32 (w / 2) .. + 31 and columns
+// 32 (w % 2) .. + 31 of the tile as 2 x 2 MFMA tiles of 16 x 16; lane l holds
+// A(row l % 16, k0 + 8 (l / 16) .. + 7), B(col l % 16, same k) and
+// accumulates D[4 (l / 16) + i][l % 16], i = 0..3.
+//   EPI_STORE: C = acc (+ bias), or the split's partial C + z M ldc.
+//   EPI_GELU:  C = acc + bias (pre-activation), H = gelu(C) in bf16.
+template <bool AK, bool BK, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, int lda, const __bf16 *__restrict__ B,
+                                              int ldb, float *__restrict__ C, int ldc, const float *__restrict__ bias,
+                                              __bf16 *__restrict__ H, int M, int N, int K, int k_chunk) {
+  __shared__ __align__(16) __bf16 As[2][kTile * kRow];
+  __shared__ __align__(16) __bf16 Bs[2][kTile * kRow];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m0 = blockIdx.x * kTile, n0 = blockIdx.y * kTile;
+  const int wm = 32 * (w >> 1), wn = 32 * (w & 1);
+  const int r = lane & 15, kq = (lane >> 4) * 8;
+  const int k_lo = blockIdx.z * k_chunk, k_hi = min(K, k_lo + k_chunk);
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int buf = 0;
+  if (k_lo < k_hi) {
+    tile_store<AK>(As[0], tile_load<AK>(A, lda, M, m0, k_lo));
+    tile_store<BK>(Bs[0], tile_load<BK>(B, ldb, N, n0, k_lo));
+  }
+  __syncthreads();
+  for (int k0 = k_lo; k0 < k_hi; k0 += kStepK) {
+    const bool more = k0 + kStepK < k_hi;
+    bf16x8 na, nbv;
+    if (more) {
+      na = tile_load<AK>(A, lda, M, m0, k0 + kStepK);
+      nbv = tile_load<BK>(B, ldb, N, n0, k0 + kStepK);
+    }
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      a[i] = *reinterpret_cast<const bf16x8 *>(&As[buf][(wm + 16 * i + r) * kRow + kq]);
+      b[i] = *reinterpret_cast<const bf16x8 *>(&Bs[buf][(wn + 16 * i + r) * kRow + kq]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (more) {
+      tile_store<AK>(As[buf ^ 1], na);
+      tile_store<BK>(Bs[buf ^ 1], nbv);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  float *Cz = C + (size_t)blockIdx.z * M * ldc;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + 16 * j + r;
+      if (col >= N) continue;
+      const float bb = bias ? bias[col] : 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = m0 + wm + 16 * i + (lane >> 4) * 4 + q;
+        if (row >= M) continue;
+        const float z = acc[i][j][q] + bb;
+        Cz[(size_t)row * ldc + col] = z;
+        if (EPI == EPI_GELU) H[(size_t)row * N + col] = (__bf16)gelu_f(z);
+      }
+    }
+}
+
+// out[i] = sum_{z < S} part[z][i] in order z = 0, 1, ...
+__global__ void k_reduce(const float *part, int S, size_t n, float *out) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (i >= (size_t)B * K) return;
-  const int b = (int)(i / K), k = (int)(i % K);
-  XT[(size_t)k * B + b] = X[i];
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < S; ++z) s += part[(size_t)z * n + i];
+  out[i] = s;
+}
+
+// Column sums of X[B][N] over row chunk blockIdx.y into part[chunk][N]:
+// 64 columns per workgroup, 4 row groups combined in a fixed order.
+__global__ __launch_bounds__(256) void k_colsum(const float *X, int B, int N, int rows_per, float *part) {
+  __shared__ float sm[4][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
+  const int b0 = blockIdx.y * rows_per, b1 = min(B, b0 + rows_per);
+  float s = 0.f;
+  if (n < N)
+    for (int b = b0 + g; b < b1; b += 4) s += X[(size_t)b * N + n];
+  sm[g][c] = s;
+  __syncthreads();
+  if (g == 0 && n < N) part[(size_t)blockIdx.y * N + n] = ((sm[0][c] + sm[1][c]) + sm[2][c]) + sm[3][c];
 }
 
 // Output layer: dZ = 2 (Y - T) / (B N); per-workgroup partial loss sums.
 __global__ __launch_bounds__(256) void k_loss(const float *Y, const float *T, float *dZ, __bf16 *dZb,
-                                              __bf16 *dZT, float *partial, int B, int N) {
+                                              float *partial, int B, int N) {
   __shared__ float sm[256];
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   float l = 0.f;
@@ -99,10 +175,8 @@ __global__ __launch_bounds__(256) void k_loss(const float *Y, const float *T, fl
     const float d = Y[i] - T[i];
     l = d * d;
     const float g = 2.f * d / ((float)B * (float)N);
-    const int b = (int)(i / N), n = (int)(i % N);
     dZ[i] = g;
     dZb[i] = (__bf16)g;
-    dZT[(size_t)n * B + b] = (__bf16)g;
   }
   sm[threadIdx.x] = l;
   __syncthreads();
@@ -113,24 +187,13 @@ __global__ __launch_bounds__(256) void k_loss(const float *Y, const float *T, fl
   if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
 }
 
-// Hidden layer: dZ = dH * g'(Z) in fp32 and bf16 (both layouts).
-__global__ void k_act_grad(const float *dH, const float *Z, float *dZ, __bf16 *dZb, __bf16 *dZT, int B, int N) {
+// Hidden layer: dZ = dH * g'(Z) in fp32 and bf16.
+__global__ void k_act_grad(const float *dH, const float *Z, float *dZ, __bf16 *dZb, size_t n) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (i >= (size_t)B * N) return;
+  if (i >= n) return;
   const float g = dH[i] * gelu_grad_f(Z[i]);
-  const int b = (int)(i / N), n = (int)(i % N);
   dZ[i] = g;
   dZb[i] = (__bf16)g;
-  dZT[(size_t)n * B + b] = (__bf16)g;
-}
-
-// db[n] = sum_b dZ[b][n] (fixed order).
-__global__ void k_bias_grad(const float *dZ, float *db, int B, int N) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  float s = 0.f;
-  for (int b = 0; b < B; ++b) s += dZ[(size_t)b * N + n];
-  db[n] = s;
 }
 
 // Adam on the packed fp32 parameters.
@@ -146,13 +209,11 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, size_t n, f
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// bf16 copies W[out][in] and WT[in][out] of one layer's fp32 weights.
-__global__ void k_weights_bf16(const float *W, __bf16 *Wb, __bf16 *WT, int out, int in) {
+// bf16 copy of one layer's fp32 weights.
+__global__ void k_weights_bf16(const float *W, __bf16 *Wb, size_t n) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (i >= (size_t)out * in) return;
-  const int o = (int)(i / in), k = (int)(i % in);
+  if (i >= n) return;
   Wb[i] = (__bf16)W[i];
-  WT[(size_t)k * out + o] = (__bf16)W[i];
 }
 
 inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -170,14 +231,14 @@ struct thor_mlp {
   size_t n_params = 0;
   std::vector<size_t> woff, boff;   // offsets of W_l, b_l in the packed arrays
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
-  std::vector<__bf16 *> Wb, WT;
-  __bf16 *XT = nullptr;
+  std::vector<__bf16 *> Wb;      // bf16 copies of W_l [out][in]
   std::vector<float *> Z;        // pre-activations, [B][w_{l+1}]
-  std::vector<__bf16 *> H, HT;   // activations of layer outputs (hidden)
+  std::vector<__bf16 *> H;       // hidden activations, [B][w_{l+1}]
   std::vector<float *> dZ;
-  std::vector<__bf16 *> dZb, dZT;
+  std::vector<__bf16 *> dZb;
   float *dH = nullptr;           // [B][max width]
-  float *partial = nullptr;
+  float *split = nullptr;        // split-K partial sums of one weight gradient
+  float *partial = nullptr;      // loss partial sums
   int adam_t = 0;
   hipStream_t stream = nullptr;
 };
@@ -200,32 +261,28 @@ size_t mlp_layout(thor_mlp *M, char *base) {
   };
   const int B = M->max_batch, nl = M->nl;
   int wmax = 0;
+  size_t wprod = 0;
   for (int x : M->w) wmax = std::max(wmax, x);
+  for (int l = 0; l < nl; ++l) wprod = std::max(wprod, (size_t)M->w[l] * M->w[l + 1]);
   M->p = (float *)take(M->n_params * 4);
   M->g = (float *)take(M->n_params * 4);
   M->m = (float *)take(M->n_params * 4);
   M->v = (float *)take(M->n_params * 4);
   M->Wb.assign(nl, nullptr);
-  M->WT.assign(nl, nullptr);
   M->Z.assign(nl, nullptr);
   M->H.assign(nl, nullptr);
-  M->HT.assign(nl, nullptr);
   M->dZ.assign(nl, nullptr);
   M->dZb.assign(nl, nullptr);
-  M->dZT.assign(nl, nullptr);
   for (int l = 0; l < nl; ++l) {
     const size_t wsz = (size_t)M->w[l] * M->w[l + 1];
     M->Wb[l] = (__bf16 *)take(wsz * 2);
-    M->WT[l] = (__bf16 *)take(wsz * 2);
     M->Z[l] = (float *)take((size_t)B * M->w[l + 1] * 4);
     M->H[l] = (__bf16 *)take((size_t)B * M->w[l + 1] * 2);
-    M->HT[l] = (__bf16 *)take((size_t)B * M->w[l + 1] * 2);
     M->dZ[l] = (float *)take((size_t)B * M->w[l + 1] * 4);
     M->dZb[l] = (__bf16 *)take((size_t)B * M->w[l + 1] * 2);
-    M->dZT[l] = (__bf16 *)take((size_t)B * M->w[l + 1] * 2);
   }
-  M->XT = (__bf16 *)take((size_t)B * M->w[0] * 2);
   M->dH = (float *)take((size_t)B * wmax * 4);
+  M->split = (float *)take(std::max((size_t)kMaxSplit * wprod, (size_t)kBiasSplit * wmax) * 4);
   M->partial = (float *)take((size_t)nb((size_t)B * M->w[nl]) * 4);
   return off;
 }
@@ -258,27 +315,35 @@ bool mlp_shape(thor_mlp *M, int n_layers, const int *widths, int max_batch) {
 void refresh_bf16(thor_mlp *M) {
   for (int l = 0; l < M->nl; ++l) {
     const size_t n = (size_t)M->w[l] * M->w[l + 1];
-    hipLaunchKernelGGL(k_weights_bf16, dim3(nb(n)), dim3(256), 0, M->stream, M->p + M->woff[l], M->Wb[l],
-                       M->WT[l], M->w[l + 1], M->w[l]);
+    hipLaunchKernelGGL(k_weights_bf16, dim3(nb(n)), dim3(256), 0, M->stream, M->p + M->woff[l], M->Wb[l], n);
   }
 }
 
-void gemm(const __bf16 *A, const __bf16 *B, float *C, const float *bias, int Mr, int N, int K, int ldc,
-          hipStream_t s) {
-  dim3 grid((Mr + kTile - 1) / kTile, (N + kTile - 1) / kTile);
-  hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, s, A, B, C, bias, Mr, N, K, ldc);
+// C[M][N] = sum_k A(m, k) B(n, k); see k_gemm for the operand forms.
+template <bool AK, bool BK, int EPI>
+void gemm(const __bf16 *A, int lda, const __bf16 *B, int ldb, float *C, int ldc, const float *bias, __bf16 *H,
+          int Mr, int N, int K, int splits, hipStream_t s) {
+  const int chunk = ((K + splits - 1) / splits + kStepK - 1) / kStepK * kStepK;
+  const int S = (K + chunk - 1) / chunk;
+  dim3 grid((Mr + kTile - 1) / kTile, (N + kTile - 1) / kTile, S);
+  hipLaunchKernelGGL((k_gemm<AK, BK, EPI>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, bias, H, Mr, N, K, chunk);
 }
 
-void forward(thor_mlp *M, const __bf16 *X, int B, bool need_t) {
+// Number of batch chunks of a weight gradient: chunks of at least 256 rows.
+int grad_splits(int B) { return std::max(1, std::min(kMaxSplit, B / 256)); }
+
+// Forward pass; the output layer's pre-activation goes to y if given, else
+// to Z[nl - 1].
+void forward(thor_mlp *M, const __bf16 *X, int B, float *y) {
   const __bf16 *in = X;
   for (int l = 0; l < M->nl; ++l) {
     const int K = M->w[l], N = M->w[l + 1];
-    gemm(in, M->Wb[l], M->Z[l], M->p + M->boff[l], B, N, K, N, M->stream);
-    const bool hidden = l + 1 < M->nl;
-    if (hidden) {
-      hipLaunchKernelGGL(k_activate, dim3(nb((size_t)B * N)), dim3(256), 0, M->stream, M->Z[l], M->H[l],
-                         need_t ? M->HT[l] : nullptr, B, N, 1);
+    const float *bias = M->p + M->boff[l];
+    if (l + 1 < M->nl) {
+      gemm<false, false, EPI_GELU>(in, K, M->Wb[l], K, M->Z[l], N, bias, M->H[l], B, N, K, 1, M->stream);
       in = M->H[l];
+    } else {
+      gemm<false, false, EPI_STORE>(in, K, M->Wb[l], K, y ? y : M->Z[l], N, bias, nullptr, B, N, K, 1, M->stream);
     }
   }
 }
@@ -287,21 +352,26 @@ void forward(thor_mlp *M, const __bf16 *X, int B, bool need_t) {
 void backward(thor_mlp *M, const __bf16 *X, const float *T, int B) {
   const int nl = M->nl;
   hipStream_t s = M->stream;
-  hipLaunchKernelGGL(k_transpose_bf16, dim3(nb((size_t)B * M->w[0])), dim3(256), 0, s, X, M->XT, B, M->w[0]);
   const int No = M->w[nl];
   hipLaunchKernelGGL(k_loss, dim3(nb((size_t)B * No)), dim3(256), 0, s, M->Z[nl - 1], T, M->dZ[nl - 1],
-                     M->dZb[nl - 1], M->dZT[nl - 1], M->partial, B, No);
+                     M->dZb[nl - 1], M->partial, B, No);
+  const int S = grad_splits(B);
   for (int l = nl - 1; l >= 0; --l) {
     const int K = M->w[l], N = M->w[l + 1];
-    const __bf16 *prevT = l == 0 ? M->XT : M->HT[l - 1];
-    // dW[N][K] = dZ^T H_prev
-    gemm(M->dZT[l], prevT, M->g + M->woff[l], nullptr, N, K, B, K, s);
-    hipLaunchKernelGGL(k_bias_grad, dim3(nb(N)), dim3(256), 0, s, M->dZ[l], M->g + M->boff[l], B, N);
+    const __bf16 *prev = l == 0 ? X : M->H[l - 1];
+    // dW[N][K] = dZ^T H_prev: both operands read with the batch as outer index
+    gemm<true, true, EPI_STORE>(M->dZb[l], N, prev, K, M->split, K, nullptr, nullptr, N, K, B, S, s);
+    const size_t nw = (size_t)N * K;
+    hipLaunchKernelGGL(k_reduce, dim3(nb(nw)), dim3(256), 0, s, M->split, S, nw, M->g + M->woff[l]);
+    // db[N] = column sums of dZ
+    const int rows = (B + kBiasSplit - 1) / kBiasSplit;
+    hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64, kBiasSplit), dim3(256), 0, s, M->dZ[l], B, N, rows, M->split);
+    hipLaunchKernelGGL(k_reduce, dim3(nb(N)), dim3(256), 0, s, M->split, kBiasSplit, (size_t)N, M->g + M->boff[l]);
     if (l > 0) {
-      // dH[B][K] = dZ W, then through the activation of layer l-1
-      gemm(M->dZb[l], M->WT[l], M->dH, nullptr, B, K, N, K, s);
-      hipLaunchKernelGGL(k_act_grad, dim3(nb((size_t)B * K)), dim3(256), 0, s, M->dH, M->Z[l - 1], M->dZ[l - 1],
-                         M->dZb[l - 1], M->dZT[l - 1], B, K);
+      // dH[B][K] = dZ W, W read as [k = out][n = in]; then through the activation
+      gemm<false, true, EPI_STORE>(M->dZb[l], N, M->Wb[l], K, M->dH, K, nullptr, nullptr, B, K, N, 1, s);
+      const size_t n = (size_t)B * K;
+      hipLaunchKernelGGL(k_act_grad, dim3(nb(n)), dim3(256), 0, s, M->dH, M->Z[l - 1], M->dZ[l - 1], M->dZb[l - 1], n);
     }
   }
 }
@@ -393,17 +463,15 @@ int thor_mlp_forward(thor_mlp *m, const void *x_bf16, int B, float *y) {
   clear_error();
   if (!m || !x_bf16 || !y) { set_error("thor_mlp_forward: NULL argument"); return THOR_EINVAL; }
   if (B < 1 || B > m->max_batch) { set_error("thor_mlp_forward: batch outside 1..max_batch"); return THOR_EINVAL; }
-  forward(m, (const __bf16 *)x_bf16, B, false);
-  const int No = m->w[m->nl];
-  return mlp_ok(hipMemcpyAsync(y, m->Z[m->nl - 1], (size_t)B * No * 4, hipMemcpyDeviceToDevice, m->stream), "copy y")
-             ? THOR_OK : THOR_EHIP;
+  forward(m, (const __bf16 *)x_bf16, B, y);
+  return mlp_ok(hipGetLastError(), "mlp forward") ? THOR_OK : THOR_EHIP;
 }
 
 int thor_mlp_loss_grad(thor_mlp *m, const void *x_bf16, const float *t, int B, double *loss, float *grad_host) {
   clear_error();
   if (!m || !x_bf16 || !t) { set_error("thor_mlp_loss_grad: NULL argument"); return THOR_EINVAL; }
   if (B < 1 || B > m->max_batch || B % 32) { set_error("thor_mlp_loss_grad: batch must be a multiple of 32 within max_batch"); return THOR_EINVAL; }
-  forward(m, (const __bf16 *)x_bf16, B, true);
+  forward(m, (const __bf16 *)x_bf16, B, nullptr);
   backward(m, (const __bf16 *)x_bf16, t, B);
   const size_t np = nb((size_t)B * m->w[m->nl]);
   std::vector<float> part(np);
@@ -422,7 +490,7 @@ int thor_mlp_train_step(thor_mlp *m, const void *x_bf16, const float *t, int B, 
   clear_error();
   if (!m || !x_bf16 || !t) { set_error("thor_mlp_train_step: NULL argument"); return THOR_EINVAL; }
   if (B < 1 || B > m->max_batch || B % 32 || !(lr > 0)) { set_error("thor_mlp_train_step: batch must be a multiple of 32 within max_batch, lr > 0"); return THOR_EINVAL; }
-  forward(m, (const __bf16 *)x_bf16, B, true);
+  forward(m, (const __bf16 *)x_bf16, B, nullptr);
   backward(m, (const __bf16 *)x_bf16, t, B);
   m->adam_t += 1;
   const float b1 = 0.9f, b2 = 0.999f;
