@@ -180,7 +180,10 @@ def run_corrector_mlp(reps=20):
     """The corrector network at the g5 L32 shape (inputs 7 columns x 5 fields
     x 32 levels, three hidden layers of 256, 160 outputs): one inference pass
     over all 10242 coarse columns and one training step on 4096 columns, as
-    matrix-core FLOP/s against the dense BF16 peak."""
+    matrix-core FLOP/s against the dense BF16 peak.  At this shape inference
+    moves ~61 MB for 9.4 GFLOP (~150 flop/byte, under the ~310 flop/byte
+    ridge of 2.5 PFLOP/s over 8 TB/s), so its bound is HBM: its GB/s is
+    reported too.  Times are host-launched (HIP events around 20 calls)."""
     import torch
     from paper_1607_05535_amd import thor
     widths = [1120, 256, 256, 256, 160]
@@ -207,8 +210,13 @@ def run_corrector_mlp(reps=20):
 
     t_inf = timed(lambda: net.forward(x, y))
     t_tr = timed(lambda: net.train_step(x[:n_train], t, 1e-4))
+    # inference traffic: inputs, weights, each hidden activation written and
+    # read once (bf16), outputs written (fp32)
+    b_inf = (2.0 * n_inf * widths[0] + sum(2.0 * i * o + 4.0 * o for i, o in pairs)
+             + sum(4.0 * n_inf * o for o in widths[1:-1]) + 4.0 * n_inf * widths[-1])
     return {"widths": widths,
             "inference_rows": n_inf, "inference_ms": t_inf * 1e3,
+            "inference_bytes": b_inf, "inference_GBs": b_inf / t_inf / 1e9,
             "inference_TFLOPs": f_fwd * n_inf / t_inf / 1e12,
             "train_rows": n_train, "train_step_ms": t_tr * 1e3,
             "train_TFLOPs": f_train * n_train / t_tr / 1e12,

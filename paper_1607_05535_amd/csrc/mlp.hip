@@ -28,54 +28,56 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 64;    // C tile per workgroup (4 wavefronts of 32 x 32)
-constexpr int kStepK = 32;   // k per MFMA step
+constexpr int kStepK = 64;   // k per staged tile (two MFMA k-steps of 32)
 constexpr int kRow = kStepK + 8;   // LDS row of a staged tile (bf16), padded
 constexpr int kMaxSplit = 8;       // batch chunks of the weight gradient
-constexpr int kBiasSplit = 16;     // batch chunks of the bias gradient
+constexpr int kBiasSplit = 32;     // batch chunks of the bias gradient
 
-enum Epilogue { EPI_STORE = 0, EPI_GELU = 1 };
+enum Epilogue { EPI_STORE = 0, EPI_GELU = 1, EPI_GELU_ONLY = 2 };
 
 __device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad_f(float z) {
   return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
-// One 16-byte piece of a 64 x 32 operand tile per thread (256 threads), read
-// from global memory: rows r0.. of an operand with `rows` rows.  KOUTER:
+// Piece h (0, 1) of a 64 x 64 operand tile, 16 bytes per thread (256
+// threads), read from global memory: rows r0.. of an operand with `rows`
+// rows, k from k0, zero at k >= k_hi (k_hi a multiple of 32).  KOUTER:
 // stored [k][row] with leading dimension ld, else [row][k].
 template <bool KOUTER>
-__device__ __forceinline__ bf16x8 tile_load(const __bf16 *P, int ld, int rows, int r0, int k0) {
+__device__ __forceinline__ bf16x8 tile_load(const __bf16 *P, int ld, int rows, int r0, int k0, int k_hi, int h) {
   const int t = threadIdx.x;
   const bf16x8 zero = {};
   if (!KOUTER) {
-    const int row = r0 + (t >> 2), kc = (t & 3) * 8;
-    return row < rows ? *reinterpret_cast<const bf16x8 *>(P + (size_t)row * ld + k0 + kc) : zero;
+    const int row = r0 + (t >> 2), k = k0 + (t & 3) * 16 + 8 * h;
+    return row < rows && k < k_hi ? *reinterpret_cast<const bf16x8 *>(P + (size_t)row * ld + k) : zero;
   } else {
-    const int kr = t >> 3, rc = r0 + (t & 7) * 8;   // rows is a multiple of 8
-    return rc < rows ? *reinterpret_cast<const bf16x8 *>(P + (size_t)(k0 + kr) * ld + rc) : zero;
+    const int k = k0 + (t >> 3) + 32 * h, rc = r0 + (t & 7) * 8;   // rows is a multiple of 8
+    return rc < rows && k < k_hi ? *reinterpret_cast<const bf16x8 *>(P + (size_t)k * ld + rc) : zero;
   }
 }
 
 // The same piece into the LDS tile S[row][k] (rows of kRow values).
 template <bool KOUTER>
-__device__ __forceinline__ void tile_store(__bf16 *S, const bf16x8 v) {
+__device__ __forceinline__ void tile_store(__bf16 *S, const bf16x8 v, int h) {
   const int t = threadIdx.x;
   if (!KOUTER) {
-    *reinterpret_cast<bf16x8 *>(S + (t >> 2) * kRow + (t & 3) * 8) = v;
+    *reinterpret_cast<bf16x8 *>(S + (t >> 2) * kRow + (t & 3) * 16 + 8 * h) = v;
   } else {
-    const int kr = t >> 3, rc = (t & 7) * 8;
+    const int kr = (t >> 3) + 32 * h, rc = (t & 7) * 8;
 #pragma unroll
     for (int i = 0; i < 8; ++i) S[(rc + i) * kRow + kr] = v[i];
   }
 }
 
 // C tile (m0, n0) of the product over k in [k_lo, k_hi), 4 wavefronts, LDS
-// double-buffered.  Wavefront w owns rows 32 (w / 2) .. + 31 and columns
+// double-buffered in tiles of 64 k.  Wavefront w owns rows 32 (w / 2) .. + 31 and columns
 // 32 (w % 2) .. + 31 of the tile as 2 x 2 MFMA tiles of 16 x 16; lane l holds
 // A(row l % 16, k0 + 8 (l / 16) .. + 7), B(col l % 16, same k) and
 // accumulates D[4 (l / 16) + i][l % 16], i = 0..3.
 //   EPI_STORE: C = acc (+ bias), or the split's partial C + z M ldc.
 //   EPI_GELU:  C = acc + bias (pre-activation), H = gelu(C) in bf16.
+//   EPI_GELU_ONLY: H only (inference keeps no pre-activation).
 template <bool AK, bool BK, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, int lda, const __bf16 *__restrict__ B,
                                               int ldb, float *__restrict__ C, int ldc, const float *__restrict__ bias,
@@ -94,30 +96,43 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, int 
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   int buf = 0;
   if (k_lo < k_hi) {
-    tile_store<AK>(As[0], tile_load<AK>(A, lda, M, m0, k_lo));
-    tile_store<BK>(Bs[0], tile_load<BK>(B, ldb, N, n0, k_lo));
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      tile_store<AK>(As[0], tile_load<AK>(A, lda, M, m0, k_lo, k_hi, h), h);
+      tile_store<BK>(Bs[0], tile_load<BK>(B, ldb, N, n0, k_lo, k_hi, h), h);
+    }
   }
   __syncthreads();
   for (int k0 = k_lo; k0 < k_hi; k0 += kStepK) {
     const bool more = k0 + kStepK < k_hi;
-    bf16x8 na, nbv;
+    bf16x8 na[2], nbv[2];
     if (more) {
-      na = tile_load<AK>(A, lda, M, m0, k0 + kStepK);
-      nbv = tile_load<BK>(B, ldb, N, n0, k0 + kStepK);
-    }
-    bf16x8 a[2], b[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      a[i] = *reinterpret_cast<const bf16x8 *>(&As[buf][(wm + 16 * i + r) * kRow + kq]);
-      b[i] = *reinterpret_cast<const bf16x8 *>(&Bs[buf][(wn + 16 * i + r) * kRow + kq]);
+      for (int h = 0; h < 2; ++h) {
+        na[h] = tile_load<AK>(A, lda, M, m0, k0 + kStepK, k_hi, h);
+        nbv[h] = tile_load<BK>(B, ldb, N, n0, k0 + kStepK, k_hi, h);
+      }
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int kk = 0; kk < kStepK; kk += 32) {
+      bf16x8 a[2], b[2];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < 2; ++i) {
+        a[i] = *reinterpret_cast<const bf16x8 *>(&As[buf][(wm + 16 * i + r) * kRow + kk + kq]);
+        b[i] = *reinterpret_cast<const bf16x8 *>(&Bs[buf][(wn + 16 * i + r) * kRow + kk + kq]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
     if (more) {
-      tile_store<AK>(As[buf ^ 1], na);
-      tile_store<BK>(Bs[buf ^ 1], nbv);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        tile_store<AK>(As[buf ^ 1], na[h], h);
+        tile_store<BK>(Bs[buf ^ 1], nbv[h], h);
+      }
     }
     __syncthreads();
     buf ^= 1;
@@ -135,8 +150,8 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, int 
         const int row = m0 + wm + 16 * i + (lane >> 4) * 4 + q;
         if (row >= M) continue;
         const float z = acc[i][j][q] + bb;
-        Cz[(size_t)row * ldc + col] = z;
-        if (EPI == EPI_GELU) H[(size_t)row * N + col] = (__bf16)gelu_f(z);
+        if (EPI != EPI_GELU_ONLY) Cz[(size_t)row * ldc + col] = z;
+        if (EPI != EPI_STORE) H[(size_t)row * N + col] = (__bf16)gelu_f(z);
       }
     }
 }
@@ -332,15 +347,18 @@ void gemm(const __bf16 *A, int lda, const __bf16 *B, int ldb, float *C, int ldc,
 // Number of batch chunks of a weight gradient: chunks of at least 256 rows.
 int grad_splits(int B) { return std::max(1, std::min(kMaxSplit, B / 256)); }
 
-// Forward pass; the output layer's pre-activation goes to y if given, else
-// to Z[nl - 1].
+// Forward pass; the output layer's pre-activation goes to y if given
+// (inference: hidden pre-activations are not kept), else to Z[nl - 1].
 void forward(thor_mlp *M, const __bf16 *X, int B, float *y) {
   const __bf16 *in = X;
   for (int l = 0; l < M->nl; ++l) {
     const int K = M->w[l], N = M->w[l + 1];
     const float *bias = M->p + M->boff[l];
     if (l + 1 < M->nl) {
-      gemm<false, false, EPI_GELU>(in, K, M->Wb[l], K, M->Z[l], N, bias, M->H[l], B, N, K, 1, M->stream);
+      if (y)
+        gemm<false, false, EPI_GELU_ONLY>(in, K, M->Wb[l], K, M->Z[l], N, bias, M->H[l], B, N, K, 1, M->stream);
+      else
+        gemm<false, false, EPI_GELU>(in, K, M->Wb[l], K, M->Z[l], N, bias, M->H[l], B, N, K, 1, M->stream);
       in = M->H[l];
     } else {
       gemm<false, false, EPI_STORE>(in, K, M->Wb[l], K, y ? y : M->Z[l], N, bias, nullptr, B, N, K, 1, M->stream);
