@@ -57,3 +57,50 @@ def test_rest_state_stays_at_rest_on_gpu():
     f = lib_fields(st, ("u", "v", "w"))
     for k, v in f.items():
         assert np.abs(v).max() < 1e-8, k
+
+
+def test_gas_giant_g6_l32_full_size_samples_after_one_step():
+    """The benchmark workload at full size (40962 columns x 32 levels) in the
+    benchmark's launch configuration (autotuned workgroup sizes, graph
+    replay of thor_step): after one large step the sampled cells equal the
+    oracle's stored values (tests/golden/gas_giant_g6l32_one_step.txt,
+    written by the script beside it from the oracle alone)."""
+    import os
+    from paper_1607_05535_amd import thor
+    path = os.path.join(os.path.dirname(__file__), "golden", "gas_giant_g6l32_one_step.txt")
+    rows, mass = [], None
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        parts = line.split()
+        if parts[0] == "mass":
+            mass = (float(parts[1]), float(parts[2]))
+        else:
+            rows.append([float(x) for x in parts])
+    S = np.array(rows)
+    cols, levs = S[:, 0].astype(int), S[:, 1].astype(int)
+    w = workloads.gas_giant_c2()
+    say(f"[parity] full size {w.name}: autotune, 1 graph-replayed large step, {len(S)} samples")
+    st = lib_state(w)
+    tuned = thor.thor_autotune(st.handle, w.n_acoustic)
+    say(f"         tuned {tuned}")
+    m0, rc = st.mass()
+    assert rc == 0 and abs(m0 / mass[0] - 1) < 1e-13
+    st.step(1, w.n_acoustic)
+    got = {}
+    for name in ("T", "u", "v", "w", "p", "rho"):
+        f, rc = st.field(name)
+        assert rc == 0
+        got[name] = f[cols, levs]
+    ref = dict(zip(("T", "u", "v", "w", "p", "rho"), S[:, 2:].T))
+    speed = np.sqrt(np.mean(ref["u"] ** 2 + ref["v"] ** 2 + ref["w"] ** 2))
+    errs = {}
+    for name in ("T", "p", "rho"):
+        errs[name] = float(np.max(np.abs(got[name] / ref[name] - 1)))
+    for name in ("u", "v", "w"):
+        errs[name] = float(np.max(np.abs(got[name] - ref[name])) / speed)
+    say(f"         max errors {errs}")
+    for k, e in errs.items():
+        assert e < TOL, (k, e)
+    m1, rc = st.mass()
+    assert rc == 0 and abs(m1 / mass[1] - 1) < 1e-12
