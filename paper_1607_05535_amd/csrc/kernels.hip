@@ -332,12 +332,14 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
   const double rhs_m = shfl(rhs, lm);
 
   const double dz = c.dz;
-  const double rI = radius_i(c, lev), rI1 = rI + dz, rIm = rI - dz;
-  const double rC = radius_c(c, lev), rCm = rC - dz;
-  const double ap = dtau * rI1 * rI1 / (rC * rC * dz);     // alpha+ of cell lev
-  const double am = dtau * rI * rI / (rC * rC * dz);       // alpha- of cell lev
-  const double ap_m = dtau * rI * rI / (rCm * rCm * dz);   // alpha+ of cell lev-1
-  const double am_m = dtau * rIm * rIm / (rCm * rCm * dz); // alpha- of cell lev-1
+  const double rI = radius_i(c, lev), rI1 = rI + dz;
+  const double rC = radius_c(c, lev);
+  const double irc2dz = 1.0 / (rC * rC * dz);
+  const double gp = rI1 * rI1 * irc2dz, gm = rI * rI * irc2dz;
+  const double ap = dtau * gp;         // alpha+ of cell lev
+  const double am = dtau * gm;         // alpha- of cell lev
+  const double ap_m = shfl(ap, lm);    // alpha+ of cell lev-1
+  const double am_m = shfl(am, lm);    // alpha- of cell lev-1
   const double c1 = dtau / dz, c2 = 0.5 * c.grav * dtau;
 
   double a = 0.0, b = 1.0, cc = 0.0, d = 0.0;
@@ -380,7 +382,7 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
     p = rho_new * c.Rd * Tn;
     rth_new = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
   }
-  const double D3 = Drho + (rI1 * rI1 * Wp - rI * rI * Wn) / (rC * rC * dz);
+  const double D3 = Drho + (gp * Wp - gm * Wn);
   if (ln.store) {
     f.rho[idx] = rho_new;
     f.rth[idx] = rth_new;
