@@ -492,17 +492,18 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
   {
     const H nx = shfl(Fx[0], lp), ny = shfl(Fy[0], lp), nz = shfl(Fz[0], lp);
     const H om2 = (H)(2.0 * c.omega);
+    const H idz = (H)(1.0 / c.dz);
 #pragma unroll
     for (int q = 0; q < kHq; ++q) {
       const int lev = lev0 + q;
-      const H rC = (H)radius_c(c, lev);
+      const H irc = (H)1 / (H)radius_c(c, lev);
       H Fx1 = q + 1 < kHq ? Fx[q + 1] : nx, Fy1 = q + 1 < kHq ? Fy[q + 1] : ny,
         Fz1 = q + 1 < kHq ? Fz[q + 1] : nz;
       if (lev == L - 1) Fx1 = Fy1 = Fz1 = 0;
-      Ax[q] /= rC;
-      Ay[q] /= rC;
-      Az[q] /= rC;
-      const H s = (H)1 / (rC * rC * (H)c.dz);
+      Ax[q] *= irc;
+      Ay[q] *= irc;
+      Az[q] *= irc;
+      const H s = irc * irc * idz;
       Ax[q] += (Fx1 - Fx[q]) * s;
       Ay[q] += (Fy1 - Fy[q]) * s;
       Az[q] += (Fz1 - Fz[q]) * s;
@@ -689,8 +690,8 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
     H ox[kHq], oy[kHq], oz[kHq];
 #pragma unroll
     for (int q = 0; q < kHq; ++q) {
-      const double rC = radius_c(c, lev0 + q);
-      const double x = gx[q] / rC, y = gy[q] / rC, z = gz[q] / rC;
+      const double irc = 1.0 / radius_c(c, lev0 + q);
+      const double x = gx[q] * irc, y = gy[q] * irc, z = gz[q] * irc;
       const double gr = x * rx + y * ry + z * rz;
       ox[q] = (H)(-(x - gr * rx));
       oy[q] = (H)(-(y - gr * ry));
@@ -724,9 +725,10 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
     for (int q = 0; q < kHq; ++q) {
       const int lev = lev0 + q;
       const double rC = radius_c(c, lev), rI = radius_i(c, lev);
+      const double irc = 1.0 / rC;
       const double W1 = lev == L - 1 ? 0.0 : (q + 1 < kHq ? W[q + 1] : W_n);
       const double Wl = lev == 0 ? 0.0 : W[q];
-      Dt[q] = (H)((double)dm[q] / rC + ((rI + c.dz) * (rI + c.dz) * W1 - rI * rI * Wl) / (rC * rC * c.dz));
+      Dt[q] = (H)((double)dm[q] * irc + ((rI + c.dz) * (rI + c.dz) * W1 - rI * rI * Wl) * (irc * irc / c.dz));
       // [t] vertical imbalance at interface lev
       const double pm = q ? p[q - 1] : p_m, rm = q ? rho[q - 1] : rho_m;
       FW[q] = lev == 0 ? 0.0 : -(p[q] - pm) / c.dz - 0.5 * c.grav * (rm + rho[q]);
