@@ -224,31 +224,63 @@ def run_corrector_mlp(reps=20):
             "inference_frac": f_fwd * n_inf / t_inf / 1e12 / BF16_PEAK_TFLOPS}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w):
     """The FP64 oracle on the host: one large step's worth estimated from a
     bounded sample (the per-step terms, one RK stage of slow terms and two
-    acoustic substeps), single thread."""
-    import numpy as np  # noqa: F401
+    acoustic substeps), with every BLAS/OpenMP pool held to one thread."""
+    from threadpoolctl import threadpool_limits
     from oracle import dynamics as odyn
     from oracle import grid as ogrid
     G = ogrid.Grid(w.glevel, k=100.0)
     model, st = odyn.model_from_workload(w, G)
-    t0 = time.perf_counter()
-    large = odyn.large_step_terms(model, st)
-    t1 = time.perf_counter()
-    f = odyn.slow_forcing(model, st, large)
-    t2 = time.perf_counter()
-    s = st
-    dtau = w.dt / w.n_acoustic
-    for _ in range(2):
-        s = odyn.acoustic_substep(model, s, f, dtau, large)
-    t3 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        large = odyn.large_step_terms(model, st)
+        t1 = time.perf_counter()
+        f = odyn.slow_forcing(model, st, large)
+        t2 = time.perf_counter()
+        s = st
+        dtau = w.dt / w.n_acoustic
+        for _ in range(2):
+            s = odyn.acoustic_substep(model, s, f, dtau, large)
+        t3 = time.perf_counter()
     t_large = (t1 - t0) + 3 * (t2 - t1) + w.substeps_per_large * (t3 - t2) / 2
     value = w.cells * w.substeps_per_large / t_large
     return dict(value=value, unit="cell-updates/s", cores=1, kind="oracle",
                 sample=(f"{w.name}: per-step terms + 1 slow stage + 2 acoustic substeps "
                         f"({t3 - t0:.1f} s), extrapolated to one large step "
-                        f"({t_large:.1f} s: 1 + 3 slow + {w.substeps_per_large} substeps)"))
+                        f"({t_large:.1f} s: 1 + 3 slow + {w.substeps_per_large} substeps)"),
+                cpu_model=cpu_model(), host_cpus=os.cpu_count())
+
+
+def copy_GBs():
+    """Read + write GB/s of a plain 1 GiB device copy on this GPU."""
+    import torch
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 10 * 1e-3
+    del src, dst
+    torch.cuda.empty_cache()
+    return 16.0 * n / t / 1e9
 
 
 def copy_probe():
@@ -297,6 +329,7 @@ def main():
     updates = w.cells * subs * args.steps
 
     T64, kt64, sc64, tuned64 = run_gpu(w, 0, args.steps, args.warmup)
+    copy_bw = copy_GBs()
     value = updates / T64
     vmean = kt64["vert"][0] * 1e-3
     vb = vert_bytes_per_cell(w.n_lev, False) * w.cells
@@ -321,7 +354,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "vert (acoustic phase V)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(),
-                     "bytes_per_launch": vb, "mean_launch_ms": kt64["vert"][0]},
+                     "bytes_per_launch": vb, "mean_launch_ms": kt64["vert"][0],
+                     "copy_GBs": copy_bw, "frac_of_copy": achieved / copy_bw},
+        # phase M + phase V kernel time per substep, as cell-updates/s
+        "kernel_only_substep_value": w.cells / ((kt64["vert"][0] + kt64["hmom"][0]) * 1e-3),
         "kernel_ms": {k: v[0] for k, v in kt64.items()},
         "achieved_GBs": achieved_gbs(w, kt64, False),
         "autotuned_wavefronts_per_workgroup": tuned64,
