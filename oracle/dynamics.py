@@ -68,11 +68,15 @@ class Numerics:
 
 @dataclass
 class Forcing:
-    kind: int = 0            # 0 none, 1 Newtonian relaxation
+    kind: int = 0            # 0 none, 1 Newtonian relaxation, 2 hot-Jupiter benchmark
     tau: float = 1.0e5
-    T_mean: float = 1300.0
-    dT_daynight: float = 500.0
+    T_mean: float = 1300.0   # kind 2: T_surf of T_vert
+    dT_daynight: float = 500.0   # kind 2: equator-to-pole difference Delta T_E-P
     lon_substellar: float = 0.0
+    lapse: float = 2.0e-4        # kind 2: Gamma_trop (K/m)
+    z_strat: float = 2.0e6       # kind 2: z_stra (m)
+    dT_strat: float = 10.0       # kind 2: Delta T_stra (K)
+    sigma_strat: float = 0.12    # kind 2: sigma_stra
 
 
 @dataclass
@@ -380,16 +384,45 @@ def large_step_terms(model, st):
                 H_rth=H_rth, G_t=G_t, I=I)
 
 
+def t_vert(f, z):
+    """Eq. tvert: the hot-Jupiter vertical temperature profile at heights z."""
+    zs, lap = f.z_strat, f.lapse
+    trop = f.T_mean - lap * (zs + (z - zs) / 2.0) + np.sqrt((lap * (z - zs) / 2.0) ** 2 + f.dT_strat ** 2)
+    return np.where(z <= zs, trop, f.T_mean - lap * zs + f.dT_strat)
+
+
+def surface_pressure(model, p, T):
+    """Sec. 5: surface pressure of each column, the lowest cell's pressure
+    carried hydrostatically down to z = 0 at that cell's temperature."""
+    pl = model.planet
+    return p[:, 0] * np.exp(pl.gravity * model.zC[0] / (pl.Rd * T[:, 0]))
+
+
+def hot_jupiter_teq(model, p, T):
+    """Eqs. teq-hj and btrop: T_eq = T_vert + beta_trop Delta T_E-P cos(lambda
+    - lambda_ss) cos(phi), with sigma = p / p_s of the dynamics output."""
+    f = model.forcing
+    z = model.zC[None, :]
+    sigma = p / surface_pressure(model, p, T)[:, None]
+    beta = np.where(z <= f.z_strat,
+                    np.sin(np.pi * (sigma - f.sigma_strat) / (2.0 * (1.0 - f.sigma_strat))), 0.0)
+    lam, phi = lon_lat(model.rhat)
+    h = np.cos(lam - f.lon_substellar) * np.cos(phi)
+    return t_vert(f, z) + beta * f.dT_daynight * h[:, None]
+
+
 def newtonian(model, st):
-    """Eq. im_eq_t with constant K_T = 1/tau at fixed density."""
+    """Eq. im_eq_t with constant K_T = 1/tau at fixed density; T_eq from the
+    day/night recipe (kind 1) or the hot-Jupiter benchmark (kind 2)."""
     f, pl = model.forcing, model.planet
-    if f.kind != 1:
+    if f.kind not in (1, 2):
         return st
     dt = model.num.dt
     p = model.eos(st.rth)
     T = p / (st.rho * pl.Rd)
     kt = dt / f.tau
-    Tn = (T + kt * model.Teq) / (1.0 + kt)
+    Teq = model.Teq if f.kind == 1 else hot_jupiter_teq(model, p, T)
+    Tn = (T + kt * Teq) / (1.0 + kt)
     rth = model.rth_from_p(st.rho * pl.Rd * Tn)
     return State(st.rho, st.M, rth, st.W)
 
@@ -438,7 +471,8 @@ def model_from_workload(w, G):
     planet = Planet(w.radius, w.omega, w.gravity, w.Rd, w.Cp, w.p_ref)
     vert = Vertical(w.n_lev, w.z_top)
     num = Numerics(w.dt, w.diff_D, w.div_damp)
-    forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar)
+    forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar,
+                      w.lapse, w.z_strat, w.dT_strat, w.sigma_strat)
     model = Model(G, planet, vert, num, forcing)
     st = init_state(model, Init(w.T0, w.p_surf, w.noise_amp, w.seed))
     return model, st

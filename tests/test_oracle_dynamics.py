@@ -291,3 +291,77 @@ def test_kd_matches_table1_damping_times():
                          dy.Numerics(dt, D))
         dbar2 = grid.mean_spacing(2, A)
         assert abs(dbar2 ** 4 / (32 * model.Kd) / tau - 1) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Hot-Jupiter benchmark forcing (Sec. 5, Eqs. teq-hj, btrop, tvert)
+# ---------------------------------------------------------------------------
+
+def test_hot_jupiter_vertical_profile_closed_forms():
+    """Eq. tvert with the printed constants: continuous at z_stra, constant
+    T_surf - Gamma z_stra + Delta T_stra above it (1210 K), and at the
+    ground T_surf - Gamma z_stra / 2 + sqrt((Gamma z_stra / 2)^2 + Delta T^2)."""
+    f = dy.Forcing(kind=2, tau=1.5e5, T_mean=1600.0, dT_daynight=300.0)
+    zs = f.z_strat
+    assert abs(dy.t_vert(f, np.array([zs]))[0] - 1210.0) < 1e-9
+    assert np.all(dy.t_vert(f, np.array([zs + 1.0, 3e6, 4.875e6])) == 1210.0)
+    assert abs(dy.t_vert(f, np.array([zs * (1 - 1e-12)]))[0] - 1210.0) < 1e-6
+    assert abs(dy.t_vert(f, np.array([0.0]))[0] - (1400.0 + np.sqrt(200.0 ** 2 + 100.0))) < 1e-9
+    # monotone cooling through the troposphere
+    z = np.linspace(0.0, zs, 200)
+    assert np.all(np.diff(dy.t_vert(f, z)) < 0)
+
+
+def test_surface_pressure_of_the_hydrostatic_initial_state():
+    """Sec. 5 extrapolation at constant temperature recovers the surface
+    pressure the discrete hydrostatic isothermal state was built from."""
+    w = workloads.hot_jupiter(glevel=2, n_lev=37)
+    model, st = dy.model_from_workload(w, oracle_grid(2))
+    f = dy.fields(model, st)
+    ps = dy.surface_pressure(model, f["p"], f["T"])
+    assert np.abs(ps / w.p_surf - 1).max() < 1e-13
+
+
+def test_hot_jupiter_teq_special_cases():
+    """Eq. btrop: beta = sin(pi (sigma - sigma_stra) / (2 (1 - sigma_stra)))
+    in the lowest cell (sigma from the extrapolated surface pressure), 0 at
+    sigma = sigma_stra and above z_stra; Eq. teq-hj then gives T_vert +
+    beta Delta T_E-P cos(lon) cos(lat), T_vert, and the stratosphere's T_vert."""
+    w = workloads.hot_jupiter(glevel=2, n_lev=37)
+    model, st = dy.model_from_workload(w, oracle_grid(2))
+    fc = model.forcing
+    N, L = model.G.n, w.n_lev
+    T = np.full((N, L), 1500.0)
+    ps = 2.0e7
+    z = model.zC
+    # pressures chosen so that sigma = 1 in level 0 and sigma = sigma_stra in level 1
+    p = np.empty((N, L))
+    p0 = ps * np.exp(-w.gravity * z[0] / (w.Rd * 1500.0))
+    p[:, 0] = p0
+    p[:, 1] = fc.sigma_strat * ps
+    p[:, 2:] = 1.0e5
+    Teq = dy.hot_jupiter_teq(model, p, T)
+    lam, phi = dy.lon_lat(model.rhat)
+    h = np.cos(lam) * np.cos(phi)
+    tv = dy.t_vert(fc, z)
+    sig0 = p0 / ps
+    beta0 = np.sin(np.pi * (sig0 - fc.sigma_strat) / (2 * (1 - fc.sigma_strat)))
+    assert np.abs(Teq[:, 0] - (tv[0] + beta0 * 300.0 * h)).max() < 1e-9
+    assert 0.0 < beta0 <= 1.0   # sigma < 1 at the lowest cell centre
+    assert np.abs(Teq[:, 1] - tv[1]).max() < 1e-9
+    above = z > fc.z_strat
+    assert above.any() and np.all(Teq[:, above] == 1210.0)
+
+
+def test_hot_jupiter_relaxation_is_backward_euler():
+    """Eq. im_eq_t with the benchmark's T_eq of the dynamics output."""
+    w = workloads.hot_jupiter(glevel=2, n_lev=37, noise_amp=0.5)
+    model, st = dy.model_from_workload(w, oracle_grid(2))
+    f0 = dy.fields(model, st)
+    Teq = dy.hot_jupiter_teq(model, f0["p"], f0["T"])
+    out = dy.newtonian(model, st)
+    T1 = dy.fields(model, out)["T"]
+    lhs = (T1 - f0["T"]) / model.num.dt
+    rhs = (Teq - T1) / model.forcing.tau
+    assert np.abs(lhs - rhs).max() < 1e-9 * np.abs(rhs).max()
+    assert np.array_equal(out.rho, st.rho)

@@ -46,6 +46,10 @@ class Workload:
     T_mean: float = 0.0
     dT_daynight: float = 0.0
     lon_substellar: float = 0.0
+    lapse: float = 2.0e-4
+    z_strat: float = 2.0e6
+    dT_strat: float = 10.0
+    sigma_strat: float = 0.12
     extra: dict = field(default_factory=dict)
 
     @property
@@ -133,6 +137,21 @@ def ensemble(n=64, seed=4, glevels=(4, 5, 6), levels=(20, 32, 48), n_acoustic=8)
                             dt, n_acoustic, 1, D_EARTH, True, T0, 1.0e5, 0.1,
                             seed * 1000 + i))
     return out
+
+
+def hot_jupiter(glevel=5, n_lev=37, n_large=1, dt=600.0, n_acoustic=8, noise_amp=0.0, seed=5):
+    """The hot-Jupiter benchmark of Sec. 5 (Eqs. teq-hj, btrop, tvert): Table 1
+    planet (radius 1e8 m, rotation 2.1e-5 1/s, gravity 8, cp 13226.5,
+    Rd 3779), 37 layers to 4875 km, isothermal 1600 K at rest, Newtonian
+    relaxation with timescale 1.5e5 s toward T_vert + beta_trop 300 K
+    cos(lon) cos(lat) (T_surf 1600 K, lapse 2e-4 K/m, z_stra 2000 km,
+    Delta T_stra 10 K, sigma_stra 0.12), no boundary-layer friction, large
+    step 600 s, diffusion timescale 941.2 s.  Surface pressure 2.2e7 Pa
+    (not given for this test; the gas-giant recipes' value)."""
+    return Workload(f"g{glevel}L{n_lev}-hotjupiter", glevel, n_lev, 4.875e6, 1.0e8, 2.1e-5, 8.0,
+                    3779.0, 13226.5, 1.0e5, dt, n_acoustic, n_large, D_HOT_JUPITER, True, 1600.0,
+                    2.2e7, noise_amp, seed, forcing_kind=2, tau=1.5e5, T_mean=1600.0,
+                    dT_daynight=300.0, lon_substellar=0.0)
 
 
 def corrector_pair(fine_glevel=7, coarse_glevel=5, n_lev=32, dt_coarse=600.0, ratio=4, base_seed=1000):
