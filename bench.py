@@ -135,6 +135,18 @@ def mixed_one_day():
             "seconds_fp64": times[0], "seconds_mixed": times[1], "speedup": times[0] / times[1]}
 
 
+def run_hot_jupiter(steps, warmup):
+    """The hot-Jupiter benchmark of Sec. 5 at its own size (g5, 10242 columns
+    x 37 layers, 600 s steps, 8 substeps), FP64, autotuned."""
+    import workloads
+    w = workloads.hot_jupiter(glevel=5, n_lev=37)
+    T, kt, sc, tuned = run_gpu(w, 0, steps, warmup)
+    return {"workload": "hot-Jupiter benchmark g5 (10242 columns) x 37 levels, dt 600 s, n = 8",
+            "value": w.cells * w.substeps_per_large * steps / T, "unit": "cell-updates/s",
+            "ms_per_step": T / steps * 1e3, "max_speed": sc["max_speed"],
+            "kernel_ms": {k: v[0] for k, v in kt.items()}}
+
+
 def run_ensemble(steps, warmup):
     """The 64-planet ensemble advanced with one launch per phase, against the
     same planets advanced one after the other with the single-planet path."""
@@ -313,6 +325,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-one-day", action="store_true")
     ap.add_argument("--no-corrector", action="store_true")
+    ap.add_argument("--no-hot-jupiter", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -371,6 +384,8 @@ def main():
                         "kernel_ms": {k: v[0] for k, v in kt32.items()}}
         if not args.no_one_day:
             out["mixed"]["one_day"] = mixed_one_day()
+    if not args.no_hot_jupiter:
+        out["hot_jupiter"] = run_hot_jupiter(args.steps, args.warmup)
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble(max(1, args.steps // 10), 2)
     if not args.no_corrector:

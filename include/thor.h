@@ -141,14 +141,28 @@ typedef struct {
                       FP64 */
 } thor_numerics;
 
-enum { THOR_FORCING_NONE = 0, THOR_FORCING_NEWTONIAN = 1 };
+/* Physics after each large step (Sec. 5, Eq. im_eq_t): backward-Euler
+ * Newtonian relaxation of T at fixed density with K_T = 1/tau, toward
+ *   NEWTONIAN:   T_eq = T_mean + dT_daynight/2 cos(lat) cos(lon - lon_ss);
+ *   HOT_JUPITER: the hot-Jupiter benchmark, Eqs. teq-hj, btrop, tvert:
+ *                T_eq = T_vert(z) + beta_trop(sigma, z) dT_daynight
+ *                       cos(lon - lon_ss) cos(lat), T_vert with T_surf = T_mean,
+ *                lapse, z_strat, dT_strat; beta_trop with sigma_strat;
+ *                sigma = p / p_s, p_s the column's lowest-cell pressure
+ *                carried down to z = 0 hydrostatically at that cell's
+ *                temperature.  No boundary-layer friction. */
+enum { THOR_FORCING_NONE = 0, THOR_FORCING_NEWTONIAN = 1, THOR_FORCING_HOT_JUPITER = 2 };
 
 typedef struct {
   int kind;               /* THOR_FORCING_* */
   double tau;             /* relaxation time scale, K_T = 1/tau [s] */
-  double T_mean;          /* T_eq = T_mean + dT/2 cos(lat) cos(lon - lon_ss) */
-  double dT_daynight;     /* day/night contrast [K] */
+  double T_mean;          /* NEWTONIAN: mean T_eq; HOT_JUPITER: T_surf [K] */
+  double dT_daynight;     /* NEWTONIAN: day/night contrast; HOT_JUPITER: Delta T_E-P [K] */
   double lon_substellar;  /* [rad] */
+  double lapse;           /* HOT_JUPITER: Gamma_trop [K/m] */
+  double z_strat;         /* HOT_JUPITER: z_stra [m] */
+  double dT_strat;        /* HOT_JUPITER: Delta T_stra [K] */
+  double sigma_strat;     /* HOT_JUPITER: sigma_stra, in [0, 1) */
 } thor_forcing;
 
 typedef struct {

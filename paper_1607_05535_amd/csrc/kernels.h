@@ -29,7 +29,7 @@ struct Fields {
   const int32_t *ddi;     // [N][18] two-ring columns (-1 pad)
   const H *ddw;           // [N][18][3] lap(grad .) weights
   const double *area;     // [N]
-  const double *teq;      // [N] Newtonian target temperature
+  const double *teq;      // [N] Newtonian T_eq, or cos(lon - lon_ss) cos(lat) (hot Jupiter)
 
   // current small-step state
   double *rho, *rth, *W;  // [N][L]
@@ -66,6 +66,8 @@ struct Consts {
   int div_damp;
   int forcing;
   double tau;
+  // hot-Jupiter benchmark forcing (Eqs. teq-hj, btrop, tvert)
+  double hj_Tsurf, hj_dTep, hj_lapse, hj_zstrat, hj_dTstrat, hj_sstrat;
 };
 
 // Workgroups have 1, 2, 4 or 8 wavefronts (tuned per kernel family).

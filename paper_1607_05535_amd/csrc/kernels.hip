@@ -381,6 +381,28 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
     const double Tn = (T + kt * f.teq[col]) / (1.0 + kt);
     p = rho_new * c.Rd * Tn;
     rth_new = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
+  } else if (LAST && c.forcing == THOR_FORCING_HOT_JUPITER) {
+    // Eq. im_eq_t toward the hot-Jupiter T_eq (Eqs. teq-hj, btrop, tvert);
+    // sigma from the surface pressure the column's lowest cell implies at
+    // constant temperature
+    const double kt = c.dt / c.tau;
+    const double T = p / (rho_new * c.Rd);
+    const int l0 = ln.lane - lev;
+    const double p0 = shfl(p, l0), T0 = shfl(T, l0);
+    const double ps = p0 * exp(c.grav * (0.5 * dz) / (c.Rd * T0));
+    const double z = (lev + 0.5) * dz, zs = c.hj_zstrat;
+    double Teq;
+    if (z <= zs) {
+      const double a = c.hj_lapse * (z - zs) / 2.0;
+      const double tv = c.hj_Tsurf - c.hj_lapse * (zs + (z - zs) / 2.0) + sqrt(a * a + c.hj_dTstrat * c.hj_dTstrat);
+      const double beta = sin(M_PI * (p / ps - c.hj_sstrat) / (2.0 * (1.0 - c.hj_sstrat)));
+      Teq = tv + beta * c.hj_dTep * f.teq[col];
+    } else {
+      Teq = c.hj_Tsurf - c.hj_lapse * zs + c.hj_dTstrat;
+    }
+    const double Tn = (T + kt * Teq) / (1.0 + kt);
+    p = rho_new * c.Rd * Tn;
+    rth_new = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
   }
   const double D3 = Drho + (gp * Wp - gm * Wn);
   if (ln.store) {

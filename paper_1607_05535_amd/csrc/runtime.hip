@@ -143,12 +143,19 @@ bool validate(const thor_planet *pl, const thor_vertical *v, const thor_numerics
     set_error("thor_state_init: numerics need dt > 0, diff_D >= 0, precision FP64|MIXED, div_damp 0|1");
     return false;
   }
-  if (fo->kind != THOR_FORCING_NONE && fo->kind != THOR_FORCING_NEWTONIAN) {
+  if (fo->kind != THOR_FORCING_NONE && fo->kind != THOR_FORCING_NEWTONIAN && fo->kind != THOR_FORCING_HOT_JUPITER) {
     set_error("thor_state_init: unknown forcing kind");
     return false;
   }
-  if (fo->kind == THOR_FORCING_NEWTONIAN && !(fo->tau > 0)) {
+  if (fo->kind != THOR_FORCING_NONE && !(fo->tau > 0)) {
     set_error("thor_state_init: Newtonian forcing needs tau > 0");
+    return false;
+  }
+  if (fo->kind == THOR_FORCING_HOT_JUPITER &&
+      !(fo->T_mean > 0 && fo->lapse >= 0 && fo->z_strat > 0 && fo->dT_strat >= 0 && fo->sigma_strat >= 0 &&
+        fo->sigma_strat < 1)) {
+    set_error("thor_state_init: hot-Jupiter forcing needs T_mean > 0, lapse >= 0, z_strat > 0, dT_strat >= 0, "
+              "0 <= sigma_strat < 1");
     return false;
   }
   if (!(in->T0 > 0 && in->p_surf > 0 && in->noise_amp >= 0 && in->noise_amp < in->T0)) {
@@ -201,7 +208,10 @@ int upload(thor_state *s, const Grid &G, const thor_planet *pl, const thor_verti
     rh[3 * i + 2] = (H)p.z;
     double lam = std::sqrt(p.x * p.x + p.y * p.y) < 1e-12 ? 0.0 : std::atan2(p.y, p.x);
     double phi = std::asin(std::fmin(1.0, std::fmax(-1.0, p.z)));
-    teq[i] = fo->T_mean + 0.5 * fo->dT_daynight * std::cos(phi) * std::cos(lam - fo->lon_substellar);
+    // NEWTONIAN: T_eq itself; HOT_JUPITER: its horizontal factor cos(lon - lon_ss) cos(lat)
+    teq[i] = fo->kind == THOR_FORCING_HOT_JUPITER
+                 ? std::cos(lam - fo->lon_substellar) * std::cos(phi)
+                 : fo->T_mean + 0.5 * fo->dT_daynight * std::cos(phi) * std::cos(lam - fo->lon_substellar);
   }
   // initial state: isothermal columns in discrete hydrostatic balance
   std::vector<double> rcol(L), pcol(L);
@@ -462,7 +472,13 @@ int thor_state_init(const thor_grid *g, const thor_planet *pl, const thor_vertic
   c.dt = num->dt;
   c.div_damp = num->div_damp;
   c.forcing = fo->kind;
-  c.tau = fo->kind == THOR_FORCING_NEWTONIAN ? fo->tau : 1.0;
+  c.tau = fo->kind != THOR_FORCING_NONE ? fo->tau : 1.0;
+  c.hj_Tsurf = fo->T_mean;
+  c.hj_dTep = fo->dT_daynight;
+  c.hj_lapse = fo->lapse;
+  c.hj_zstrat = fo->z_strat;
+  c.hj_dTstrat = fo->dT_strat;
+  c.hj_sstrat = fo->sigma_strat;
   if (!hip_ok(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking), "capture stream")) {
     delete s;
     return THOR_EHIP;

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libthor.so")
 
 THOR_OK, THOR_EINVAL, THOR_ENOMEM, THOR_EHIP, THOR_ENONFINITE, THOR_ENOTCONV = 0, -1, -2, -3, -4, -5
 THOR_FP64, THOR_MIXED = 0, 1
-THOR_FORCING_NONE, THOR_FORCING_NEWTONIAN = 0, 1
+THOR_FORCING_NONE, THOR_FORCING_NEWTONIAN, THOR_FORCING_HOT_JUPITER = 0, 1, 2
 THOR_DIAG_MASS, THOR_DIAG_FIELD, THOR_DIAG_STATE_EXPORT, THOR_DIAG_SCALARS = 1, 2, 3, 4
 FIELDS = {"T": 0, "u": 1, "v": 2, "w": 3, "p": 4, "rho": 5, "rhotheta": 6,
           "Mx": 7, "My": 8, "Mz": 9, "W": 10}
@@ -61,7 +61,9 @@ class Numerics(ctypes.Structure):
 
 class Forcing(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("tau", ctypes.c_double), ("T_mean", ctypes.c_double),
-                ("dT_daynight", ctypes.c_double), ("lon_substellar", ctypes.c_double)]
+                ("dT_daynight", ctypes.c_double), ("lon_substellar", ctypes.c_double),
+                ("lapse", ctypes.c_double), ("z_strat", ctypes.c_double), ("dT_strat", ctypes.c_double),
+                ("sigma_strat", ctypes.c_double)]
 
 
 class Init(ctypes.Structure):
@@ -341,7 +343,8 @@ def structs_from_workload(w, precision=THOR_FP64):
     planet = Planet(w.radius, w.omega, w.gravity, w.Rd, w.Cp, w.p_ref)
     vert = Vertical(w.n_lev, w.z_top)
     num = Numerics(w.dt, w.diff_D, int(w.div_damp), precision)
-    forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar)
+    forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar,
+                      w.lapse, w.z_strat, w.dT_strat, w.sigma_strat)
     init = Init(w.T0, w.p_surf, w.noise_amp, w.seed, 0)
     return planet, vert, num, forcing, init
 

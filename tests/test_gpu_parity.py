@@ -104,3 +104,11 @@ def test_gas_giant_g6_l32_full_size_samples_after_one_step():
         assert e < TOL, (k, e)
     m1, rc = st.mass()
     assert rc == 0 and abs(m1 / mass[1] - 1) < 1e-12
+
+
+def test_hot_jupiter_benchmark_forcing():
+    """The hot-Jupiter benchmark physics (Eqs. teq-hj, btrop, tvert; 37 layers
+    to 4875 km, a level count that is not a multiple of 4) on g3 with a step
+    scaled to the coarser grid."""
+    w = workloads.hot_jupiter(glevel=3, n_lev=37, n_large=3, dt=2400.0, noise_amp=0.1)
+    _compare(w)
