@@ -147,6 +147,35 @@ def run_hot_jupiter(steps, warmup):
             "kernel_ms": {k: v[0] for k, v in kt.items()}}
 
 
+def run_zonal(reps=20):
+    """Post-processing of one snapshot of the g6 L32 benchmark state: u, v,
+    T, theta interpolated to 20 pressure levels and reduced over 36 latitude
+    bands (mean and eddy passes), FP64."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1607_05535_amd import thor
+    w = workloads.gas_giant_c2()
+    g = thor.Grid(w.glevel)
+    st = thor.State(g, *thor.structs_from_workload(w), device="cuda:0")
+    st.step(2, w.n_acoustic)
+    plev = np.geomspace(2e3, 2e7, 20)
+    z = thor.Zonal(st, g, w.radius, w.gravity, 36, plev)
+    z.accumulate()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        z.accumulate()
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    # state read (rho, rho theta, M) + interpolated values written once and read twice
+    bytes_ = w.cells * 5 * 8.0 + w.n_col * len(plev) * 5 * 8.0 * 3
+    return {"workload": "g6 L32 snapshot, 20 pressure levels, 36 bands", "ms_per_snapshot": t * 1e3,
+            "GBs": bytes_ / t / 1e9}
+
+
 def run_ensemble(steps, warmup):
     """The 64-planet ensemble advanced with one launch per phase, against the
     same planets advanced one after the other with the single-planet path."""
@@ -326,6 +355,7 @@ def main():
     ap.add_argument("--no-one-day", action="store_true")
     ap.add_argument("--no-corrector", action="store_true")
     ap.add_argument("--no-hot-jupiter", action="store_true")
+    ap.add_argument("--no-zonal", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -386,6 +416,8 @@ def main():
             out["mixed"]["one_day"] = mixed_one_day()
     if not args.no_hot_jupiter:
         out["hot_jupiter"] = run_hot_jupiter(args.steps, args.warmup)
+    if not args.no_zonal:
+        out["zonal_postprocessing"] = run_zonal()
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble(max(1, args.steps // 10), 2)
     if not args.no_corrector:

@@ -397,6 +397,48 @@ int thor_corrector_batch(thor_corrector *c, const float *coarse_fields, const fl
 int thor_corrector_apply(thor_corrector *c, int *n_applied);
 void thor_corrector_free(thor_corrector *c);
 
+/* ---------------------------------------------------------------------------
+ * Post-processing on pressure levels (the paper shows its results on
+ * pressure levels, interpolated linearly from the model levels; Sec. 6).
+ *
+ * Each thor_zonal_accumulate call takes the state as it stands (between
+ * large steps): every column's u, v, T and theta = rho theta / rho are
+ * interpolated linearly in p to the levels plev (a level outside the
+ * column's range of cell-centre pressures has no value there); per latitude
+ * band b, covering [-90 + 180 b / n_bands, -90 + 180 (b + 1) / n_bands)
+ * degrees (the north pole in the last band), area-weighted means over the
+ * columns with a value and the eddy fluxes [u'v'], [v'T'] (eddies are
+ * deviations from the band mean) are added to device time sums.
+ * thor_zonal_result gives the time means, each over the snapshots in which
+ * the band/level had a value, and the mass streamfunction
+ *   Psi = 2 pi radius cos(lat_b) / gravity * int_0^p [v] dp
+ * (trapezoid rule over plev, [v](0) = [v](plev[0])).  Results are
+ * reproducible: every sum runs in a fixed order.
+ * ------------------------------------------------------------------------- */
+typedef struct thor_zonal thor_zonal;
+enum {
+  THOR_ZM_U = 0, THOR_ZM_V = 1, THOR_ZM_T = 2, THOR_ZM_THETA = 3, THOR_ZM_UPVP = 4, THOR_ZM_VPTP = 5,
+  THOR_ZM_WEIGHT = 6,     /* area fraction of the band with a value */
+  THOR_ZM_PSI = 7,        /* kg/s */
+  THOR_ZM_SNAPSHOTS = 8,  /* snapshots in which the band/level had a value */
+  THOR_ZM_COUNT = 9
+};
+
+/* plev: n_plev pressures [Pa], positive and strictly ascending (host).
+ * EINVAL: bad arguments.  1..4096 bands, 1..1024 levels. */
+int thor_zonal_bytes(const thor_state *s, int n_bands, const double *plev, int n_plev, size_t *bytes);
+/* g: the state's grid; radius, gravity: for Psi.  Uses the state's stream;
+ * synchronises.  dev_buf: caller-owned, 256-byte aligned, never freed. */
+int thor_zonal_init(thor_state *s, const thor_grid *g, double radius, double gravity, int n_bands,
+                    const double *plev, int n_plev, void *dev_buf, size_t dev_bytes, thor_zonal **out);
+/* Add the current snapshot.  Asynchronous on the state's stream. */
+int thor_zonal_accumulate(thor_zonal *z);
+/* host_out [n_bands][n_plev][THOR_ZM_COUNT]; synchronises. */
+int thor_zonal_result(thor_zonal *z, double *host_out, int *n_snapshots);
+/* Zero the time sums (asynchronous, no memset). */
+int thor_zonal_reset(thor_zonal *z);
+void thor_zonal_free(thor_zonal *z);   /* never frees dev_buf */
+
 #ifdef __cplusplus
 }
 #endif

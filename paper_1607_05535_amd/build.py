@@ -18,7 +18,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=on",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
-SOURCES = ["grid.cpp", "kernels.hip", "runtime.hip", "mlp.hip", "corrector.hip"]
+SOURCES = ["grid.cpp", "kernels.hip", "runtime.hip", "mlp.hip", "corrector.hip", "postproc.hip"]
 
 
 def build(verbose=False, jobs=3):

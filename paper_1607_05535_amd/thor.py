@@ -31,7 +31,9 @@ EXPORTED = ["thor_last_error", "thor_grid_params_default", "thor_grid_build", "t
             "thor_mlp_free", "thor_restriction_bytes", "thor_restriction_build",
             "thor_restriction_export", "thor_restriction_free", "thor_restrict", "thor_state_fields32",
             "thor_field_stats", "thor_corrector_bytes", "thor_corrector_init", "thor_corrector_batch",
-            "thor_corrector_apply", "thor_corrector_free"]
+            "thor_corrector_apply", "thor_corrector_free", "thor_zonal_bytes", "thor_zonal_init",
+            "thor_zonal_accumulate", "thor_zonal_result", "thor_zonal_reset", "thor_zonal_free"]
+ZM_FIELDS = ("u", "v", "T", "theta", "upvp", "vpTp", "weight", "psi", "snapshots")
 
 
 class ThorError(RuntimeError):
@@ -152,6 +154,14 @@ def lib():
     L.thor_corrector_free.argtypes = [vp]
     L.thor_corrector_free.restype = None
     _lib = L
+    L.thor_zonal_bytes.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    L.thor_zonal_init.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, ctypes.c_int,
+                                  vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.thor_zonal_accumulate.argtypes = [vp]
+    L.thor_zonal_result.argtypes = [vp, vp, ip]
+    L.thor_zonal_reset.argtypes = [vp]
+    L.thor_zonal_free.argtypes = [vp]
+    L.thor_zonal_free.restype = None
     return L
 
 
@@ -597,6 +607,44 @@ class Corrector:
         try:
             if getattr(self, "handle", None):
                 lib().thor_corrector_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+class Zonal:
+    """Zonal and time means on pressure levels of a state (see thor.h):
+    accumulate() adds the state as it stands; result() returns a dict of
+    [n_bands, n_plev] arrays (u, v, T, theta, upvp, vpTp, weight, psi,
+    snapshots) and the number of accumulated snapshots."""
+
+    def __init__(self, state, grid, radius, gravity, n_bands, plev):
+        plev = np.ascontiguousarray(plev, dtype=np.float64)
+        nbytes = ctypes.c_size_t()
+        _check(lib().thor_zonal_bytes(state.handle, n_bands, plev.ctypes.data, len(plev), ctypes.byref(nbytes)))
+        self.buf = torch.empty(nbytes.value, dtype=torch.uint8, device=state.buf.device)
+        self.state, self.nb, self.np = state, n_bands, len(plev)
+        h = ctypes.c_void_p()
+        _check(lib().thor_zonal_init(state.handle, grid.handle, radius, gravity, n_bands, plev.ctypes.data,
+                                     len(plev), self.buf.data_ptr(), nbytes.value, ctypes.byref(h)))
+        self.handle = h
+
+    def accumulate(self):
+        _check(lib().thor_zonal_accumulate(self.handle))
+
+    def reset(self):
+        _check(lib().thor_zonal_reset(self.handle))
+
+    def result(self):
+        out = np.empty((self.nb, self.np, len(ZM_FIELDS)))
+        n = ctypes.c_int()
+        _check(lib().thor_zonal_result(self.handle, out.ctypes.data, ctypes.byref(n)))
+        return {k: out[:, :, i] for i, k in enumerate(ZM_FIELDS)}, n.value
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().thor_zonal_free(self.handle)
                 self.handle = None
         except Exception:
             pass

@@ -1,0 +1,59 @@
+"""Post-processing on pressure levels through the C ABI against the oracle:
+zonal and time means, eddy fluxes, valid fractions and the mass
+streamfunction over two snapshots of a small gas giant, with pressure
+levels reaching outside the columns' pressure range."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import dynamics as odyn
+from oracle import postproc as opp
+from tests.conftest import oracle_grid
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_zonal_means_match_the_oracle():
+    from paper_1607_05535_amd import thor
+    w = workloads.small_gas_giant(glevel=3, n_lev=12)
+    w.noise_amp = 2.0
+    nb = 9
+    G = oracle_grid(w.glevel)
+    _, lat = odyn.lon_lat(G.P)
+    edges = -np.pi / 2 + np.arange(nb + 1) * np.pi / nb
+    assert np.min(np.abs(lat[:, None] - edges[None, 1:-1])) > 1e-9   # no column on a band edge
+    model, ost = odyn.model_from_workload(w, G)
+    p0 = odyn.fields(model, ost)["p"]
+    plev = np.linspace(0.5 * p0[:, -1].min(), 1.05 * p0[:, 0].max(), 14)
+    say(f"[zonal] {w.name}: {nb} bands, {len(plev)} levels, 2 snapshots")
+    grid = thor.Grid(w.glevel)
+    st = thor.State(grid, *thor.structs_from_workload(w))
+    z = thor.Zonal(st, grid, w.radius, w.gravity, nb, plev)
+    snaps = []
+    for _ in range(2):
+        st.step(1, w.n_acoustic)
+        z.accumulate()
+        ost = odyn.run(model, ost, 1, w.n_acoustic)
+        snaps.append(opp.snapshot(model, ost, plev, nb))
+    got, n = z.result()
+    ref, cnt = opp.time_mean(snaps)
+    ref["psi"] = opp.streamfunction(ref["v"], plev, w.radius, w.gravity)
+    assert n == 2
+    assert np.array_equal(got["snapshots"], cnt)
+    assert (cnt == 0).any() and (cnt == 2).any()          # levels outside every column exist
+    assert np.abs(got["weight"] - ref["weight"]).max() < 1e-12
+    speed = max(np.abs(ref["u"]).max(), np.abs(ref["v"]).max())
+    errs = {}
+    for k in ("u", "v"):
+        errs[k] = np.abs(got[k] - ref[k]).max() / speed
+    for k in ("T", "theta"):
+        errs[k] = np.abs(got[k] / np.where(ref[k] == 0, 1, ref[k]) - np.where(ref[k] == 0, 0, 1)).max()
+    for k in ("upvp", "vpTp", "psi"):
+        errs[k] = np.abs(got[k] - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-300)
+    say(f"        errors {errs}")
+    for k, e in errs.items():
+        assert e < 1e-9, (k, e)
+    z.reset()
+    got, n = z.result()
+    assert n == 0 and np.all(got["snapshots"] == 0) and np.all(got["u"] == 0)
