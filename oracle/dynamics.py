@@ -77,6 +77,16 @@ class Forcing:
     z_strat: float = 2.0e6       # kind 2: z_stra (m)
     dT_strat: float = 10.0       # kind 2: Delta T_stra (K)
     sigma_strat: float = 0.12    # kind 2: sigma_stra
+    # kind 3, Held-Suarez (Eqs. im_eq_v, im_eq_fv, Sec. 5 T_eq and K_T)
+    k_f: float = 1.0 / 86400.0
+    k_a: float = 1.0 / (40.0 * 86400.0)
+    k_s: float = 1.0 / (4.0 * 86400.0)
+    sigma_b: float = 0.7
+    dT_y: float = 60.0
+    dtheta_z: float = 10.0       # not printed in the paper (reading)
+    p_star: float = 1.0e5        # not printed in the paper (reading)
+    T_top: float = 315.0
+    T_min: float = 200.0
 
 
 @dataclass
@@ -411,20 +421,45 @@ def hot_jupiter_teq(model, p, T):
     return t_vert(f, z) + beta * f.dT_daynight * h[:, None]
 
 
-def newtonian(model, st):
-    """Eq. im_eq_t with constant K_T = 1/tau at fixed density; T_eq from the
-    day/night recipe (kind 1) or the hot-Jupiter benchmark (kind 2)."""
+def held_suarez_rates(model, p, T):
+    """Sec. 5, Earth benchmark: boundary-layer friction rate K_v(sigma)
+    (Eq. im_eq_fv), the relaxation rate K_T(sigma, lat) and T_eq(p, lat), with
+    sigma = p / p_s of the dynamics output (p_s as for the hot Jupiter)."""
     f, pl = model.forcing, model.planet
-    if f.kind not in (1, 2):
+    sigma = p / surface_pressure(model, p, T)[:, None]
+    _, phi = lon_lat(model.rhat)
+    s2, c2 = np.sin(phi)[:, None] ** 2, np.cos(phi)[:, None] ** 2
+    ramp = np.maximum(0.0, (sigma - f.sigma_b) / (1.0 - f.sigma_b))
+    Kv = f.k_f * ramp
+    KT = f.k_a + (f.k_s - f.k_a) * ramp * c2 * c2
+    kappa = pl.Rd / pl.Cp
+    x = p / f.p_star
+    Teq = np.maximum(f.T_min, (f.T_top - f.dT_y * s2 - f.dtheta_z * np.log(x) * c2) * x ** kappa)
+    return Kv, KT, Teq
+
+
+def newtonian(model, st):
+    """Sec. 5 physics after the dynamics, backward Euler (Eqs. im_eq_t and
+    im_eq_v) at fixed density: kind 1 relaxes T with K_T = 1/tau toward the
+    day/night T_eq, kind 2 toward the hot-Jupiter T_eq, kind 3 is the
+    Held-Suarez forcing (relaxation and boundary-layer friction)."""
+    f, pl = model.forcing, model.planet
+    if f.kind not in (1, 2, 3):
         return st
     dt = model.num.dt
     p = model.eos(st.rth)
     T = p / (st.rho * pl.Rd)
-    kt = dt / f.tau
-    Teq = model.Teq if f.kind == 1 else hot_jupiter_teq(model, p, T)
+    M = st.M
+    if f.kind == 3:
+        Kv, KT, Teq = held_suarez_rates(model, p, T)
+        kt = dt * KT
+        M = st.M / (1.0 + Kv * dt)[..., None]
+    else:
+        kt = dt / f.tau
+        Teq = model.Teq if f.kind == 1 else hot_jupiter_teq(model, p, T)
     Tn = (T + kt * Teq) / (1.0 + kt)
     rth = model.rth_from_p(st.rho * pl.Rd * Tn)
-    return State(st.rho, st.M, rth, st.W)
+    return State(st.rho, M, rth, st.W)
 
 
 def large_step(model, st, n):
@@ -472,7 +507,8 @@ def model_from_workload(w, G):
     vert = Vertical(w.n_lev, w.z_top)
     num = Numerics(w.dt, w.diff_D, w.div_damp)
     forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar,
-                      w.lapse, w.z_strat, w.dT_strat, w.sigma_strat)
+                      w.lapse, w.z_strat, w.dT_strat, w.sigma_strat, w.k_f, w.k_a, w.k_s, w.sigma_b,
+                      w.dT_y, w.dtheta_z, w.p_star, w.T_top, w.T_min)
     model = Model(G, planet, vert, num, forcing)
     st = init_state(model, Init(w.T0, w.p_surf, w.noise_amp, w.seed))
     return model, st

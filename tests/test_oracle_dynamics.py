@@ -365,3 +365,58 @@ def test_hot_jupiter_relaxation_is_backward_euler():
     rhs = (Teq - T1) / model.forcing.tau
     assert np.abs(lhs - rhs).max() < 1e-9 * np.abs(rhs).max()
     assert np.array_equal(out.rho, st.rho)
+
+
+# ---------------------------------------------------------------------------
+# Held-Suarez forcing (Sec. 5 Earth benchmark, Eqs. im_eq_v, im_eq_fv)
+# ---------------------------------------------------------------------------
+
+def _hs_pressures(w, model, sig, T=250.0):
+    """Pressures whose sigma (with the extrapolated surface pressure) is sig
+    per level, for levels 1..; level 0 sits at its hydrostatic sigma."""
+    N, L = model.G.n, w.n_lev
+    ps = 9.0e4
+    p = np.empty((N, L))
+    p[:, 0] = ps * np.exp(-w.gravity * model.zC[0] / (w.Rd * T))
+    for k in range(1, L):
+        p[:, k] = sig[k] * ps
+    return p, np.full((N, L), T)
+
+
+def test_held_suarez_rates_closed_forms():
+    """K_v = 0 for sigma <= sigma_b and k_f (sigma - sigma_b) / (1 - sigma_b)
+    above; K_T = k_a at sigma <= sigma_b; T_eq = max(200, 315 - 60 sin^2 lat) at
+    p = p*; T_eq floors at 200 K at low pressure."""
+    w = workloads.held_suarez(glevel=2, n_lev=6)
+    model, st = dy.model_from_workload(w, oracle_grid(2))
+    f = model.forcing
+    sig = np.array([0.0, 0.5, f.sigma_b, 0.85, f.p_star / 9.0e4, 1e-4])
+    p, T = _hs_pressures(w, model, sig)
+    Kv, KT, Teq = dy.held_suarez_rates(model, p, T)
+    _, phi = dy.lon_lat(model.rhat)
+    assert np.all(Kv[:, 1:3] == 0.0) and np.all(KT[:, 1:3] == f.k_a)
+    assert np.allclose(Kv[:, 3], f.k_f * (0.85 - 0.7) / 0.3, rtol=1e-12)
+    ramp = (0.85 - 0.7) / 0.3
+    assert np.allclose(KT[:, 3], f.k_a + (f.k_s - f.k_a) * ramp * np.cos(phi) ** 4, rtol=1e-12)
+    assert np.allclose(Teq[:, 4], np.maximum(200.0, 315.0 - 60.0 * np.sin(phi) ** 2), rtol=0, atol=1e-9)
+    assert np.all(Teq[:, 5] == 200.0)
+
+
+def test_held_suarez_physics_is_backward_euler():
+    """Eqs. im_eq_v and im_eq_t: (M_new - M) / dt = -K_v M_new and
+    (T_new - T) / dt = K_T (T_eq - T_new) with the rates of the dynamics
+    output, at fixed density."""
+    w = workloads.held_suarez(glevel=2, n_lev=12, noise_amp=0.5)
+    model, st = dy.model_from_workload(w, oracle_grid(2))
+    rs = np.random.default_rng(3)
+    st = dy.State(st.rho, rs.normal(size=st.M.shape) * st.rho[..., None], st.rth, st.W)
+    f0 = dy.fields(model, st)
+    Kv, KT, Teq = dy.held_suarez_rates(model, f0["p"], f0["T"])
+    assert Kv.max() > 0 and Kv.min() == 0.0
+    out = dy.newtonian(model, st)
+    dt = model.num.dt
+    lhs = (out.M - st.M) / dt
+    assert np.abs(lhs + Kv[..., None] * out.M).max() < 1e-12 * np.abs(lhs).max()
+    T1 = dy.fields(model, out)["T"]
+    assert np.abs((T1 - f0["T"]) / dt - KT * (Teq - T1)).max() < 1e-9 * np.abs(KT * (Teq - T1)).max()
+    assert np.array_equal(out.rho, st.rho)

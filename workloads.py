@@ -50,6 +50,15 @@ class Workload:
     z_strat: float = 2.0e6
     dT_strat: float = 10.0
     sigma_strat: float = 0.12
+    k_f: float = 1.0 / 86400.0
+    k_a: float = 1.0 / (40.0 * 86400.0)
+    k_s: float = 1.0 / (4.0 * 86400.0)
+    sigma_b: float = 0.7
+    dT_y: float = 60.0
+    dtheta_z: float = 10.0
+    p_star: float = 1.0e5
+    T_top: float = 315.0
+    T_min: float = 200.0
     extra: dict = field(default_factory=dict)
 
     @property
@@ -152,6 +161,19 @@ def hot_jupiter(glevel=5, n_lev=37, n_large=1, dt=600.0, n_acoustic=8, noise_amp
                     3779.0, 13226.5, 1.0e5, dt, n_acoustic, n_large, D_HOT_JUPITER, True, 1600.0,
                     2.2e7, noise_amp, seed, forcing_kind=2, tau=1.5e5, T_mean=1600.0,
                     dT_daynight=300.0, lon_substellar=0.0)
+
+
+def held_suarez(glevel=5, n_lev=37, n_large=1, dt=1000.0, n_acoustic=8, noise_amp=0.1, seed=6, T0=300.0):
+    """The Earth benchmark of Sec. 5 (Held-Suarez forcing): Table 1 Earth
+    (radius 6.371e6 m, rotation 7.292e-5 1/s, gravity 9.8, cp 1004.6,
+    Rd 287.04), 37 layers to 32 km, large step 1000 s, diffusion timescale
+    6.46e3 s; friction k_f = 1/day above sigma_b = 0.7, relaxation k_a =
+    1/40 days, k_s = 1/4 days, (Delta T)_y = 60 K.  (Delta theta)_z = 10 K
+    and p* = 1e5 Pa are not printed in the paper (readings).  The start is
+    isothermal with small noise instead of the equatorial T_eq profile."""
+    return Workload(f"g{glevel}L{n_lev}-heldsuarez", glevel, n_lev, 3.2e4, 6.371e6, 7.292e-5, 9.8,
+                    287.04, 1004.6, 1.0e5, dt, n_acoustic, n_large, D_EARTH, True, T0, 1.0e5,
+                    noise_amp, seed, forcing_kind=3)
 
 
 def corrector_pair(fine_glevel=7, coarse_glevel=5, n_lev=32, dt_coarse=600.0, ratio=4, base_seed=1000):
