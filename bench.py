@@ -135,14 +135,11 @@ def mixed_one_day():
             "seconds_fp64": times[0], "seconds_mixed": times[1], "speedup": times[0] / times[1]}
 
 
-def run_hot_jupiter(steps, warmup):
-    """The hot-Jupiter benchmark of Sec. 5 at its own size (g5, 10242 columns
-    x 37 layers, 600 s steps, 8 substeps), FP64, autotuned."""
-    import workloads
-    w = workloads.hot_jupiter(glevel=5, n_lev=37)
+def run_physics_case(w, label, steps, warmup):
+    """One of the paper's two benchmark setups at its own size, FP64,
+    autotuned: cell-updates/s and kernel times."""
     T, kt, sc, tuned = run_gpu(w, 0, steps, warmup)
-    return {"workload": "hot-Jupiter benchmark g5 (10242 columns) x 37 levels, dt 600 s, n = 8",
-            "value": w.cells * w.substeps_per_large * steps / T, "unit": "cell-updates/s",
+    return {"workload": label, "value": w.cells * w.substeps_per_large * steps / T, "unit": "cell-updates/s",
             "ms_per_step": T / steps * 1e3, "max_speed": sc["max_speed"],
             "kernel_ms": {k: v[0] for k, v in kt.items()}}
 
@@ -415,7 +412,14 @@ def main():
         if not args.no_one_day:
             out["mixed"]["one_day"] = mixed_one_day()
     if not args.no_hot_jupiter:
-        out["hot_jupiter"] = run_hot_jupiter(args.steps, args.warmup)
+        out["hot_jupiter"] = run_physics_case(
+            workloads.hot_jupiter(glevel=5, n_lev=37),
+            "hot-Jupiter benchmark g5 (10242 columns) x 37 levels to 4875 km, dt 600 s, n = 8",
+            args.steps, args.warmup)
+        out["held_suarez"] = run_physics_case(
+            workloads.held_suarez(glevel=5, n_lev=37),
+            "Held-Suarez benchmark g5 (10242 columns) x 37 levels to 32 km, dt 1000 s, n = 8",
+            args.steps, args.warmup)
     if not args.no_zonal:
         out["zonal_postprocessing"] = run_zonal()
     if not args.no_ensemble:

@@ -142,7 +142,8 @@ typedef struct {
 } thor_numerics;
 
 /* Physics after each large step (Sec. 5, Eq. im_eq_t): backward-Euler
- * Newtonian relaxation of T at fixed density with K_T = 1/tau, toward
+ * Newtonian relaxation of T at fixed density (K_T = 1/tau unless stated)
+ * toward
  *   NEWTONIAN:   T_eq = T_mean + dT_daynight/2 cos(lat) cos(lon - lon_ss);
  *   HOT_JUPITER: the hot-Jupiter benchmark, Eqs. teq-hj, btrop, tvert:
  *                T_eq = T_vert(z) + beta_trop(sigma, z) dT_daynight
@@ -150,8 +151,18 @@ typedef struct {
  *                lapse, z_strat, dT_strat; beta_trop with sigma_strat;
  *                sigma = p / p_s, p_s the column's lowest-cell pressure
  *                carried down to z = 0 hydrostatically at that cell's
- *                temperature.  No boundary-layer friction. */
-enum { THOR_FORCING_NONE = 0, THOR_FORCING_NEWTONIAN = 1, THOR_FORCING_HOT_JUPITER = 2 };
+ *                temperature.  No boundary-layer friction.
+ *   HELD_SUAREZ: the Earth benchmark (Eqs. im_eq_v, im_eq_fv and the T_eq,
+ *                K_T of Sec. 5): boundary-layer friction of the horizontal
+ *                momentum, (rho v_h) / (1 + K_v dt) with K_v = k_f max(0,
+ *                (sigma - sigma_b) / (1 - sigma_b)), and relaxation with
+ *                K_T = k_a + (k_s - k_a) max(0, (sigma - sigma_b) /
+ *                (1 - sigma_b)) cos^4(lat) toward T_eq = max(T_min, [T_top -
+ *                dT_y sin^2(lat) - dtheta_z ln(p / p_star) cos^2(lat)]
+ *                (p / p_star)^(Rd / Cp)); sigma and p as for HOT_JUPITER.
+ *                (tau and the HOT_JUPITER fields are unused.) */
+enum { THOR_FORCING_NONE = 0, THOR_FORCING_NEWTONIAN = 1, THOR_FORCING_HOT_JUPITER = 2,
+       THOR_FORCING_HELD_SUAREZ = 3 };
 
 typedef struct {
   int kind;               /* THOR_FORCING_* */
@@ -163,6 +174,11 @@ typedef struct {
   double z_strat;         /* HOT_JUPITER: z_stra [m] */
   double dT_strat;        /* HOT_JUPITER: Delta T_stra [K] */
   double sigma_strat;     /* HOT_JUPITER: sigma_stra, in [0, 1) */
+  double k_f, k_a, k_s;   /* HELD_SUAREZ: rates [1/s] */
+  double sigma_b;         /* HELD_SUAREZ: boundary-layer top, in [0, 1) */
+  double dT_y, dtheta_z;  /* HELD_SUAREZ: [K] */
+  double p_star;          /* HELD_SUAREZ: [Pa] */
+  double T_top, T_min;    /* HELD_SUAREZ: [K] */
 } thor_forcing;
 
 typedef struct {

@@ -29,7 +29,7 @@ struct Fields {
   const int32_t *ddi;     // [N][18] two-ring columns (-1 pad)
   const H *ddw;           // [N][18][3] lap(grad .) weights
   const double *area;     // [N]
-  const double *teq;      // [N] Newtonian T_eq, or cos(lon - lon_ss) cos(lat) (hot Jupiter)
+  const double *teq;      // [N] Newtonian T_eq; cos(lon - lon_ss) cos(lat) (hot Jupiter); sin(lat) (Held-Suarez)
 
   // current small-step state
   double *rho, *rth, *W;  // [N][L]
@@ -68,6 +68,8 @@ struct Consts {
   double tau;
   // hot-Jupiter benchmark forcing (Eqs. teq-hj, btrop, tvert)
   double hj_Tsurf, hj_dTep, hj_lapse, hj_zstrat, hj_dTstrat, hj_sstrat;
+  // Held-Suarez forcing (Eqs. im_eq_v, im_eq_fv; Sec. 5 T_eq, K_T)
+  double hs_kf, hs_ka, hs_ks, hs_sb, hs_dTy, hs_dthz, hs_pstar, hs_Ttop, hs_Tmin;
 };
 
 // Workgroups have 1, 2, 4 or 8 wavefronts (tuned per kernel family).

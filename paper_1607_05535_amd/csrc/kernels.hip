@@ -404,14 +404,50 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
     p = rho_new * c.Rd * Tn;
     rth_new = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
   }
+  double hs_sigma = 0.0;
+  if (LAST && c.forcing == THOR_FORCING_HELD_SUAREZ) {
+    // Held-Suarez relaxation (Eq. im_eq_t with the Sec. 5 K_T and T_eq);
+    // sigma of the dynamics output is kept for the friction kernel
+    const double T = p / (rho_new * c.Rd);
+    const int l0 = ln.lane - lev;
+    const double p0 = shfl(p, l0), T0 = shfl(T, l0);
+    const double ps = p0 * exp(c.grav * (0.5 * dz) / (c.Rd * T0));
+    hs_sigma = p / ps;
+    const double s2 = f.teq[col] * f.teq[col], c2 = 1.0 - s2;
+    const double ramp = fmax(0.0, (hs_sigma - c.hs_sb) / (1.0 - c.hs_sb));
+    const double KT = c.hs_ka + (c.hs_ks - c.hs_ka) * ramp * c2 * c2;
+    const double x = p / c.hs_pstar;
+    const double Teq = fmax(c.hs_Tmin, (c.hs_Ttop - c.hs_dTy * s2 - c.hs_dthz * log(x) * c2) * pow(x, c.Rd / c.Cp));
+    const double kt = c.dt * KT;
+    const double Tn = (T + kt * Teq) / (1.0 + kt);
+    p = rho_new * c.Rd * Tn;
+    rth_new = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
+  }
   const double D3 = Drho + (gp * Wp - gm * Wn);
   if (ln.store) {
     f.rho[idx] = rho_new;
     f.rth[idx] = rth_new;
     f.W[idx] = Wn;
     f.ps[idx] = (H)(p - pt);
-    f.D[idx] = (H)D3;
+    // after the last substep D is not read again; the Held-Suarez friction
+    // takes sigma from it
+    f.D[idx] = (H)(LAST && c.forcing == THOR_FORCING_HELD_SUAREZ ? hs_sigma : D3);
   }
+}
+
+// Held-Suarez boundary-layer friction (Eq. im_eq_v with K_v of Eq. im_eq_fv)
+// after the last phase V of a large step, with sigma of the dynamics output
+// left in D by that kernel.  Other forcings: nothing.
+template <typename H>
+__device__ __forceinline__ void b_friction(const Fields<H> &f, const Consts &c, const Lane &ln) {
+  if (!ln.store || c.forcing != THOR_FORCING_HELD_SUAREZ) return;
+  const size_t idx = (size_t)ln.col * c.L + ln.lev;
+  const double sigma = (double)f.D[idx];
+  const double kv = c.hs_kf * fmax(0.0, (sigma - c.hs_sb) / (1.0 - c.hs_sb));
+  const double den = 1.0 + kv * c.dt;
+  f.Mx[idx] = (H)((double)f.Mx[idx] / den);
+  f.My[idx] = (H)((double)f.My[idx] / den);
+  f.Mz[idx] = (H)((double)f.Mz[idx] / den);
 }
 
 // ---------------------------------------------------------------------------
@@ -961,6 +997,7 @@ THOR_KERNEL(large1, sizeof(H) == 8 ? 3 : 4, map_hlane, , )
 THOR_KERNEL(large2, 5, map_hlane, , )
 THOR_KERNEL(diag, 8, map_lane, COMMA int field, COMMA field)
 THOR_KERNEL(import, 8, map_lane, COMMA const double *blob, COMMA blob)
+THOR_KERNEL(friction, 8, map_lane, , )
 template <typename H>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? HMOM_OCC_D : HMOM_OCC_F)))
 void k_hmom(Fields<H> f, Consts c, int div, int first) {
@@ -1001,10 +1038,13 @@ void launch_hmom(const Fields<H> &f, const Consts &c, int wpb, int div, bool fir
 template <typename H>
 void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, bool last,
                  hipStream_t s) {
-  if (last)
+  if (last) {
     hipLaunchKernelGGL((k_vert<H, true>), dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c, div, (int)first);
-  else
+    if (c.forcing == THOR_FORCING_HELD_SUAREZ)
+      hipLaunchKernelGGL(k_friction<H>, dim3(n_blocks(c, 4)), dim3(256), 0, s, f, c);
+  } else {
     hipLaunchKernelGGL((k_vert<H, false>), dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c, div, (int)first);
+  }
 }
 template <typename H>
 void launch_slow(const Fields<H> &f, const Consts &c, int wpb, bool from_t, hipStream_t s) {
@@ -1053,6 +1093,8 @@ void launch_batch(const Planet<H> *P, const int2 *tiles, int n_tiles, int wpb, i
       break;
     case BatchOp::VertLast:
       hipLaunchKernelGGL((kb_vert<H, true>), g, b, 0, s, P, tiles, parity, arg0, arg1);
+      // the friction of Held-Suarez members (a no-op for the others), same tiles
+      hipLaunchKernelGGL(kb_friction<H>, g, b, 0, s, P, tiles, parity);
       break;
   }
 }

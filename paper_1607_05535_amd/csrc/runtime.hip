@@ -143,11 +143,18 @@ bool validate(const thor_planet *pl, const thor_vertical *v, const thor_numerics
     set_error("thor_state_init: numerics need dt > 0, diff_D >= 0, precision FP64|MIXED, div_damp 0|1");
     return false;
   }
-  if (fo->kind != THOR_FORCING_NONE && fo->kind != THOR_FORCING_NEWTONIAN && fo->kind != THOR_FORCING_HOT_JUPITER) {
+  if (fo->kind != THOR_FORCING_NONE && fo->kind != THOR_FORCING_NEWTONIAN && fo->kind != THOR_FORCING_HOT_JUPITER &&
+      fo->kind != THOR_FORCING_HELD_SUAREZ) {
     set_error("thor_state_init: unknown forcing kind");
     return false;
   }
-  if (fo->kind != THOR_FORCING_NONE && !(fo->tau > 0)) {
+  if (fo->kind == THOR_FORCING_HELD_SUAREZ &&
+      !(fo->k_f >= 0 && fo->k_a >= 0 && fo->k_s >= 0 && fo->sigma_b >= 0 && fo->sigma_b < 1 && fo->p_star > 0 &&
+        fo->T_min > 0 && fo->T_top > 0)) {
+    set_error("thor_state_init: Held-Suarez forcing needs rates >= 0, 0 <= sigma_b < 1, p_star > 0, T_min, T_top > 0");
+    return false;
+  }
+  if ((fo->kind == THOR_FORCING_NEWTONIAN || fo->kind == THOR_FORCING_HOT_JUPITER) && !(fo->tau > 0)) {
     set_error("thor_state_init: Newtonian forcing needs tau > 0");
     return false;
   }
@@ -209,8 +216,10 @@ int upload(thor_state *s, const Grid &G, const thor_planet *pl, const thor_verti
     double lam = std::sqrt(p.x * p.x + p.y * p.y) < 1e-12 ? 0.0 : std::atan2(p.y, p.x);
     double phi = std::asin(std::fmin(1.0, std::fmax(-1.0, p.z)));
     // NEWTONIAN: T_eq itself; HOT_JUPITER: its horizontal factor cos(lon - lon_ss) cos(lat)
-    teq[i] = fo->kind == THOR_FORCING_HOT_JUPITER
-                 ? std::cos(lam - fo->lon_substellar) * std::cos(phi)
+    // HELD_SUAREZ: sin(lat)
+    teq[i] = fo->kind == THOR_FORCING_HOT_JUPITER ? std::cos(lam - fo->lon_substellar) * std::cos(phi)
+             : fo->kind == THOR_FORCING_HELD_SUAREZ
+                 ? std::sin(phi)
                  : fo->T_mean + 0.5 * fo->dT_daynight * std::cos(phi) * std::cos(lam - fo->lon_substellar);
   }
   // initial state: isothermal columns in discrete hydrostatic balance
@@ -472,7 +481,16 @@ int thor_state_init(const thor_grid *g, const thor_planet *pl, const thor_vertic
   c.dt = num->dt;
   c.div_damp = num->div_damp;
   c.forcing = fo->kind;
-  c.tau = fo->kind != THOR_FORCING_NONE ? fo->tau : 1.0;
+  c.tau = (fo->kind == THOR_FORCING_NEWTONIAN || fo->kind == THOR_FORCING_HOT_JUPITER) ? fo->tau : 1.0;
+  c.hs_kf = fo->k_f;
+  c.hs_ka = fo->k_a;
+  c.hs_ks = fo->k_s;
+  c.hs_sb = fo->sigma_b;
+  c.hs_dTy = fo->dT_y;
+  c.hs_dthz = fo->dtheta_z;
+  c.hs_pstar = fo->p_star;
+  c.hs_Ttop = fo->T_top;
+  c.hs_Tmin = fo->T_min;
   c.hj_Tsurf = fo->T_mean;
   c.hj_dTep = fo->dT_daynight;
   c.hj_lapse = fo->lapse;

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libthor.so")
 
 THOR_OK, THOR_EINVAL, THOR_ENOMEM, THOR_EHIP, THOR_ENONFINITE, THOR_ENOTCONV = 0, -1, -2, -3, -4, -5
 THOR_FP64, THOR_MIXED = 0, 1
-THOR_FORCING_NONE, THOR_FORCING_NEWTONIAN, THOR_FORCING_HOT_JUPITER = 0, 1, 2
+THOR_FORCING_NONE, THOR_FORCING_NEWTONIAN, THOR_FORCING_HOT_JUPITER, THOR_FORCING_HELD_SUAREZ = 0, 1, 2, 3
 THOR_DIAG_MASS, THOR_DIAG_FIELD, THOR_DIAG_STATE_EXPORT, THOR_DIAG_SCALARS = 1, 2, 3, 4
 FIELDS = {"T": 0, "u": 1, "v": 2, "w": 3, "p": 4, "rho": 5, "rhotheta": 6,
           "Mx": 7, "My": 8, "Mz": 9, "W": 10}
@@ -65,7 +65,10 @@ class Forcing(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("tau", ctypes.c_double), ("T_mean", ctypes.c_double),
                 ("dT_daynight", ctypes.c_double), ("lon_substellar", ctypes.c_double),
                 ("lapse", ctypes.c_double), ("z_strat", ctypes.c_double), ("dT_strat", ctypes.c_double),
-                ("sigma_strat", ctypes.c_double)]
+                ("sigma_strat", ctypes.c_double), ("k_f", ctypes.c_double), ("k_a", ctypes.c_double),
+                ("k_s", ctypes.c_double), ("sigma_b", ctypes.c_double), ("dT_y", ctypes.c_double),
+                ("dtheta_z", ctypes.c_double), ("p_star", ctypes.c_double), ("T_top", ctypes.c_double),
+                ("T_min", ctypes.c_double)]
 
 
 class Init(ctypes.Structure):
@@ -354,7 +357,8 @@ def structs_from_workload(w, precision=THOR_FP64):
     vert = Vertical(w.n_lev, w.z_top)
     num = Numerics(w.dt, w.diff_D, int(w.div_damp), precision)
     forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar,
-                      w.lapse, w.z_strat, w.dT_strat, w.sigma_strat)
+                      w.lapse, w.z_strat, w.dT_strat, w.sigma_strat, w.k_f, w.k_a, w.k_s, w.sigma_b,
+                      w.dT_y, w.dtheta_z, w.p_star, w.T_top, w.T_min)
     init = Init(w.T0, w.p_surf, w.noise_amp, w.seed, 0)
     return planet, vert, num, forcing, init
 

@@ -13,6 +13,7 @@ pytestmark = pytest.mark.gpu
 def _small_ensemble():
     ws = workloads.ensemble(n=6, seed=11, glevels=(2, 3), levels=(7, 20, 33, 48))
     ws[0].forcing_kind, ws[0].tau, ws[0].T_mean, ws[0].dT_daynight = 1, 1e5, ws[0].T0, 40.0
+    ws[1].forcing_kind = 3   # Held-Suarez: relaxation and the separate friction launch
     return ws
 
 

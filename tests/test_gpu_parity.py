@@ -112,3 +112,10 @@ def test_hot_jupiter_benchmark_forcing():
     scaled to the coarser grid."""
     w = workloads.hot_jupiter(glevel=3, n_lev=37, n_large=3, dt=2400.0, noise_amp=0.1)
     _compare(w)
+
+
+def test_held_suarez_forcing():
+    """The Earth benchmark physics (Held-Suarez relaxation and boundary-layer
+    friction, 37 layers to 32 km) on g3 with a step scaled to the coarser grid."""
+    w = workloads.held_suarez(glevel=3, n_lev=37, n_large=4, dt=3000.0, noise_amp=1.0)
+    _compare(w)
