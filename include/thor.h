@@ -328,7 +328,8 @@ int thor_mlp_set_params(thor_mlp *m, const float *host_params);   /* resets Adam
 int thor_mlp_get_params(thor_mlp *m, float *host_params);         /* synchronises */
 
 /* y[B][out] (device, FP32) = network(x[B][in] device BF16).  Asynchronous.
- * EINVAL: B outside 1..max_batch. */
+ * EINVAL: B outside 1..max_batch, or x not 16-byte aligned (also for the
+ * two calls below). */
 int thor_mlp_forward(thor_mlp *m, const void *x_bf16, int B, float *y);
 
 /* Mean-squared loss sum (y - t)^2 / (B out) and, if grad_host is not NULL,
@@ -385,7 +386,8 @@ int thor_field_stats(const float *C, const float *Fn, int n_arrays, size_t strid
                      double *mean_std_host);
 
 /* A corrector of state s by network net (35 n_lev inputs, 5 n_lev outputs,
- * max_batch >= n_col; n_lev a multiple of 32).  norm_host: 20 n_lev floats
+ * max_batch >= n_col; n_lev a multiple of 32; EINVAL otherwise; dev_buf
+ * 256-byte aligned).  norm_host: 20 n_lev floats
  * [4][5][n_lev]: input means and spreads per (field, level), then those of
  * the targets (fine - coarse).
  * A column is corrected only while every normalised output stays within
@@ -402,7 +404,9 @@ int thor_corrector_init(thor_state *s, thor_mlp *net, const float *norm_host, fl
 /* Training batch from stored pairs (device arrays): row b is column cols[b]
  * of pair pairs[b]; inputs from coarse_fields, targets the normalised
  * fine_fields - coarse_fields of that column; pairs are pair_stride floats
- * apart.  x_bf16 [B][35 n_lev], target [B][5 n_lev].  Asynchronous. */
+ * apart.  x_bf16 [B][35 n_lev], target [B][5 n_lev].  Asynchronous.  The
+ * indices live in device memory and are not checked: the caller keeps
+ * 0 <= cols[b] < n_col and pairs[b] within its stored pairs. */
 int thor_corrector_batch(thor_corrector *c, const float *coarse_fields, const float *fine_fields,
                          size_t pair_stride, const int32_t *pairs, const int32_t *cols, int B,
                          void *x_bf16, float *target);

@@ -477,6 +477,13 @@ int thor_corrector_init(thor_state *s, thor_mlp *net, const float *norm_host, fl
   if (!s || !net || !norm_host || !dev_buf || !out) { set_error("thor_corrector_init: NULL argument"); return THOR_EINVAL; }
   *out = nullptr;
   if ((7 * kF * s->c.L) % 32) { set_error("thor_corrector_init: n_lev must be a multiple of 32"); return THOR_EINVAL; }
+  int n_in = 0, n_out = 0, max_batch = 0;
+  mlp_shape_of(net, &n_in, &n_out, &max_batch);
+  if (n_in != 7 * kF * s->c.L || n_out != kF * s->c.L || max_batch < s->c.N) {
+    set_error("thor_corrector_init: the network needs 35 n_lev inputs, 5 n_lev outputs and max_batch >= n_col");
+    return THOR_EINVAL;
+  }
+  if (((uintptr_t)dev_buf & 255) != 0) { set_error("thor_corrector_init: dev_buf must be 256-byte aligned"); return THOR_EINVAL; }
   size_t need = 0;
   thor_corrector_bytes(s, &need);
   if (dev_bytes < need) { set_error("thor_corrector_init: dev_bytes too small"); return THOR_ENOMEM; }

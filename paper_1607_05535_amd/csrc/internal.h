@@ -39,6 +39,13 @@ void clear_error();
 
 }  // namespace thor
 
+struct thor_mlp;
+namespace thor {
+// Input width, output width and largest batch of a corrector network.
+void mlp_shape_of(const thor_mlp *m, int *in, int *out, int *max_batch);
+
+}  // namespace thor
+
 struct thor_grid {
   thor::Grid g;
 };

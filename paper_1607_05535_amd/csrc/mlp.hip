@@ -409,6 +409,14 @@ struct Rng {
 
 }  // namespace
 
+namespace thor {
+void mlp_shape_of(const thor_mlp *m, int *in, int *out, int *max_batch) {
+  *in = m->w.front();
+  *out = m->w.back();
+  *max_batch = m->max_batch;
+}
+}  // namespace thor
+
 extern "C" {
 
 int thor_mlp_bytes(int n_layers, const int *widths, int max_batch, size_t *bytes) {
@@ -481,6 +489,7 @@ int thor_mlp_forward(thor_mlp *m, const void *x_bf16, int B, float *y) {
   clear_error();
   if (!m || !x_bf16 || !y) { set_error("thor_mlp_forward: NULL argument"); return THOR_EINVAL; }
   if (B < 1 || B > m->max_batch) { set_error("thor_mlp_forward: batch outside 1..max_batch"); return THOR_EINVAL; }
+  if (((uintptr_t)x_bf16 & 15) != 0) { set_error("thor_mlp_forward: inputs must be 16-byte aligned"); return THOR_EINVAL; }
   forward(m, (const __bf16 *)x_bf16, B, y);
   return mlp_ok(hipGetLastError(), "mlp forward") ? THOR_OK : THOR_EHIP;
 }
@@ -489,6 +498,7 @@ int thor_mlp_loss_grad(thor_mlp *m, const void *x_bf16, const float *t, int B, d
   clear_error();
   if (!m || !x_bf16 || !t) { set_error("thor_mlp_loss_grad: NULL argument"); return THOR_EINVAL; }
   if (B < 1 || B > m->max_batch || B % 32) { set_error("thor_mlp_loss_grad: batch must be a multiple of 32 within max_batch"); return THOR_EINVAL; }
+  if (((uintptr_t)x_bf16 & 15) != 0) { set_error("thor_mlp_loss_grad: inputs must be 16-byte aligned"); return THOR_EINVAL; }
   forward(m, (const __bf16 *)x_bf16, B, nullptr);
   backward(m, (const __bf16 *)x_bf16, t, B);
   const size_t np = nb((size_t)B * m->w[m->nl]);
@@ -508,6 +518,7 @@ int thor_mlp_train_step(thor_mlp *m, const void *x_bf16, const float *t, int B, 
   clear_error();
   if (!m || !x_bf16 || !t) { set_error("thor_mlp_train_step: NULL argument"); return THOR_EINVAL; }
   if (B < 1 || B > m->max_batch || B % 32 || !(lr > 0)) { set_error("thor_mlp_train_step: batch must be a multiple of 32 within max_batch, lr > 0"); return THOR_EINVAL; }
+  if (((uintptr_t)x_bf16 & 15) != 0) { set_error("thor_mlp_train_step: inputs must be 16-byte aligned"); return THOR_EINVAL; }
   forward(m, (const __bf16 *)x_bf16, B, nullptr);
   backward(m, (const __bf16 *)x_bf16, t, B);
   m->adam_t += 1;

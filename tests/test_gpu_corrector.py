@@ -61,3 +61,18 @@ def test_trained_corrector_beats_plain_coarse_step():
     assert res["columns_corrected_fraction"] > 0.5
     for k in ("T", "p"):
         assert res[k]["rms_corrected"] < res[k]["rms_plain"], k
+
+
+def test_corrector_rejects_a_network_of_the_wrong_shape():
+    """A network whose widths or batch capacity do not fit the state is an
+    argument error, before anything runs."""
+    from paper_1607_05535_amd import thor, learned
+    P = _pipeline()
+    norm = np.ones(20 * P.L, dtype=np.float32)
+    for widths, max_batch in ((learned.widths_for(P.L)[:-1] + [32], P.N),      # wrong output width
+                              ([64] + learned.widths_for(P.L)[1:], P.N),        # wrong input width
+                              (learned.widths_for(P.L), P.N - 1)):               # batch too small
+        net = thor.MLP(widths, max_batch, seed=1)
+        with pytest.raises(thor.ThorError) as e:
+            thor.Corrector(P.work, net, norm)
+        assert e.value.code == thor.THOR_EINVAL
