@@ -317,6 +317,7 @@ int thor_restriction_build(const thor_grid *fine, const thor_grid *coarse, void 
   size_t need = 0;
   thor_restriction_bytes(fine, coarse, &need);
   if (dev_buf && dev_bytes < need) { set_error("thor_restriction_build: dev_bytes too small"); return THOR_ENOMEM; }
+  if (((uintptr_t)dev_buf & 255) != 0) { set_error("thor_restriction_build: dev_buf must be 256-byte aligned"); return THOR_EINVAL; }
   const Grid &F = fine->g, &C = coarse->g;
   if (F.glevel < C.glevel) { set_error("thor_restriction_build: fine grid is coarser"); return THOR_EINVAL; }
   thor_restriction *r = new (std::nothrow) thor_restriction;

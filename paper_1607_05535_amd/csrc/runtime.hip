@@ -781,6 +781,7 @@ int thor_batch_init(int n, const thor_grid *const *grids, const thor_planet *pl,
                     void *dev_buf, size_t dev_bytes, void *hip_stream, thor_batch **out) {
   clear_error();
   if (!out || !dev_buf || !pl || !fo || !in) { set_error("thor_batch_init: NULL argument"); return THOR_EINVAL; }
+  if (((uintptr_t)dev_buf & 255) != 0) { set_error("thor_batch_init: dev_buf must be 256-byte aligned"); return THOR_EINVAL; }
   *out = nullptr;
   size_t need = 0;
   int rc = thor_batch_bytes(n, grids, v, num, &need);
