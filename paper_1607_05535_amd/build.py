@@ -32,7 +32,7 @@ def build(verbose=False, jobs=3):
         lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "c++"]
         cmd = [HIPCC] + HIP_FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
-            cmd = ["g++", "-O3", "-std=c++17", "-fPIC", "-Wall", "-c",
+            cmd = ["g++", "-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-c",
                    os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -52,7 +52,7 @@ def build(verbose=False, jobs=3):
         raise RuntimeError("libthor build failed:\n" + "\n".join(f"[{s}]\n{t}" for s, t in failed))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "--offload-arch=gfx950", "-o", tmp] + objs + \
-          ["-Wl,-rpath,/opt/rocm/lib"]
+          ["-pthread", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)

@@ -16,6 +16,8 @@
 #include <cmath>
 #include <limits>
 #include <new>
+#include <thread>
+#include <vector>
 
 #include "internal.h"
 
@@ -204,9 +206,16 @@ int build_grid(const thor_grid_params &p, Grid &G) {
       if (G.deg[c] == 6) mov.push_back(c);
     std::vector<Vec3> vel(mov.size(), Vec3{0, 0, 0}), nxt(mov.size());
     G.converged = false;
-    for (int it = 1; it <= p.max_iter; ++it) {
-      double maxmove2 = 0.0;
-      for (size_t m = 0; m < mov.size(); ++m) {
+    // Every point's update reads only the previous positions, so the points
+    // are split over host threads; the result does not depend on the split.
+    const size_t nm = mov.size();
+    const int nt = (int)std::max<size_t>(1, std::min<size_t>({(size_t)std::thread::hardware_concurrency(),
+                                                               (size_t)16, nm / 4096 + 1}));
+    std::vector<double> part(nt);
+    auto sweep = [&](int t) {
+      const size_t lo = nm * t / nt, hi = nm * (t + 1) / nt;
+      double mm = 0.0;
+      for (size_t m = lo; m < hi; ++m) {
         const Vec3 p0 = P[mov[m]];
         Vec3 F{0, 0, 0};
         for (int k = 0; k < 6; ++k) {
@@ -220,10 +229,23 @@ int build_grid(const thor_grid_params &p, Grid &G) {
         vel[m] = v;
         Vec3 q = unit(p0 + p.dt * v);
         Vec3 dq = q - p0;
-        maxmove2 = std::max(maxmove2, dot(dq, dq));
+        mm = std::max(mm, dot(dq, dq));
         nxt[m] = q;
       }
-      for (size_t m = 0; m < mov.size(); ++m) P[mov[m]] = nxt[m];
+      part[t] = mm;
+    };
+    for (int it = 1; it <= p.max_iter; ++it) {
+      if (nt == 1) {
+        sweep(0);
+      } else {
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nt; ++t) pool.emplace_back(sweep, t);
+        sweep(0);
+        for (auto &th : pool) th.join();
+      }
+      double maxmove2 = 0.0;
+      for (double v : part) maxmove2 = std::max(maxmove2, v);
+      for (size_t m = 0; m < nm; ++m) P[mov[m]] = nxt[m];
       G.spring_iters = it;
       if (std::sqrt(maxmove2) < p.tol) {
         G.converged = true;
