@@ -82,3 +82,28 @@ def test_gas_giant_g6_l32_invariants():
     sc, rc = st.scalars()
     assert rc == 0 and 0 < sc["max_speed"] < 50.0
     assert 700 < sc["min_T"] and sc["max_T"] < 1700
+
+
+def test_maximum_size_rest_state():
+    """The largest supported configuration, g8 (655362 columns) x 64 levels
+    (41.9 M cells, ~14 GB of FP64 state), autotuned and graph-replayed: a
+    resting isothermal atmosphere in discrete hydrostatic balance stays at
+    rest and keeps its mass."""
+    import torch
+    from paper_1607_05535_amd import thor
+    w = small_earth(glevel=8, n_lev=64, n_large=1, noise=0.0)
+    w.dt = 100.0
+    say(f"[max size] g8 L64: {w.cells} cells")
+    st = lib_state(w)
+    m0, rc = st.mass()
+    assert rc == 0
+    thor.thor_autotune(st.handle, w.n_acoustic)
+    st.step(w.n_large, w.n_acoustic)
+    sc, rc = st.scalars()
+    assert rc == 0
+    m1, _ = st.mass()
+    say(f"          max speed {sc['max_speed']:.3e} m/s, max |w| {sc['max_w']:.3e}, mass drift {m1 / m0 - 1:.2e}")
+    assert sc["max_speed"] < 1e-8 and sc["max_w"] < 1e-8
+    assert abs(m1 / m0 - 1) < 1e-13
+    del st
+    torch.cuda.empty_cache()
