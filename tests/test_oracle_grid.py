@@ -211,3 +211,37 @@ def test_mean_spacing_example_from_paper():
     dbar_km = grid.mean_spacing(5, 7.0e7) / 1e3
     assert abs(dbar_km - gold["dbar_jupiter_g5_km"]) < 1.0
     assert abs(np.degrees(grid.mean_angle(5)) - gold["thetabar_g5_deg"]) < 0.05
+
+
+def test_spring_relaxation_approaches_a_force_balance():
+    """Sec. 2.2: the relaxation drives each hexagon point toward a balance of
+    its springs.  When the paper's rule stops it (steps < 1e-5) the largest
+    net force is a few percent of a single spring's force; with a 100x
+    tighter rule it falls by more than 100x.  The tangent direction is
+    written here through cross products, (p0 x pk) x p0, independently of
+    the oracle's projection."""
+    G0 = oracle_grid(4, smooth=False)
+    k = 100.0
+    dbar = 1.15 * 2 * np.pi / (10 * 2 ** 3)
+    hexes = np.flatnonzero(G0.deg == 6)
+
+    def worst_net_force(tol):
+        P, it, ok = grid.spring_dynamics(G0.P, G0.nbr, G0.deg, 4, k=k, tol=tol)
+        assert ok
+        net, single = [], []
+        for c in hexes:
+            p0 = P[c]
+            F = np.zeros(3)
+            for q in G0.nbr[c]:
+                pk = P[q]
+                t = np.cross(np.cross(p0, pk), p0)
+                t /= np.linalg.norm(t)
+                d = np.arctan2(np.linalg.norm(np.cross(p0, pk)), p0 @ pk)
+                F += k * (d - dbar) * t
+                single.append(abs(k * (d - dbar)))
+            net.append(np.linalg.norm(F))
+        return max(net) / np.median(single)
+
+    loose, tight = worst_net_force(1e-5), worst_net_force(1e-7)
+    assert loose < 0.05
+    assert tight < loose / 100
