@@ -432,8 +432,12 @@ void thor_corrector_free(thor_corrector *c);
  * thor_zonal_result gives the time means, each over the snapshots in which
  * the band/level had a value, and the mass streamfunction
  *   Psi = 2 pi radius cos(lat_b) / gravity * int_0^p [v] dp
- * (trapezoid rule over plev, [v](0) = [v](plev[0])).  Results are
- * reproducible: every sum runs in a fixed order.
+ * (trapezoid rule over plev, [v](0) = [v](plev[0])).  Beside them, each
+ * snapshot adds to the grid-imprinting map of the Held-Suarez results
+ * (Sec. 6): per column, w* = w - {w} in the first model layer (w at the
+ * layer centre; {w} the area-weighted mean over the column's band), whose
+ * time mean [w*] thor_zonal_imprint returns.  Results are reproducible:
+ * every sum runs in a fixed order.
  * ------------------------------------------------------------------------- */
 typedef struct thor_zonal thor_zonal;
 enum {
@@ -455,7 +459,11 @@ int thor_zonal_init(thor_state *s, const thor_grid *g, double radius, double gra
 int thor_zonal_accumulate(thor_zonal *z);
 /* host_out [n_bands][n_plev][THOR_ZM_COUNT]; synchronises. */
 int thor_zonal_result(thor_zonal *z, double *host_out, int *n_snapshots);
-/* Zero the time sums (asynchronous, no memset). */
+/* host_out [n_col] (canonical ids): [w*] in m/s, 0 before the first
+ * snapshot; n_snapshots may be NULL.  Synchronises. */
+int thor_zonal_imprint(thor_zonal *z, double *host_out, int *n_snapshots);
+/* Zero the time sums, the imprinting map's included (asynchronous, no
+ * memset). */
 int thor_zonal_reset(thor_zonal *z);
 void thor_zonal_free(thor_zonal *z);   /* never frees dev_buf */
 

@@ -19,7 +19,11 @@ grid, nor what happens outside a column's pressure range):
     averaged in time like every other quantity; a band/level without any
     value in a snapshot contributes nothing to that snapshot's average;
   * Psi integrates with the trapezoid rule over the pressure levels and
-    takes [v] at p = 0 equal to its value at the first (smallest) level.
+    takes [v] at p = 0 equal to its value at the first (smallest) level;
+  * the grid-imprinting map [w*] (Sec. 6, Held-Suarez results) uses the
+    deviation of w from its zonal (band) mean, w* = w - {w}, on the first
+    model layer, and then averages it in time: with the bracket read as a
+    time mean alone, w - [w] would average to zero identically.
 """
 import numpy as np
 
@@ -112,3 +116,30 @@ def streamfunction(vbar, plev, radius, gravity):
     for j in range(1, len(plev)):
         integ[:, j] = integ[:, j - 1] + 0.5 * (vbar[:, j] + vbar[:, j - 1]) * (plev[j] - plev[j - 1])
     return 2 * np.pi * radius * np.cos(lat)[:, None] / gravity * integ
+
+
+def first_layer_w(model, st):
+    """Vertical velocity at the centre of the lowest layer, per column: the
+    mean of its two interface momenta (the ground one is zero) over rho."""
+    return 0.5 * (st.W[:, 0] + st.W[:, 1]) / st.rho[:, 0]
+
+
+def imprint_snapshot(model, st, n_bands):
+    """w* of one state in the first layer: w minus the area-weighted mean of
+    w over the column's latitude band (the grid-imprinting diagnostic of
+    Sec. 6 before its time average)."""
+    w = first_layer_w(model, st)
+    _, lat = lon_lat(model.rhat)
+    band = band_of(lat, n_bands)
+    A = model.G.Ac
+    out = np.zeros_like(w)
+    for b in range(n_bands):
+        c = np.flatnonzero(band == b)
+        if len(c):
+            out[c] = w[c] - np.sum(A[c] * w[c]) / A[c].sum()
+    return out
+
+
+def imprint_map(snaps):
+    """[w*]: the time average of the per-snapshot w* maps."""
+    return np.mean(np.stack(snaps), axis=0)

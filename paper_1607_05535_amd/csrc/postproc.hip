@@ -5,12 +5,17 @@
 // fluxes [u'v'] and [v'T'] (eddies = deviations from the zonal mean) and the
 // valid area fraction are added to running time sums; the result divides
 // the sums by the number of snapshots with a value and adds the mass
-// streamfunction Psi = 2 pi A cos(lat) / g * int_0^p [v] dp.
+// streamfunction Psi = 2 pi A cos(lat) / g * int_0^p [v] dp.  Beside them,
+// the grid-imprinting map of the Held-Suarez results: per column, the time
+// sum of w* = w - {w} in the first model layer, {w} the area-weighted mean
+// of w over the column's latitude band.
 //
 // Readings: a level outside a column's [top-cell, bottom-cell] pressure
 // range has no value in that column; band b covers latitudes
 // [-90 + 180 b / n, -90 + 180 (b + 1) / n) degrees (the north pole in the
-// last band); Psi uses the trapezoid rule with [v](p = 0) = [v](first level).
+// last band); Psi uses the trapezoid rule with [v](p = 0) = [v](first level);
+// the imprinting bracket is a zonal deviation followed by a time mean (a
+// deviation from the time mean alone would average to zero).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,8 +45,11 @@ bool zok(hipError_t e, const char *what) {
 // u, v, theta of every level, then for each pressure level the interval of
 // the lowest-index level pair whose pressures bracket it; the column's
 // values there go to Z[col][j][0..3] and Z[col][j][4] = 1 (0 if none).
+// Zw[col] = w at the centre of the first layer (half the momentum of the
+// first interior interface over rho; the ground interface carries none).
 template <typename H>
-__global__ __launch_bounds__(256) void k_zinterp(Fields<H> f, Consts c, const double *plev, int np, double *Z) {
+__global__ __launch_bounds__(256) void k_zinterp(Fields<H> f, Consts c, const double *plev, int np, double *Z,
+                                                 double *Zw) {
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int L = c.L, cpw = 64 / L;
@@ -65,6 +73,9 @@ __global__ __launch_bounds__(256) void k_zinterp(Fields<H> f, Consts c, const do
   q[3] = rth / rho;
   const int lp = lane < 63 ? lane + 1 : 63;
   const double p_up = __shfl(p, lp, 64);
+  const double Wl = lev == 0 ? 0.0 : (double)f.W_t[idx];
+  const double W_up = __shfl(Wl, lp, 64);
+  if (store && lev == 0) Zw[col] = L > 1 ? 0.5 * W_up / rho : 0.0;
   double q_up[kZq];
 #pragma unroll
   for (int k = 0; k < kZq; ++k) q_up[k] = __shfl(q[k], lp, 64);
@@ -155,6 +166,29 @@ __global__ __launch_bounds__(kZthreads) void k_zreduce(const double *Z, int np, 
   }
 }
 
+// Band b (one workgroup): area-weighted mean of the first-layer w over all
+// of the band's columns, then each column's deviation from it added to the
+// time sum Wsum[col].
+__global__ __launch_bounds__(kZthreads) void k_zimprint(const double *Zw, const int32_t *off, const int32_t *cols,
+                                                        const double *area, double *Wsum) {
+  __shared__ double sm[kZthreads];
+  const int b = blockIdx.x;
+  const int a0 = off[b], a1 = off[b + 1];
+  double sA = 0, sw = 0;
+  for (int i = a0 + threadIdx.x; i < a1; i += kZthreads) {
+    const int col = cols[i];
+    sA += area[col];
+    sw += area[col] * Zw[col];
+  }
+  sA = block_sum(sA, sm);
+  if (sA == 0.0) return;   // empty band, uniform across the workgroup
+  const double mw = block_sum(sw, sm) / sA;
+  for (int i = a0 + threadIdx.x; i < a1; i += kZthreads) {
+    const int col = cols[i];
+    Wsum[col] += Zw[col] - mw;
+  }
+}
+
 __global__ void k_zzero(double *S, size_t n) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (i < n) S[i] = 0.0;
@@ -172,7 +206,7 @@ struct thor_zonal {
   int nb = 0, np = 0;
   std::vector<double> plev_h;
   double radius = 0, gravity = 0;
-  double *plev = nullptr, *Z = nullptr, *S = nullptr, *area = nullptr;
+  double *plev = nullptr, *Z = nullptr, *S = nullptr, *area = nullptr, *Zw = nullptr, *Wsum = nullptr;
   int32_t *off = nullptr, *cols = nullptr;
   int snapshots = 0;
 };
@@ -192,6 +226,8 @@ size_t zonal_layout(thor_zonal *z, size_t N, char *base) {
   z->area = (double *)take(N * sizeof(double));
   z->off = (int32_t *)take((z->nb + 1) * sizeof(int32_t));
   z->cols = (int32_t *)take(N * sizeof(int32_t));
+  z->Zw = (double *)take(N * sizeof(double));
+  z->Wsum = (double *)take(N * sizeof(double));
   return off;
 }
 
@@ -270,6 +306,7 @@ int thor_zonal_init(thor_state *s, const thor_grid *g, double radius, double gra
             zok(hipMemcpyAsync(z->cols, cols.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy cols");
   if (ok) {
     hipLaunchKernelGGL(k_zzero, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, z->S, ns);
+    hipLaunchKernelGGL(k_zzero, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, z->Wsum, N);
     ok = zok(hipGetLastError(), "zero sums") && zok(hipStreamSynchronize(st), "zonal init synchronize");
   }
   if (!ok) { delete z; return THOR_EHIP; }
@@ -285,10 +322,13 @@ int thor_zonal_accumulate(thor_zonal *z) {
   const long waves = (s->c.N + cpw - 1) / cpw;
   const unsigned nbk = (unsigned)((waves + 3) / 4);
   if (s->precision == THOR_MIXED)
-    hipLaunchKernelGGL(k_zinterp<float>, dim3(nbk), dim3(256), 0, s->stream, s->f32[s->parity], s->c, z->plev, z->np, z->Z);
+    hipLaunchKernelGGL(k_zinterp<float>, dim3(nbk), dim3(256), 0, s->stream, s->f32[s->parity], s->c, z->plev, z->np, z->Z,
+                       z->Zw);
   else
-    hipLaunchKernelGGL(k_zinterp<double>, dim3(nbk), dim3(256), 0, s->stream, s->f64[s->parity], s->c, z->plev, z->np, z->Z);
+    hipLaunchKernelGGL(k_zinterp<double>, dim3(nbk), dim3(256), 0, s->stream, s->f64[s->parity], s->c, z->plev, z->np, z->Z,
+                       z->Zw);
   hipLaunchKernelGGL(k_zreduce, dim3(z->nb, z->np), dim3(kZthreads), 0, s->stream, z->Z, z->np, z->off, z->cols, z->area, z->S);
+  hipLaunchKernelGGL(k_zimprint, dim3(z->nb), dim3(kZthreads), 0, s->stream, z->Zw, z->off, z->cols, z->area, z->Wsum);
   if (!zok(hipGetLastError(), "zonal accumulate")) return THOR_EHIP;
   z->snapshots += 1;
   return THOR_OK;
@@ -323,11 +363,26 @@ int thor_zonal_result(thor_zonal *z, double *host_out, int *n_snapshots) {
   return THOR_OK;
 }
 
+int thor_zonal_imprint(thor_zonal *z, double *host_out, int *n_snapshots) {
+  clear_error();
+  if (!z || !host_out) { set_error("thor_zonal_imprint: NULL argument"); return THOR_EINVAL; }
+  const size_t N = (size_t)z->s->n_col;
+  if (!zok(hipMemcpyAsync(host_out, z->Wsum, N * sizeof(double), hipMemcpyDeviceToHost, z->s->stream), "copy imprint") ||
+      !zok(hipStreamSynchronize(z->s->stream), "zonal imprint synchronize"))
+    return THOR_EHIP;
+  const double n = z->snapshots;
+  for (size_t i = 0; i < N; ++i) host_out[i] = n > 0 ? host_out[i] / n : 0.0;
+  if (n_snapshots) *n_snapshots = z->snapshots;
+  return THOR_OK;
+}
+
 int thor_zonal_reset(thor_zonal *z) {
   clear_error();
   if (!z) { set_error("thor_zonal_reset: NULL argument"); return THOR_EINVAL; }
   const size_t ns = (size_t)z->nb * z->np * 8;
+  const size_t N = (size_t)z->s->n_col;
   hipLaunchKernelGGL(k_zzero, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, z->s->stream, z->S, ns);
+  hipLaunchKernelGGL(k_zzero, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, z->s->stream, z->Wsum, N);
   z->snapshots = 0;
   return zok(hipGetLastError(), "zonal reset") ? THOR_OK : THOR_EHIP;
 }

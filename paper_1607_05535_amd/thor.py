@@ -32,7 +32,8 @@ EXPORTED = ["thor_last_error", "thor_grid_params_default", "thor_grid_build", "t
             "thor_restriction_export", "thor_restriction_free", "thor_restrict", "thor_state_fields32",
             "thor_field_stats", "thor_corrector_bytes", "thor_corrector_init", "thor_corrector_batch",
             "thor_corrector_apply", "thor_corrector_free", "thor_zonal_bytes", "thor_zonal_init",
-            "thor_zonal_accumulate", "thor_zonal_result", "thor_zonal_reset", "thor_zonal_free"]
+            "thor_zonal_accumulate", "thor_zonal_result", "thor_zonal_imprint", "thor_zonal_reset",
+            "thor_zonal_free"]
 ZM_FIELDS = ("u", "v", "T", "theta", "upvp", "vpTp", "weight", "psi", "snapshots")
 
 
@@ -162,6 +163,7 @@ def lib():
                                   vp, ctypes.c_size_t, ctypes.POINTER(vp)]
     L.thor_zonal_accumulate.argtypes = [vp]
     L.thor_zonal_result.argtypes = [vp, vp, ip]
+    L.thor_zonal_imprint.argtypes = [vp, vp, ip]
     L.thor_zonal_reset.argtypes = [vp]
     L.thor_zonal_free.argtypes = [vp]
     L.thor_zonal_free.restype = None
@@ -620,7 +622,8 @@ class Zonal:
     """Zonal and time means on pressure levels of a state (see thor.h):
     accumulate() adds the state as it stands; result() returns a dict of
     [n_bands, n_plev] arrays (u, v, T, theta, upvp, vpTp, weight, psi,
-    snapshots) and the number of accumulated snapshots."""
+    snapshots) and the number of accumulated snapshots; imprint() the
+    first-layer grid-imprinting map [w*]."""
 
     def __init__(self, state, grid, radius, gravity, n_bands, plev):
         plev = np.ascontiguousarray(plev, dtype=np.float64)
@@ -644,6 +647,13 @@ class Zonal:
         n = ctypes.c_int()
         _check(lib().thor_zonal_result(self.handle, out.ctypes.data, ctypes.byref(n)))
         return {k: out[:, :, i] for i, k in enumerate(ZM_FIELDS)}, n.value
+
+    def imprint(self):
+        """[w*] per column (canonical ids) and the number of snapshots."""
+        out = np.empty(self.state.n_col)
+        n = ctypes.c_int()
+        _check(lib().thor_zonal_imprint(self.handle, out.ctypes.data, ctypes.byref(n)))
+        return out, n.value
 
     def __del__(self):
         try:

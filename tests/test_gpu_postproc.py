@@ -1,6 +1,7 @@
 """Post-processing on pressure levels through the C ABI against the oracle:
-zonal and time means, eddy fluxes, valid fractions and the mass
-streamfunction over two snapshots of a small gas giant, with pressure
+zonal and time means, eddy fluxes, valid fractions, the mass
+streamfunction and the first-layer grid-imprinting map [w*] over two
+snapshots of a small gas giant, with pressure
 levels reaching outside the columns' pressure range."""
 import numpy as np
 import pytest
@@ -30,13 +31,22 @@ def test_zonal_means_match_the_oracle():
     grid = thor.Grid(w.glevel)
     st = thor.State(grid, *thor.structs_from_workload(w))
     z = thor.Zonal(st, grid, w.radius, w.gravity, nb, plev)
-    snaps = []
+    snaps, wsnaps = [], []
     for _ in range(2):
         st.step(1, w.n_acoustic)
         z.accumulate()
         ost = odyn.run(model, ost, 1, w.n_acoustic)
         snaps.append(opp.snapshot(model, ost, plev, nb))
+        wsnaps.append(opp.imprint_snapshot(model, ost, nb))
     got, n = z.result()
+    imp, n_imp = z.imprint()
+    imp_ref = opp.imprint_map(wsnaps)
+    assert n_imp == 2
+    wscale = np.abs(opp.first_layer_w(model, ost)).max()
+    assert np.abs(imp_ref).max() > 1e-3 * wscale          # the map is not trivially zero
+    imp_err = np.abs(imp - imp_ref).max() / wscale
+    say(f"        [w*] error {imp_err:.2e} (scale {wscale:.3e} m/s)")
+    assert imp_err < 1e-9
     ref, cnt = opp.time_mean(snaps)
     ref["psi"] = opp.streamfunction(ref["v"], plev, w.radius, w.gravity)
     assert n == 2
@@ -57,3 +67,5 @@ def test_zonal_means_match_the_oracle():
     z.reset()
     got, n = z.result()
     assert n == 0 and np.all(got["snapshots"] == 0) and np.all(got["u"] == 0)
+    imp, n_imp = z.imprint()
+    assert n_imp == 0 and np.all(imp == 0)

@@ -82,3 +82,53 @@ def test_bands_cover_the_sphere_once():
     lat = np.array([-np.pi / 2, -0.1, 0.0, 0.3, np.pi / 2])
     b = pp.band_of(lat, 4)
     assert list(b) == [0, 1, 2, 2, 3]
+
+
+def _state_with_first_layer_w(w, target):
+    """The rest state of workload w with first-layer vertical velocity
+    `target` [n_col]: the momentum at the first interior interface set to
+    2 rho target (the ground interface carries none)."""
+    model, st = dy.model_from_workload(w, oracle_grid(w.glevel))
+    W = np.zeros_like(st.W)
+    W[:, 1] = 2.0 * st.rho[:, 0] * target
+    return model, dy.State(st.rho, st.M, st.rth, W)
+
+
+def test_first_layer_w_is_the_centre_value_of_the_diagnostic_field():
+    w = workloads.small_gas_giant(glevel=2, n_lev=6)
+    model, st = dy.model_from_workload(w, oracle_grid(w.glevel))
+    rs = np.random.default_rng(3)
+    W = rs.normal(size=st.W.shape)
+    W[:, 0] = W[:, -1] = 0.0
+    st = dy.State(st.rho, st.M, st.rth, W)
+    assert np.abs(pp.first_layer_w(model, st) - dy.fields(model, st)["w"][:, 0]).max() < 1e-15
+
+
+def test_imprint_of_a_zonally_varying_w():
+    """w = a(band) + b cos(lon): w* = b (cos(lon) - <cos(lon)>_band), with the
+    band mean weighted by the control-volume areas; the band constants
+    vanish, w* averages to zero over every band, and a resting state has
+    none."""
+    w = workloads.small_gas_giant(glevel=3, n_lev=8)
+    w.noise_amp = 0.0
+    nb = 7
+    G = oracle_grid(w.glevel)
+    lam, lat = dy.lon_lat(G.P)
+    band = pp.band_of(lat, nb)
+    a = 0.05 * (band - 3.0) ** 2
+    b = 0.02
+    model, st = _state_with_first_layer_w(w, a + b * np.cos(lam))
+    ws = pp.imprint_snapshot(model, st, nb)
+    A = G.Ac
+    for k in range(nb):
+        m = band == k
+        mc = np.sum(A[m] * np.cos(lam[m])) / A[m].sum()
+        assert np.abs(ws[m] - b * (np.cos(lam[m]) - mc)).max() < 1e-14
+        assert abs(np.sum(A[m] * ws[m])) < 1e-14 * A[m].sum()
+    model, rest = dy.model_from_workload(w, G)
+    assert np.all(pp.imprint_snapshot(model, rest, nb) == 0.0)
+
+
+def test_imprint_map_is_the_time_mean():
+    m1, m2 = np.array([1.0, -2.0, 0.5]), np.array([3.0, 0.0, -0.5])
+    assert np.array_equal(pp.imprint_map([m1, m2]), [2.0, -1.0, 0.0])
