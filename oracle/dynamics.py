@@ -64,6 +64,7 @@ class Numerics:
     dt: float
     diff_D: float
     div_damp: bool = True
+    energy_fixer: bool = False   # Sec. 3: globally uniform internal-energy fixer
 
 
 @dataclass
@@ -469,6 +470,8 @@ def large_step(model, st, n):
         lambda prev: slow_forcing(model, prev, large),
         lambda phi, f, dtau: acoustic_substep(model, phi, f, dtau, large),
         model.num.dt, n)
+    if model.num.energy_fixer:
+        out = fix_energy(model, out, total_energy(model, st))
     return newtonian(model, out)
 
 
@@ -481,6 +484,32 @@ def run(model, st, n_large, n):
 def mass(model, st):
     """sum_i sum_k rho A_c r_k^2 dz (A_c on the unit sphere)."""
     return float(np.sum(st.rho * model.G.Ac[:, None] * model.rC[None, :] ** 2) * model.dz)
+
+
+def total_energy(model, st):
+    """Total energy of the state: internal rho Cv T = Cv p / Rd, kinetic
+    (|rho v_h|^2 + (rho v_r)^2) / (2 rho) with rho v_r at the layer centre,
+    and potential rho g z (constant radial gravity, z above the ground),
+    summed over the cells with the volumes of ``mass``."""
+    pl = model.planet
+    p = model.eos(st.rth)
+    Wc = to_centres(st.W)
+    e = (model.Cv / pl.Rd) * p \
+        + 0.5 * (np.sum(st.M ** 2, axis=-1) + Wc ** 2) / st.rho \
+        + st.rho * pl.gravity * model.zC[None, :]
+    return float(np.sum(e * model.G.Ac[:, None] * model.rC[None, :] ** 2) * model.dz)
+
+
+def fix_energy(model, st, E_target):
+    """Energy fixer in the manner of Williamson (2009), which the paper
+    implements (Sec. 3, discussion of the thermodynamic equation): one
+    temperature increment, the same at every cell, at fixed density, that
+    brings the total energy back to E_target.  The internal energy is linear
+    in T at fixed rho, so the increment is (E_target - E) / (Cv * mass)."""
+    pl = model.planet
+    dT = (E_target - total_energy(model, st)) / (model.Cv * mass(model, st))
+    T = model.eos(st.rth) / (st.rho * pl.Rd) + dT
+    return State(st.rho, st.M, model.rth_from_p(st.rho * pl.Rd * T), st.W)
 
 
 def fields(model, st):
@@ -505,7 +534,7 @@ def model_from_workload(w, G):
     """Oracle model and initial state for a workload recipe (``workloads``)."""
     planet = Planet(w.radius, w.omega, w.gravity, w.Rd, w.Cp, w.p_ref)
     vert = Vertical(w.n_lev, w.z_top)
-    num = Numerics(w.dt, w.diff_D, w.div_damp)
+    num = Numerics(w.dt, w.diff_D, w.div_damp, w.energy_fixer)
     forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar,
                       w.lapse, w.z_strat, w.dT_strat, w.sigma_strat, w.k_f, w.k_a, w.k_s, w.sigma_b,
                       w.dT_y, w.dtheta_z, w.p_star, w.T_top, w.T_min)

@@ -59,6 +59,7 @@ class Workload:
     p_star: float = 1.0e5
     T_top: float = 315.0
     T_min: float = 200.0
+    energy_fixer: bool = False
     extra: dict = field(default_factory=dict)
 
     @property
