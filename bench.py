@@ -353,6 +353,7 @@ def main():
     ap.add_argument("--no-corrector", action="store_true")
     ap.add_argument("--no-hot-jupiter", action="store_true")
     ap.add_argument("--no-zonal", action="store_true")
+    ap.add_argument("--no-energy-fixer", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -411,6 +412,13 @@ def main():
                         "kernel_ms": {k: v[0] for k, v in kt32.items()}}
         if not args.no_one_day:
             out["mixed"]["one_day"] = mixed_one_day()
+    if not args.no_energy_fixer:
+        wf = workloads.gas_giant_c2()
+        wf.energy_fixer = True
+        Tf, ktf, scf, _ = run_gpu(wf, 0, args.steps, args.warmup)
+        out["energy_fixer"] = {"workload": "the g6 L32 workload with the uniform internal-energy fixer",
+                               "value": updates / Tf, "ms_per_step": Tf / args.steps * 1e3,
+                               "overhead_vs_fp64": Tf / T64 - 1.0}
     if not args.no_hot_jupiter:
         out["hot_jupiter"] = run_physics_case(
             workloads.hot_jupiter(glevel=5, n_lev=37),

@@ -139,6 +139,13 @@ typedef struct {
   int precision;   /* THOR_FP64, or THOR_MIXED: horizontal stencils and
                       advection in FP32, vertical solve and reference state in
                       FP64 */
+  int energy_fixer; /* 1: after the dynamics of every large step (before the
+                      physics), one temperature increment, the same at every
+                      cell and at fixed density, restores the total energy
+                      (THOR_DIAG_ENERGY) of the step's start: the globally
+                      uniform internal-energy adjustment of Williamson (2009)
+                      that the paper implements but leaves off for its
+                      results (Sec. 3).  Not available in ensembles. */
 } thor_numerics;
 
 /* Physics after each large step (Sec. 5, Eq. im_eq_t): backward-Euler
@@ -226,7 +233,11 @@ enum {
   THOR_DIAG_MASS = 1,          /* 1 double: sum rho A_c r_k^2 dz (A_c unit sphere) */
   THOR_DIAG_FIELD = 2,         /* n_col * n_lev doubles of field `field` */
   THOR_DIAG_STATE_EXPORT = 3,  /* checkpoint blob of thor_state_blob_bytes */
-  THOR_DIAG_SCALARS = 4        /* thor_scalars */
+  THOR_DIAG_SCALARS = 4,       /* thor_scalars */
+  THOR_DIAG_ENERGY = 5         /* 1 double: total energy [J] = sum over cells of
+                                  (Cv p / Rd + (|rho v_h|^2 + (rho v_r)^2) / (2 rho)
+                                  + rho g z) A_c r_k^2 dz, rho v_r at the layer
+                                  centre (mean of its interfaces) */
 };
 enum {
   THOR_F_T = 0, THOR_F_U, THOR_F_V, THOR_F_W, THOR_F_P, THOR_F_RHO,

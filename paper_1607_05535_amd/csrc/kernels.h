@@ -55,6 +55,8 @@ struct Fields {
   // diagnostics
   double *diag;           // [N][L]
   double *partial;        // per-block partial sums
+  double *epart;          // energy fixer: partial sums of the step's start and of
+                          // the dynamics output, then the temperature increment
 };
 
 struct Consts {
@@ -64,6 +66,7 @@ struct Consts {
   double dz, Kd;
   double dt;
   int div_damp;
+  int energy_fixer;       // 1: uniform internal-energy fixer after the dynamics
   int forcing;
   double tau;
   // hot-Jupiter benchmark forcing (Eqs. teq-hj, btrop, tvert)
@@ -116,6 +119,15 @@ template <typename H>
 void launch_mass(const Fields<H> &f, const Consts &c, hipStream_t s, int *nblocks_out);
 template <typename H>
 void launch_to_state(const Fields<H> &f, const Consts &c, const double *blob, hipStream_t s);
+// Total energy and mass partial sums of the state Phi[t] (which = 0) or of
+// the small-step state (which = 1) into out[2 b], out[2 b + 1].
+template <typename H>
+void launch_energy(const Fields<H> &f, const Consts &c, int which, double *out, hipStream_t s, int *nblocks_out);
+// The energy fixer after the dynamics of a large step (the start's partial
+// sums already in f.epart), followed by the physics: replaces the physics of
+// the last phase V, which then runs with last = false.
+template <typename H>
+void launch_fixer(const Fields<H> &f, const Consts &c, hipStream_t s);
 
 // One member of an ensemble as the device sees it.
 template <typename H>

@@ -273,6 +273,62 @@ __device__ __forceinline__ void b_hmom(const Fields<H> &f, const Consts &c, cons
 }
 
 // ---------------------------------------------------------------------------
+// Physics after the dynamics (Sec. 5), backward Euler at fixed density, on
+// one cell of a column whose levels sit on consecutive lanes (every lane of
+// the wavefront calls it, since the lowest cell is read by shuffle): the
+// relaxation of T (Eq. im_eq_t) for the configured forcing.  Takes and
+// returns the cell's pressure; sigma receives p / p_s of the input state
+// (Held-Suarez only, for the friction).
+//   NEWTONIAN:   K_T = 1 / tau toward the day/night T_eq;
+//   HOT_JUPITER: K_T = 1 / tau toward Eqs. teq-hj, btrop, tvert, sigma from
+//                the surface pressure the lowest cell implies at constant T;
+//   HELD_SUAREZ: K_T and T_eq of Sec. 5 with the same sigma.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double physics_p(const Consts &c, const double *teq, int col, int lev, int lane,
+                                            double rho, double p, double &sigma) {
+  const double dz = c.dz;
+  if (c.forcing == THOR_FORCING_NEWTONIAN) {
+    const double kt = c.dt / c.tau;
+    const double T = p / (rho * c.Rd);
+    const double Tn = (T + kt * teq[col]) / (1.0 + kt);
+    p = rho * c.Rd * Tn;
+  } else if (c.forcing == THOR_FORCING_HOT_JUPITER) {
+    const double kt = c.dt / c.tau;
+    const double T = p / (rho * c.Rd);
+    const int l0 = lane - lev;
+    const double p0 = shfl(p, l0), T0 = shfl(T, l0);
+    const double ps = p0 * exp(c.grav * (0.5 * dz) / (c.Rd * T0));
+    const double z = (lev + 0.5) * dz, zs = c.hj_zstrat;
+    double Teq;
+    if (z <= zs) {
+      const double a = c.hj_lapse * (z - zs) / 2.0;
+      const double tv = c.hj_Tsurf - c.hj_lapse * (zs + (z - zs) / 2.0) + sqrt(a * a + c.hj_dTstrat * c.hj_dTstrat);
+      const double beta = sin(M_PI * (p / ps - c.hj_sstrat) / (2.0 * (1.0 - c.hj_sstrat)));
+      Teq = tv + beta * c.hj_dTep * teq[col];
+    } else {
+      Teq = c.hj_Tsurf - c.hj_lapse * zs + c.hj_dTstrat;
+    }
+    const double Tn = (T + kt * Teq) / (1.0 + kt);
+    p = rho * c.Rd * Tn;
+  } else if (c.forcing == THOR_FORCING_HELD_SUAREZ) {
+    const double T = p / (rho * c.Rd);
+    const int l0 = lane - lev;
+    const double p0 = shfl(p, l0), T0 = shfl(T, l0);
+    const double ps = p0 * exp(c.grav * (0.5 * dz) / (c.Rd * T0));
+    sigma = p / ps;
+    const double s2 = teq[col] * teq[col], c2 = 1.0 - s2;
+    const double ramp = fmax(0.0, (sigma - c.hs_sb) / (1.0 - c.hs_sb));
+    const double KT = c.hs_ka + (c.hs_ks - c.hs_ka) * ramp * c2 * c2;
+    const double x = p / c.hs_pstar;
+    const double Teq = fmax(c.hs_Tmin, (c.hs_Ttop - c.hs_dTy * s2 - c.hs_dthz * log(x) * c2) * pow(x, c.Rd / c.Cp));
+    const double kt = c.dt * KT;
+    const double Tn = (T + kt * Teq) / (1.0 + kt);
+    p = rho * c.Rd * Tn;
+  }
+  return p;
+}
+
+// ---------------------------------------------------------------------------
 // Acoustic phase V: horizontal mass and theta fluxes of the new momentum,
 // then the HEVI vertical-momentum tridiagonal (Eqs. dens2, momr2, pt2
 // combined), its solution, and the density / rho-theta updates with the new
@@ -374,53 +430,9 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
   const double rho_new = rho_hat - ap * Wp + am * Wn;
   double rth_new = rth_hat - ap * thI_p * Wp + am * thI * Wn;
   double p = c.p_ref * pow(c.Rd * rth_new / c.p_ref, c.gamma);
-  if (LAST && c.forcing == THOR_FORCING_NEWTONIAN) {
-    // physics after the dynamics (Eq. im_eq_t, K_T = 1/tau) at fixed density
-    const double kt = c.dt / c.tau;
-    const double T = p / (rho_new * c.Rd);
-    const double Tn = (T + kt * f.teq[col]) / (1.0 + kt);
-    p = rho_new * c.Rd * Tn;
-    rth_new = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
-  } else if (LAST && c.forcing == THOR_FORCING_HOT_JUPITER) {
-    // Eq. im_eq_t toward the hot-Jupiter T_eq (Eqs. teq-hj, btrop, tvert);
-    // sigma from the surface pressure the column's lowest cell implies at
-    // constant temperature
-    const double kt = c.dt / c.tau;
-    const double T = p / (rho_new * c.Rd);
-    const int l0 = ln.lane - lev;
-    const double p0 = shfl(p, l0), T0 = shfl(T, l0);
-    const double ps = p0 * exp(c.grav * (0.5 * dz) / (c.Rd * T0));
-    const double z = (lev + 0.5) * dz, zs = c.hj_zstrat;
-    double Teq;
-    if (z <= zs) {
-      const double a = c.hj_lapse * (z - zs) / 2.0;
-      const double tv = c.hj_Tsurf - c.hj_lapse * (zs + (z - zs) / 2.0) + sqrt(a * a + c.hj_dTstrat * c.hj_dTstrat);
-      const double beta = sin(M_PI * (p / ps - c.hj_sstrat) / (2.0 * (1.0 - c.hj_sstrat)));
-      Teq = tv + beta * c.hj_dTep * f.teq[col];
-    } else {
-      Teq = c.hj_Tsurf - c.hj_lapse * zs + c.hj_dTstrat;
-    }
-    const double Tn = (T + kt * Teq) / (1.0 + kt);
-    p = rho_new * c.Rd * Tn;
-    rth_new = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
-  }
   double hs_sigma = 0.0;
-  if (LAST && c.forcing == THOR_FORCING_HELD_SUAREZ) {
-    // Held-Suarez relaxation (Eq. im_eq_t with the Sec. 5 K_T and T_eq);
-    // sigma of the dynamics output is kept for the friction kernel
-    const double T = p / (rho_new * c.Rd);
-    const int l0 = ln.lane - lev;
-    const double p0 = shfl(p, l0), T0 = shfl(T, l0);
-    const double ps = p0 * exp(c.grav * (0.5 * dz) / (c.Rd * T0));
-    hs_sigma = p / ps;
-    const double s2 = f.teq[col] * f.teq[col], c2 = 1.0 - s2;
-    const double ramp = fmax(0.0, (hs_sigma - c.hs_sb) / (1.0 - c.hs_sb));
-    const double KT = c.hs_ka + (c.hs_ks - c.hs_ka) * ramp * c2 * c2;
-    const double x = p / c.hs_pstar;
-    const double Teq = fmax(c.hs_Tmin, (c.hs_Ttop - c.hs_dTy * s2 - c.hs_dthz * log(x) * c2) * pow(x, c.Rd / c.Cp));
-    const double kt = c.dt * KT;
-    const double Tn = (T + kt * Teq) / (1.0 + kt);
-    p = rho_new * c.Rd * Tn;
+  if (LAST && c.forcing != THOR_FORCING_NONE) {
+    p = physics_p(c, f.teq, col, lev, ln.lane, rho_new, p, hs_sigma);
     rth_new = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
   }
   const double D3 = Drho + (gp * Wp - gm * Wn);
@@ -954,6 +966,101 @@ __global__ __launch_bounds__(256) void k_mass(Fields<H> f, Consts c) {
   }
 }
 
+// Total energy and mass partial sums per workgroup of one state, FP64, in a
+// fixed reduction order.  which = 0: the large-step state Phi[t]; 1: the
+// small-step state.  Per cell: internal energy Cv p / Rd, kinetic energy
+// (|M|^2 + W_c^2) / (2 rho) with W_c the mean of the cell's two interface
+// momenta (zero at the ground and the lid), potential energy rho g z; times
+// the volume A_c r^2 dz.  out[2 b] = energy, out[2 b + 1] = mass.
+template <typename H>
+__global__ __launch_bounds__(256) void k_energy(Fields<H> f, Consts c, int which, double *out) {
+  __shared__ double sm[4][2];
+  const Lane ln = map_lane(c, xcd_block());
+  const int L = c.L, lev = ln.lev, col = ln.col;
+  const size_t idx = (size_t)col * L + lev;
+  const double *rho_a = which ? f.rho : f.rho_t;
+  const double *rth_a = which ? f.rth : f.rth_t;
+  const double *W_a = which ? f.W : f.W_t;
+  const H *Mx = which ? f.Mx : f.Mx_t;
+  const H *My = which ? f.My : f.My_t;
+  const H *Mz = which ? f.Mz : f.Mz_t;
+  const int lp = ln.lane < 63 ? ln.lane + 1 : 63;
+  const double W = lev == 0 ? 0.0 : W_a[idx];
+  double W1 = shfl(W, lp);
+  if (lev == L - 1) W1 = 0.0;
+  double e = 0.0, m = 0.0;
+  if (ln.store) {
+    const double rC = radius_c(c, lev);
+    const double vol = f.area[col] * rC * rC * c.dz;
+    const double rho = rho_a[idx];
+    const double p = c.p_ref * pow(c.Rd * rth_a[idx] / c.p_ref, c.gamma);
+    const double mx = (double)Mx[idx], my = (double)My[idx], mz = (double)Mz[idx];
+    const double wc = 0.5 * (W + W1);
+    const double ke = 0.5 * (mx * mx + my * my + mz * mz + wc * wc) / rho;
+    e = (c.Cv / c.Rd * p + ke + rho * c.grav * ((lev + 0.5) * c.dz)) * vol;
+    m = rho * vol;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    e += __shfl_down(e, o, 64);
+    m += __shfl_down(m, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sm[w][0] = e;
+    sm[w][1] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b2 = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      a += sm[i][0];
+      b2 += sm[i][1];
+    }
+    out[2 * blockIdx.x] = a;
+    out[2 * blockIdx.x + 1] = b2;
+  }
+}
+
+// One workgroup of 256: the totals of the partial sums of the step's start
+// (pa) and of the dynamics output (pb), each in a fixed order, and the
+// energy fixer's temperature increment dT = (E_a - E_b) / (Cv M_b) into *dT.
+__global__ __launch_bounds__(256) void k_efix(const double *pa, const double *pb, int nb, double cv, double *dT) {
+  __shared__ double sm[3][256];
+  double ea = 0.0, eb = 0.0, mb = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    ea += pa[2 * i];
+    eb += pb[2 * i];
+    mb += pb[2 * i + 1];
+  }
+  sm[0][threadIdx.x] = ea;
+  sm[1][threadIdx.x] = eb;
+  sm[2][threadIdx.x] = mb;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < 3; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *dT = (sm[0][0] - sm[1][0]) / (cv * sm[2][0]);
+}
+
+// Energy fixer and physics on the dynamics output: T += dT at every cell
+// (at fixed density), then the physics of the configured forcing; for
+// Held-Suarez, sigma of the fixed state goes to D for the friction kernel.
+template <typename H>
+__global__ __launch_bounds__(256) void k_fixphys(Fields<H> f, Consts c, const double *dT) {
+  const Lane ln = map_lane(c, xcd_block());
+  const size_t idx = (size_t)ln.col * c.L + ln.lev;
+  const double rho = f.rho[idx];
+  const double p0 = c.p_ref * pow(c.Rd * f.rth[idx] / c.p_ref, c.gamma);
+  double p = rho * c.Rd * (p0 / (rho * c.Rd) + *dT);
+  double sigma = 0.0;
+  p = physics_p(c, f.teq, ln.col, ln.lev, ln.lane, rho, p, sigma);
+  if (!ln.store) return;
+  f.rth[idx] = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
+  if (c.forcing == THOR_FORCING_HELD_SUAREZ) f.D[idx] = (H)sigma;
+}
+
 // Prognostic fields from a staged FP64 blob (checkpoint import).
 template <typename H>
 __device__ __forceinline__ void b_import(const Fields<H> &f, const Consts &c, const Lane &ln, const double *blob) {
@@ -1066,6 +1173,21 @@ void launch_mass(const Fields<H> &f, const Consts &c, hipStream_t s, int *nblock
   hipLaunchKernelGGL(k_mass<H>, dim3(n_blocks(c, 4)), dim3(256), 0, s, f, c);
 }
 template <typename H>
+void launch_energy(const Fields<H> &f, const Consts &c, int which, double *out, hipStream_t s, int *nblocks_out) {
+  *nblocks_out = n_blocks(c, 4);
+  hipLaunchKernelGGL(k_energy<H>, dim3(n_blocks(c, 4)), dim3(256), 0, s, f, c, which, out);
+}
+template <typename H>
+void launch_fixer(const Fields<H> &f, const Consts &c, hipStream_t s) {
+  const int nb = n_blocks(c, 4);
+  double *pa = f.epart, *pb = f.epart + 2 * (size_t)nb, *dT = f.epart + 4 * (size_t)nb;
+  hipLaunchKernelGGL(k_energy<H>, dim3(nb), dim3(256), 0, s, f, c, 1, pb);
+  hipLaunchKernelGGL(k_efix, dim3(1), dim3(256), 0, s, pa, pb, nb, c.Cv, dT);
+  hipLaunchKernelGGL(k_fixphys<H>, dim3(nb), dim3(256), 0, s, f, c, (const double *)dT);
+  if (c.forcing == THOR_FORCING_HELD_SUAREZ)
+    hipLaunchKernelGGL(k_friction<H>, dim3(nb), dim3(256), 0, s, f, c);
+}
+template <typename H>
 void launch_to_state(const Fields<H> &f, const Consts &c, const double *blob, hipStream_t s) {
   hipLaunchKernelGGL(k_import<H>, dim3(n_blocks(c, 4)), dim3(256), 0, s, f, c, blob);
 }
@@ -1107,6 +1229,8 @@ void launch_batch(const Planet<H> *P, const int2 *tiles, int n_tiles, int wpb, i
   template void launch_diag_field<H>(const Fields<H> &, const Consts &, int, hipStream_t);           \
   template void launch_mass<H>(const Fields<H> &, const Consts &, hipStream_t, int *);               \
   template void launch_to_state<H>(const Fields<H> &, const Consts &, const double *, hipStream_t);  \
+  template void launch_energy<H>(const Fields<H> &, const Consts &, int, double *, hipStream_t, int *); \
+  template void launch_fixer<H>(const Fields<H> &, const Consts &, hipStream_t);                     \
   template void launch_batch<H>(const Planet<H> *, const int2 *, int, int, int, BatchOp, int, int,  \
                                 hipStream_t);
 

@@ -100,6 +100,7 @@ void carve(Carver &cv, Fields<H> &f, size_t N, size_t L) {
   // the staging/diagnostic area doubles as checkpoint staging (6 fields)
   f.diag = cv.take<double>(6 * NL);
   f.partial = cv.take<double>(2 * ((N + 3) / 4 + 16));
+  f.epart = cv.take<double>(4 * ((N + 3) / 4 + 16) + 8);
 }
 
 template <typename H>
@@ -139,8 +140,9 @@ bool validate(const thor_planet *pl, const thor_vertical *v, const thor_numerics
     return false;
   }
   if (!(num->dt > 0) || !(num->diff_D >= 0) || (num->precision != THOR_FP64 && num->precision != THOR_MIXED) ||
-      (num->div_damp != 0 && num->div_damp != 1)) {
-    set_error("thor_state_init: numerics need dt > 0, diff_D >= 0, precision FP64|MIXED, div_damp 0|1");
+      (num->div_damp != 0 && num->div_damp != 1) || (num->energy_fixer != 0 && num->energy_fixer != 1)) {
+    set_error("thor_state_init: numerics need dt > 0, diff_D >= 0, precision FP64|MIXED, div_damp 0|1, "
+              "energy_fixer 0|1");
     return false;
   }
   if (fo->kind != THOR_FORCING_NONE && fo->kind != THOR_FORCING_NEWTONIAN && fo->kind != THOR_FORCING_HOT_JUPITER &&
@@ -287,6 +289,10 @@ template <typename H>
 void enqueue_large_step(thor_state *s, const Fields<H> &f, int n, hipStream_t st) {
   const Consts &c = s->c;
   const int *it = s->wpb;
+  if (c.energy_fixer) {   // energy of the step's start (not a timed family)
+    int nb = 0;
+    launch_energy(f, c, 0, f.epart, st, &nb);
+  }
   timed(s, st, "large", [&] { launch_large(f, c, it[FAM_LARGE], st); });
   const int ns[3] = {1, n / 2, n};
   const int div[3] = {3, n, n};   // dtau = dt / div
@@ -295,9 +301,10 @@ void enqueue_large_step(thor_state *s, const Fields<H> &f, int n, hipStream_t st
     for (int i = 0; i < ns[stage]; ++i) {
       const bool first = i == 0, last = stage == 2 && i + 1 == ns[stage];
       timed(s, st, "hmom", [&] { launch_hmom(f, c, it[FAM_HMOM], div[stage], first, st); });
-      timed(s, st, "vert", [&] { launch_vert(f, c, it[FAM_VERT], div[stage], first, last, st); });
+      timed(s, st, "vert", [&] { launch_vert(f, c, it[FAM_VERT], div[stage], first, last && !c.energy_fixer, st); });
     }
   }
+  if (c.energy_fixer) launch_fixer(f, c, st);
 }
 
 void enqueue(thor_state *s, int n, int parity, hipStream_t st) {
@@ -360,6 +367,8 @@ int diag_impl(thor_state *s, const Fields<H> &f, int kind, int field, void *host
     if (out_bytes < sizeof(double)) { set_error("thor_diag: out_bytes too small"); return THOR_EINVAL; }
   } else if (kind == THOR_DIAG_SCALARS) {
     if (out_bytes < sizeof(thor_scalars)) { set_error("thor_diag: out_bytes too small"); return THOR_EINVAL; }
+  } else if (kind == THOR_DIAG_ENERGY) {
+    if (out_bytes < sizeof(double)) { set_error("thor_diag: out_bytes too small"); return THOR_EINVAL; }
   } else if (kind == THOR_DIAG_STATE_EXPORT) {
     if (out_bytes < thor_state_blob_bytes(s)) { set_error("thor_diag: out_bytes too small"); return THOR_EINVAL; }
   } else {
@@ -385,6 +394,16 @@ int diag_impl(thor_state *s, const Fields<H> &f, int kind, int field, void *host
   };
   if (kind == THOR_DIAG_MASS) {
     *(double *)host_out = mass;
+  } else if (kind == THOR_DIAG_ENERGY) {
+    int ne = 0;
+    launch_energy(f, c, 0, f.partial, st, &ne);
+    std::vector<double> ep(2 * (size_t)ne);
+    if (!hip_ok(hipMemcpyAsync(ep.data(), f.partial, ep.size() * sizeof(double), hipMemcpyDeviceToHost, st), "copy energy") ||
+        !hip_ok(hipStreamSynchronize(st), "diag synchronize"))
+      return THOR_EHIP;
+    double e = 0.0;
+    for (int i = 0; i < ne; ++i) e += ep[2 * i];
+    *(double *)host_out = e;
   } else if (kind == THOR_DIAG_FIELD) {
     if (!field_to_host(field, (double *)host_out)) return THOR_EHIP;
   } else if (kind == THOR_DIAG_SCALARS) {
@@ -480,6 +499,7 @@ int thor_state_init(const thor_grid *g, const thor_planet *pl, const thor_vertic
   c.Kd = num->diff_D * std::pow(dbar, 4) / num->dt;                                             // Eq. kd
   c.dt = num->dt;
   c.div_damp = num->div_damp;
+  c.energy_fixer = num->energy_fixer;
   c.forcing = fo->kind;
   c.tau = (fo->kind == THOR_FORCING_NEWTONIAN || fo->kind == THOR_FORCING_HOT_JUPITER) ? fo->tau : 1.0;
   c.hs_kf = fo->k_f;
@@ -787,8 +807,13 @@ int thor_batch_init(int n, const thor_grid *const *grids, const thor_planet *pl,
   int rc = thor_batch_bytes(n, grids, v, num, &need);
   if (rc != THOR_OK) return rc;
   if (dev_bytes < need) { set_error("thor_batch_init: dev_bytes smaller than thor_batch_bytes"); return THOR_ENOMEM; }
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
     if (!validate(&pl[i], &v[i], &num[i], &fo[i], &in[i])) return THOR_EINVAL;
+    if (num[i].energy_fixer) {
+      set_error("thor_batch_init: the energy fixer is not available in ensembles");
+      return THOR_EINVAL;
+    }
+  }
   thor_batch *b = new (std::nothrow) thor_batch;
   if (!b) { set_error("thor_batch_init: out of host memory"); return THOR_ENOMEM; }
   b->n = n;

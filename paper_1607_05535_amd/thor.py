@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libthor.so")
 THOR_OK, THOR_EINVAL, THOR_ENOMEM, THOR_EHIP, THOR_ENONFINITE, THOR_ENOTCONV = 0, -1, -2, -3, -4, -5
 THOR_FP64, THOR_MIXED = 0, 1
 THOR_FORCING_NONE, THOR_FORCING_NEWTONIAN, THOR_FORCING_HOT_JUPITER, THOR_FORCING_HELD_SUAREZ = 0, 1, 2, 3
-THOR_DIAG_MASS, THOR_DIAG_FIELD, THOR_DIAG_STATE_EXPORT, THOR_DIAG_SCALARS = 1, 2, 3, 4
+THOR_DIAG_MASS, THOR_DIAG_FIELD, THOR_DIAG_STATE_EXPORT, THOR_DIAG_SCALARS, THOR_DIAG_ENERGY = 1, 2, 3, 4, 5
 FIELDS = {"T": 0, "u": 1, "v": 2, "w": 3, "p": 4, "rho": 5, "rhotheta": 6,
           "Mx": 7, "My": 8, "Mz": 9, "W": 10}
 
@@ -59,7 +59,7 @@ class Vertical(ctypes.Structure):
 
 class Numerics(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("diff_D", ctypes.c_double), ("div_damp", ctypes.c_int),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("energy_fixer", ctypes.c_int)]
 
 
 class Forcing(ctypes.Structure):
@@ -357,7 +357,7 @@ class Grid:
 def structs_from_workload(w, precision=THOR_FP64):
     planet = Planet(w.radius, w.omega, w.gravity, w.Rd, w.Cp, w.p_ref)
     vert = Vertical(w.n_lev, w.z_top)
-    num = Numerics(w.dt, w.diff_D, int(w.div_damp), precision)
+    num = Numerics(w.dt, w.diff_D, int(w.div_damp), precision, int(w.energy_fixer))
     forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar,
                       w.lapse, w.z_strat, w.dT_strat, w.sigma_strat, w.k_f, w.k_a, w.k_s, w.sigma_b,
                       w.dT_y, w.dtheta_z, w.p_star, w.T_top, w.T_min)
@@ -388,6 +388,11 @@ class State:
     def mass(self):
         out = np.empty(1)
         rc = thor_diag(self.handle, THOR_DIAG_MASS, 0, out)
+        return float(out[0]), rc
+
+    def energy(self):
+        out = np.empty(1)
+        rc = thor_diag(self.handle, THOR_DIAG_ENERGY, 0, out)
         return float(out[0]), rc
 
     def scalars(self):
@@ -423,6 +428,7 @@ class Member:
 
     field = State.field
     mass = State.mass
+    energy = State.energy
     scalars = State.scalars
     export = State.export
 
