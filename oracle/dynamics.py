@@ -65,6 +65,7 @@ class Numerics:
     diff_D: float
     div_damp: bool = True
     energy_fixer: bool = False   # Sec. 3: globally uniform internal-energy fixer
+    hydrostatic: bool = False    # Sec. 3: hydrostatic approximation
 
 
 @dataclass
@@ -361,11 +362,22 @@ def acoustic_substep(model, st, f, dtau, large):
         c1 = dtau / dz
         c2 = 0.5 * g * dtau
         a = -c1 * Gam[:, j - 1] * am[j - 1] * th[:, j - 1] + c2 * am[j - 1]
-        b = (1.0 + c1 * th[:, j] * (Gam[:, j] * am[j] + Gam[:, j - 1] * ap[j - 1])
-             + c2 * (am[j] - ap[j - 1]))
         c = -c1 * Gam[:, j] * ap[j] * th[:, j + 1] - c2 * ap[j]
-        d = (st.W[:, j] + dtau * f["S_W"][:, j] - c1 * (p_hs[:, j] - p_hs[:, j - 1])
-             - c2 * (rho_hs[:, j - 1] + rho_hs[:, j]))
+        if model.num.hydrostatic:
+            # no vertical acceleration (no time derivative, advection or
+            # other slow terms of rho v_r): the new W is the one that leaves
+            # the end of the substep in hydrostatic balance, the [t]
+            # imbalance I plus the deviation pressure gradient and buoyancy
+            # summing to zero
+            b = (c1 * th[:, j] * (Gam[:, j] * am[j] + Gam[:, j - 1] * ap[j - 1])
+                 + c2 * (am[j] - ap[j - 1]))
+            d = (dtau * large["I"][:, j] - c1 * (p_hs[:, j] - p_hs[:, j - 1])
+                 - c2 * (rho_hs[:, j - 1] + rho_hs[:, j]))
+        else:
+            b = (1.0 + c1 * th[:, j] * (Gam[:, j] * am[j] + Gam[:, j - 1] * ap[j - 1])
+                 + c2 * (am[j] - ap[j - 1]))
+            d = (st.W[:, j] + dtau * f["S_W"][:, j] - c1 * (p_hs[:, j] - p_hs[:, j - 1])
+                 - c2 * (rho_hs[:, j - 1] + rho_hs[:, j]))
         W[:, 1:L] = thomas(a, b, c, d)
     W[:, 0] = 0.0
     W[:, L] = 0.0
@@ -534,7 +546,7 @@ def model_from_workload(w, G):
     """Oracle model and initial state for a workload recipe (``workloads``)."""
     planet = Planet(w.radius, w.omega, w.gravity, w.Rd, w.Cp, w.p_ref)
     vert = Vertical(w.n_lev, w.z_top)
-    num = Numerics(w.dt, w.diff_D, w.div_damp, w.energy_fixer)
+    num = Numerics(w.dt, w.diff_D, w.div_damp, w.energy_fixer, w.hydrostatic)
     forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar,
                       w.lapse, w.z_strat, w.dT_strat, w.sigma_strat, w.k_f, w.k_a, w.k_s, w.sigma_b,
                       w.dT_y, w.dtheta_z, w.p_star, w.T_top, w.T_min)

@@ -1,0 +1,96 @@
+"""Pins of the oracle's switchable approximations (Sec. 3 lists them: the
+model implements them although the paper's runs leave them off)."""
+import numpy as np
+
+from oracle import dynamics as dy
+from tests.conftest import oracle_grid
+from tests.gpu_util import small_earth
+
+
+def _model(w):
+    return dy.model_from_workload(w, oracle_grid(w.glevel))
+
+
+def _one_substep(model, st, dtau):
+    """Large-step terms, first-stage slow forcing and one substep of dtau."""
+    large = dy.large_step_terms(model, st)
+    f = dy.slow_forcing(model, st, large)
+    return large, f, dy.acoustic_substep(model, st, f, dtau, large)
+
+
+def _imbalance(model, st, large):
+    """I + deviation pressure gradient + buoyancy at the interior interfaces:
+    the vertical-momentum tendency without its slow terms."""
+    g, dz = model.planet.gravity, model.dz
+    ps = model.eos(st.rth) - large["p_t"]
+    rs = st.rho - large["rho_t"]
+    return (large["I"][:, 1:-1] - (ps[:, 1:] - ps[:, :-1]) / dz
+            - 0.5 * g * (rs[:, :-1] + rs[:, 1:]))
+
+
+def test_hydrostatic_substep_balances_the_column():
+    """T noise at fixed p leaves the initial columns out of hydrostatic
+    balance (buoyancy).  One short hydrostatic substep (2 s, a vertical
+    acoustic Courant number of about 0.4) removes the imbalance up to the
+    linearisation of the equation of state, second order in the 0.1 K
+    noise; a non-hydrostatic one only starts to accelerate W."""
+    res = {}
+    for hyd in (False, True):
+        w = small_earth(glevel=2, n_lev=12, noise=0.1)
+        w.hydrostatic = hyd
+        model, st = _model(w)
+        large, f, out = _one_substep(model, st, 2.0)
+        # the imbalance measured against the state's own [t] terms
+        r0 = np.abs(_imbalance(model, st, large)).max()
+        r1 = np.abs(_imbalance(model, out, large)).max()
+        res[hyd] = r1 / r0
+    assert res[True] < 1e-3
+    assert res[False] > 0.5
+
+
+def test_hydrostatic_substep_forgets_the_vertical_momentum():
+    """Without vertical acceleration the new W does not depend on the old W
+    nor on the slow forcing of W (divergence damping off: its 3D divergence
+    reads W)."""
+    w = small_earth(glevel=2, n_lev=10, noise=1.0)
+    w.hydrostatic = True
+    w.div_damp = False
+    model, st = _model(w)
+    large = dy.large_step_terms(model, st)
+    f = dy.slow_forcing(model, st, large)
+    a = dy.acoustic_substep(model, st, f, 100.0, large)
+    rs = np.random.default_rng(5)
+    W2 = st.W.copy()
+    W2[:, 1:-1] += rs.normal(size=W2[:, 1:-1].shape)
+    f2 = dict(f)
+    f2["S_W"] = f["S_W"] + rs.normal(size=f["S_W"].shape)
+    b = dy.acoustic_substep(model, dy.State(st.rho, st.M, st.rth, W2), f2, 100.0, large)
+    for x, y in ((a.W, b.W), (a.rho, b.rho), (a.rth, b.rth), (a.M, b.M)):
+        assert np.array_equal(x, y)
+
+
+def test_hydrostatic_rest_state_stays_at_rest():
+    w = small_earth(glevel=2, n_lev=12, n_large=3, noise=0.0)
+    w.hydrostatic = True
+    model, st = _model(w)
+    out = dy.run(model, st, w.n_large, w.n_acoustic)
+    f = dy.fields(model, out)
+    for k in ("u", "v", "w"):
+        assert np.abs(f[k]).max() < 1e-8, k
+
+
+def test_hydrostatic_and_nonhydrostatic_agree_at_hydrostatic_scales():
+    """Cells ~1000 km wide and 1.8 km deep: the horizontal winds of the two
+    forms differ little after three steps, while the vertical velocity (a
+    diagnosed balance in one, a prognostic in the other) may differ more."""
+    out = {}
+    for hyd in (False, True):
+        w = small_earth(glevel=3, n_lev=20, n_large=3, noise=1.0)
+        w.hydrostatic = hyd
+        model, st = _model(w)
+        out[hyd] = dy.fields(model, dy.run(model, st, w.n_large, w.n_acoustic))
+    speed = np.sqrt(out[False]["u"] ** 2 + out[False]["v"] ** 2).max()
+    du = max(np.abs(out[True][k] - out[False][k]).max() for k in ("u", "v"))
+    dT = np.abs(out[True]["T"] - out[False]["T"]).max()
+    assert 1e-6 * speed < du < 0.01 * speed      # a real change, and a small one
+    assert dT < 0.005

@@ -60,6 +60,7 @@ class Workload:
     T_top: float = 315.0
     T_min: float = 200.0
     energy_fixer: bool = False
+    hydrostatic: bool = False
     extra: dict = field(default_factory=dict)
 
     @property
