@@ -146,6 +146,14 @@ typedef struct {
                       uniform internal-energy adjustment of Williamson (2009)
                       that the paper implements but leaves off for its
                       results (Sec. 3).  Not available in ensembles. */
+  int hydrostatic;  /* 1: the hydrostatic approximation of Sec. 3: no
+                      vertical acceleration (time derivative, advection and
+                      other slow terms of rho v_r dropped); each acoustic
+                      substep's tridiagonal then gives the W that leaves the
+                      columns in hydrostatic balance at the substep's end
+                      (the [t] imbalance plus the deviation pressure gradient
+                      and buoyancy sum to zero).  0: the paper's
+                      non-hydrostatic equations. */
 } thor_numerics;
 
 /* Physics after each large step (Sec. 5, Eq. im_eq_t): backward-Euler

@@ -67,6 +67,7 @@ struct Consts {
   double dt;
   int div_damp;
   int energy_fixer;       // 1: uniform internal-energy fixer after the dynamics
+  int hydrostatic;        // 1: no vertical acceleration in the acoustic substeps
   int forcing;
   double tau;
   // hot-Jupiter benchmark forcing (Eqs. teq-hj, btrop, tvert)

@@ -398,12 +398,25 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
   const double am_m = shfl(am, lm);    // alpha- of cell lev-1
   const double c1 = dtau / dz, c2 = 0.5 * c.grav * dtau;
 
+  // first term of the row's right-hand side: the old W and its slow
+  // forcing, or in the hydrostatic form (no vertical acceleration, so W
+  // leaves the end of the substep balanced) only the [t] imbalance of
+  // interface lev
+  double d0;
+  if (c.hydrostatic) {
+    const double rt = f.rho_t[idx];
+    const double pt_m = shfl(pt, lm), rt_m = shfl(rt, lm);
+    d0 = dtau * (-(pt - pt_m) / dz - 0.5 * c.grav * (rt_m + rt));
+  } else {
+    d0 = Wj + dtau * f.SW[idx];
+  }
   double a = 0.0, b = 1.0, cc = 0.0, d = 0.0;
   if (ln.real_col && lev > 0) {
     a = lev == 1 ? 0.0 : -c1 * gam_m * am_m * thI_m + c2 * am_m;
-    b = 1.0 + c1 * thI * (gam * am + gam_m * ap_m) + c2 * (am - ap_m);
+    b = c.hydrostatic ? c1 * thI * (gam * am + gam_m * ap_m) + c2 * (am - ap_m)
+                      : 1.0 + c1 * thI * (gam * am + gam_m * ap_m) + c2 * (am - ap_m);
     cc = lev == L - 1 ? 0.0 : -c1 * gam * ap * thI_p - c2 * ap;
-    d = Wj + dtau * f.SW[idx] - c1 * (phs - phs_m) - c2 * (rhs_m + rhs);
+    d = d0 - c1 * (phs - phs_m) - c2 * (rhs_m + rhs);
   }
   // cyclic reduction: after the round with stride s every row couples only
   // to rows lev -/+ 2s of the same column

@@ -140,9 +140,10 @@ bool validate(const thor_planet *pl, const thor_vertical *v, const thor_numerics
     return false;
   }
   if (!(num->dt > 0) || !(num->diff_D >= 0) || (num->precision != THOR_FP64 && num->precision != THOR_MIXED) ||
-      (num->div_damp != 0 && num->div_damp != 1) || (num->energy_fixer != 0 && num->energy_fixer != 1)) {
+      (num->div_damp != 0 && num->div_damp != 1) || (num->energy_fixer != 0 && num->energy_fixer != 1) ||
+      (num->hydrostatic != 0 && num->hydrostatic != 1)) {
     set_error("thor_state_init: numerics need dt > 0, diff_D >= 0, precision FP64|MIXED, div_damp 0|1, "
-              "energy_fixer 0|1");
+              "energy_fixer 0|1, hydrostatic 0|1");
     return false;
   }
   if (fo->kind != THOR_FORCING_NONE && fo->kind != THOR_FORCING_NEWTONIAN && fo->kind != THOR_FORCING_HOT_JUPITER &&
@@ -500,6 +501,7 @@ int thor_state_init(const thor_grid *g, const thor_planet *pl, const thor_vertic
   c.dt = num->dt;
   c.div_damp = num->div_damp;
   c.energy_fixer = num->energy_fixer;
+  c.hydrostatic = num->hydrostatic;
   c.forcing = fo->kind;
   c.tau = (fo->kind == THOR_FORCING_NEWTONIAN || fo->kind == THOR_FORCING_HOT_JUPITER) ? fo->tau : 1.0;
   c.hs_kf = fo->k_f;

@@ -1,0 +1,42 @@
+"""The switchable approximations of Sec. 3 through the C ABI against the
+oracle (FP64 parity, same bar as the default equations)."""
+import pytest
+
+import workloads
+from tests.gpu_util import lib_fields, lib_state, oracle_fields, rel_errors, say, small_earth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _parity(w, precision=0, tol=TOL, names=("T", "u", "v", "w", "p", "rho", "rhotheta")):
+    say(f"[variant] {w.name} g{w.glevel} L{w.n_lev} hydrostatic={w.hydrostatic} "
+        f"n_large={w.n_large} precision={precision}")
+    st = lib_state(w, precision)
+    st.step(w.n_large, w.n_acoustic)
+    got = lib_fields(st, names)
+    ref = oracle_fields(w)
+    err = rel_errors(got, ref)
+    say(f"          errors {err}")
+    for k, e in err.items():
+        assert e < tol, (k, e)
+
+
+@pytest.mark.parametrize("n_lev", [1, 12, 33])
+def test_hydrostatic_earth(n_lev):
+    w = small_earth(glevel=3, n_lev=n_lev, n_large=3, noise=1.0)
+    w.hydrostatic = True
+    _parity(w)
+
+
+def test_hydrostatic_gas_giant_with_forcing():
+    w = workloads.small_gas_giant(glevel=3, n_lev=20, n_large=3)
+    w.hydrostatic = True
+    _parity(w)
+
+
+def test_hydrostatic_mixed_precision_stays_close():
+    w = workloads.small_gas_giant(glevel=3, n_lev=20, n_large=3)
+    w.hydrostatic = True
+    _parity(w, precision=1, tol=1e-5, names=("T", "p", "rho"))
