@@ -66,6 +66,7 @@ class Numerics:
     div_damp: bool = True
     energy_fixer: bool = False   # Sec. 3: globally uniform internal-energy fixer
     hydrostatic: bool = False    # Sec. 3: hydrostatic approximation
+    shallow: bool = False        # Sec. 3: shallow atmosphere, traditional approximation
 
 
 @dataclass
@@ -127,6 +128,12 @@ class Model:
         self.zC = (np.arange(L) + 0.5) * self.dz
         self.rI = pl.radius + self.zI
         self.rC = pl.radius + self.zC
+        if self.num.shallow:
+            # shallow atmosphere: every distance from the centre is the
+            # planet radius (horizontal operators, vertical flux
+            # divergence, volumes)
+            self.rI = np.full(L + 1, pl.radius)
+            self.rC = np.full(L, pl.radius)
         # Eq. kd with dbar of Eq. grid_qts
         dbar = grid_mod.mean_spacing(self.G.g, pl.radius)
         self.Kd = self.num.diff_D * dbar ** 4 / self.num.dt
@@ -287,26 +294,51 @@ def slow_forcing(model, prev, large):
     G, rC, rhat = model.G, model.rC, model.rhat
     L = model.vert.n_lev
     rh = rhat[:, None, :]
-    # full Cartesian momentum m = M + Wbar rhat and velocity m / rho
-    m = prev.M + to_centres(prev.W)[..., None] * rh
-    v = m / prev.rho[..., None]
-    # advection A_q = div(v_q M) + (1/r^2) d(r^2 W v_q)/dr
-    A = np.zeros_like(m)
-    for q in range(3):
-        A[..., q] = op.div(G, v[..., q, None] * prev.M, rC)
-    vI = np.zeros((G.n, L + 1, 3))
-    vI[:, 1:L] = to_interfaces(v)
-    A += vertical_div(model, prev.W[..., None] * vI)
-    # Coriolis 2 Omega zhat x m
     Om = model.planet.omega
-    C = np.zeros_like(m)
-    C[..., 0] = -2.0 * Om * m[..., 1]
-    C[..., 1] = 2.0 * Om * m[..., 0]
-    AC = A + C
-    S_M = op.proj_h(-large["G_t"] - AC, rhat) + large["H_M"]
-    S_W = np.zeros((G.n, L + 1))
-    ACr = op.proj_r(AC, rhat)
-    S_W[:, 1:L] = large["I"][:, 1:L] - to_interfaces(ACr) + large["H_W"][:, 1:L]
+    if model.num.shallow:
+        # shallow atmosphere with the traditional approximation: the
+        # horizontal momentum is carried by the horizontal velocity M / rho
+        # (no metric terms in w), the vertical momentum as the scalar
+        # w = rho v_r / rho (no curvature term from the horizontal motion),
+        # and the Coriolis force keeps only the local vertical component of
+        # Omega acting on the horizontal motion
+        v = prev.M / prev.rho[..., None]
+        A = np.zeros_like(prev.M)
+        for q in range(3):
+            A[..., q] = op.div(G, v[..., q, None] * prev.M, rC)
+        vI = np.zeros((G.n, L + 1, 3))
+        vI[:, 1:L] = to_interfaces(v)
+        A += vertical_div(model, prev.W[..., None] * vI)
+        C = 2.0 * Om * rhat[:, None, 2:3] * np.cross(np.broadcast_to(rh, prev.M.shape), prev.M)
+        AC = A + C
+        S_M = op.proj_h(-large["G_t"] - AC, rhat) + large["H_M"]
+        w = to_centres(prev.W) / prev.rho
+        Ar = op.div(G, w[..., None] * prev.M, rC)
+        wI = np.zeros((G.n, L + 1))
+        wI[:, 1:L] = to_interfaces(w)
+        Ar = Ar + vertical_div(model, prev.W * wI)
+        S_W = np.zeros((G.n, L + 1))
+        S_W[:, 1:L] = large["I"][:, 1:L] - to_interfaces(Ar) + large["H_W"][:, 1:L]
+    else:
+        # full Cartesian momentum m = M + Wbar rhat and velocity m / rho
+        m = prev.M + to_centres(prev.W)[..., None] * rh
+        v = m / prev.rho[..., None]
+        # advection A_q = div(v_q M) + (1/r^2) d(r^2 W v_q)/dr
+        A = np.zeros_like(m)
+        for q in range(3):
+            A[..., q] = op.div(G, v[..., q, None] * prev.M, rC)
+        vI = np.zeros((G.n, L + 1, 3))
+        vI[:, 1:L] = to_interfaces(v)
+        A += vertical_div(model, prev.W[..., None] * vI)
+        # Coriolis 2 Omega zhat x m
+        C = np.zeros_like(m)
+        C[..., 0] = -2.0 * Om * m[..., 1]
+        C[..., 1] = 2.0 * Om * m[..., 0]
+        AC = A + C
+        S_M = op.proj_h(-large["G_t"] - AC, rhat) + large["H_M"]
+        S_W = np.zeros((G.n, L + 1))
+        ACr = op.proj_r(AC, rhat)
+        S_W[:, 1:L] = large["I"][:, 1:L] - to_interfaces(ACr) + large["H_W"][:, 1:L]
     thetaC = prev.rth / prev.rho
     thetaI = np.empty((G.n, L + 1))
     thetaI[:, 1:L] = to_interfaces(thetaC)
@@ -546,7 +578,7 @@ def model_from_workload(w, G):
     """Oracle model and initial state for a workload recipe (``workloads``)."""
     planet = Planet(w.radius, w.omega, w.gravity, w.Rd, w.Cp, w.p_ref)
     vert = Vertical(w.n_lev, w.z_top)
-    num = Numerics(w.dt, w.diff_D, w.div_damp, w.energy_fixer, w.hydrostatic)
+    num = Numerics(w.dt, w.diff_D, w.div_damp, w.energy_fixer, w.hydrostatic, w.shallow)
     forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar,
                       w.lapse, w.z_strat, w.dT_strat, w.sigma_strat, w.k_f, w.k_a, w.k_s, w.sigma_b,
                       w.dT_y, w.dtheta_z, w.p_star, w.T_top, w.T_min)

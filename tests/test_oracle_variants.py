@@ -94,3 +94,63 @@ def test_hydrostatic_and_nonhydrostatic_agree_at_hydrostatic_scales():
     dT = np.abs(out[True]["T"] - out[False]["T"]).max()
     assert 1e-6 * speed < du < 0.01 * speed      # a real change, and a small one
     assert dT < 0.005
+
+
+def _zonal_flow_state(model, st, U):
+    """The state's density and rho theta with u = U cos(lat) at every level,
+    no vertical motion."""
+    lam, phi = dy.lon_lat(model.rhat)
+    east = np.stack([-np.sin(lam), np.cos(lam), np.zeros_like(lam)], axis=-1)
+    u = U * np.cos(phi)
+    M = st.rho[..., None] * (u[:, None, None] * east[:, None, :])
+    return dy.State(st.rho, M, st.rth, np.zeros_like(st.W)), u, phi
+
+
+def test_vertical_momentum_forcing_of_a_zonal_flow():
+    """u = U cos(lat), w = 0.  Deep form: the radial equation receives the
+    curvature and Coriolis accelerations rho (u^2 / r + 2 Omega u cos(lat))
+    (up to the discretisation); shallow form with the traditional
+    approximation: neither, so S_W is the [t] imbalance plus hyperdiffusion
+    alone."""
+    U = 60.0
+    for shallow in (False, True):
+        w = small_earth(glevel=4, n_lev=6, noise=0.0)
+        w.shallow = shallow
+        model, st = _model(w)
+        st, u, phi = _zonal_flow_state(model, st, U)
+        large = dy.large_step_terms(model, st)
+        f = dy.slow_forcing(model, st, large)
+        extra = f["S_W"][:, 1:-1] - (large["I"][:, 1:-1] + large["H_W"][:, 1:-1])
+        if shallow:
+            assert np.abs(extra).max() <= 1e-12 * np.abs(large["I"][:, 1:-1]).max()
+        else:
+            Om, rI = model.planet.omega, model.rI[1:-1]
+            rhoI = 0.5 * (st.rho[:, :-1] + st.rho[:, 1:])
+            acc = (u * u)[:, None] / rI[None, :] + (2 * Om * u * np.cos(phi))[:, None]
+            ref = rhoI * acc
+            err = np.abs(extra - ref).max() / np.abs(ref).max()
+            assert err < 2e-3, err
+
+
+def test_shallow_rest_state_stays_at_rest():
+    w = small_earth(glevel=2, n_lev=12, n_large=3, noise=0.0)
+    w.shallow = True
+    model, st = _model(w)
+    f = dy.fields(model, dy.run(model, st, w.n_large, w.n_acoustic))
+    for k in ("u", "v", "w"):
+        assert np.abs(f[k]).max() < 1e-8, k
+
+
+def test_shallow_and_deep_agree_for_a_thin_atmosphere():
+    """A 36 km atmosphere on a 6371 km planet: the two forms differ at the
+    order of H / A in their geometry and by the dropped small terms."""
+    out = {}
+    for shallow in (False, True):
+        w = small_earth(glevel=3, n_lev=20, n_large=3, noise=1.0)
+        w.shallow = shallow
+        model, st = _model(w)
+        st, _, _ = _zonal_flow_state(model, st, 30.0)
+        out[shallow] = dy.fields(model, dy.run(model, st, w.n_large, w.n_acoustic))
+    speed = np.sqrt(out[False]["u"] ** 2 + out[False]["v"] ** 2).max()
+    du = max(np.abs(out[True][k] - out[False][k]).max() for k in ("u", "v"))
+    assert 1e-6 * speed < du < 0.01 * speed

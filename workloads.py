@@ -61,6 +61,7 @@ class Workload:
     T_min: float = 200.0
     energy_fixer: bool = False
     hydrostatic: bool = False
+    shallow: bool = False
     extra: dict = field(default_factory=dict)
 
     @property
