@@ -154,6 +154,16 @@ typedef struct {
                       (the [t] imbalance plus the deviation pressure gradient
                       and buoyancy sum to zero).  0: the paper's
                       non-hydrostatic equations. */
+  int shallow;      /* 1: the shallow-atmosphere approximation of Sec. 3 with
+                      the traditional approximation: every distance from the
+                      centre is the planet radius (horizontal operators,
+                      vertical flux divergence, volumes); the horizontal
+                      momentum is advected by the horizontal velocity and the
+                      vertical velocity as a scalar (no metric terms in w,
+                      no curvature term in the vertical equation); the
+                      Coriolis force is 2 Omega sin(lat) rhat x (rho v_h).
+                      0: the paper's deep atmosphere.  Not available in
+                      ensembles. */
 } thor_numerics;
 
 /* Physics after each large step (Sec. 5, Eq. im_eq_t): backward-Euler

@@ -68,6 +68,7 @@ struct Consts {
   int div_damp;
   int energy_fixer;       // 1: uniform internal-energy fixer after the dynamics
   int hydrostatic;        // 1: no vertical acceleration in the acoustic substeps
+  int shallow;            // 1: shallow atmosphere (r = radius), traditional Coriolis
   int forcing;
   double tau;
   // hot-Jupiter benchmark forcing (Eqs. teq-hj, btrop, tvert)

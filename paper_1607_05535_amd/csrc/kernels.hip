@@ -75,8 +75,14 @@ __device__ __forceinline__ H eos(double rth, const Consts &c) {
   return (H)(c.p_ref * pow(c.Rd * rth / c.p_ref, c.gamma));
 }
 
-__device__ __forceinline__ double radius_c(const Consts &c, int lev) { return c.radius + (lev + 0.5) * c.dz; }
-__device__ __forceinline__ double radius_i(const Consts &c, int lev) { return c.radius + lev * c.dz; }
+// Distance from the planet's centre of level centres and interfaces (the
+// planet radius at every level in the shallow-atmosphere form).
+__device__ __forceinline__ double radius_c(const Consts &c, int lev) {
+  return c.shallow ? c.radius : c.radius + (lev + 0.5) * c.dz;
+}
+__device__ __forceinline__ double radius_i(const Consts &c, int lev) {
+  return c.shallow ? c.radius : c.radius + lev * c.dz;
+}
 
 // Neighbour ids of a column; a pentagon's missing 6th neighbour points at the
 // column itself (its coefficients are zero).
@@ -388,7 +394,7 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
   const double rhs_m = shfl(rhs, lm);
 
   const double dz = c.dz;
-  const double rI = radius_i(c, lev), rI1 = rI + dz;
+  const double rI = radius_i(c, lev), rI1 = c.shallow ? rI : rI + dz;
   const double rC = radius_c(c, lev);
   const double irc2dz = 1.0 / (rC * rC * dz);
   const double gp = rI1 * rI1 * irc2dz, gm = rI * rI * irc2dz;
@@ -480,7 +486,7 @@ __device__ __forceinline__ void b_friction(const Fields<H> &f, const Consts &c, 
 // full Cartesian momentum, Coriolis, projections (Eqs. mom, proj_h, proj_r),
 // and the linearisation coefficients theta_L and gamma p / (rho theta).
 // ---------------------------------------------------------------------------
-template <typename H, bool VEC>
+template <typename H, bool VEC, bool SHALLOW>
 __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, const HLane &ln, int from_t) {
   const int L = c.L, col = ln.col, nv = ln.nv, lev0 = ln.lev0;
   const int lane = threadIdx.x & 63;
@@ -499,10 +505,13 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
   const H *rh = f.rhat + (size_t)col * 3;
   const H rx = rh[0], ry = rh[1], rz = rh[2];
 
-  // own column: full momentum m = M + Wbar rhat and velocity m / rho
+  // own column: full momentum m = M + Wbar rhat and velocity m / rho (in the
+  // shallow form the horizontal momentum M and velocity M / rho, with the
+  // vertical velocity w = Wbar / rho advected as a scalar in Ar)
   double Wk[kHq], rho0[kHq];
   H fx[kHq], fy[kHq], fz[kHq], vx0[kHq], vy0[kHq], vz0[kHq];
   H Ax[kHq], Ay[kHq], Az[kHq];
+  H w0[kHq], Ar[kHq];
   {
     ld4<VEC>(W + idx, nv, Wk);
     if (lev0 == 0) Wk[0] = 0.0;
@@ -517,9 +526,15 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
     for (int q = 0; q < kHq; ++q) {
       const double up = lev0 + q == L - 1 ? 0.0 : (q + 1 < kHq ? Wk[q + 1] : Wn);
       const H wbar = (H)(0.5 * (Wk[q] + up));
-      fx[q] = mx0[q] + wbar * rx;
-      fy[q] = my0[q] + wbar * ry;
-      fz[q] = mz0[q] + wbar * rz;
+      if (SHALLOW) {
+        fx[q] = mx0[q];
+        fy[q] = my0[q];
+        fz[q] = mz0[q];
+      } else {
+        fx[q] = mx0[q] + wbar * rx;
+        fy[q] = my0[q] + wbar * ry;
+        fz[q] = mz0[q] + wbar * rz;
+      }
       const H irho0 = (H)1 / (H)rho0[q];
       vx0[q] = fx[q] * irho0;
       vy0[q] = fy[q] * irho0;
@@ -529,6 +544,10 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
       Ax[q] = vx0[q] * t;
       Ay[q] = vy0[q] * t;
       Az[q] = vz0[q] * t;
+      if (SHALLOW) {
+        w0[q] = wbar * irho0;
+        Ar[q] = w0[q] * t;
+      }
     }
   }
 #pragma unroll 1
@@ -551,15 +570,23 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
       const double up = lev0 + q == L - 1 ? 0.0 : (q + 1 < kHq ? wn[q + 1] : wnn);
       const H wb = (H)(0.5 * (wn[q] + up));
       const H t = (cx * mxj[q] + cy * myj[q] + cz * mzj[q]) / (H)rj[q];
-      Ax[q] += (mxj[q] + wb * rnx) * t;
-      Ay[q] += (myj[q] + wb * rny) * t;
-      Az[q] += (mzj[q] + wb * rnz) * t;
+      if (SHALLOW) {
+        Ax[q] += mxj[q] * t;
+        Ay[q] += myj[q] * t;
+        Az[q] += mzj[q] * t;
+        Ar[q] += wb * t;
+      } else {
+        Ax[q] += (mxj[q] + wb * rnx) * t;
+        Ay[q] += (myj[q] + wb * rny) * t;
+        Az[q] += (mzj[q] + wb * rnz) * t;
+      }
     }
   }
   // vertical flux divergence: r^2 W v_q at the interfaces
-  H Fx[kHq], Fy[kHq], Fz[kHq];
+  H Fx[kHq], Fy[kHq], Fz[kHq], Fr[kHq];
   {
     const H vxm = shfl(vx0[kHq - 1], lm), vym = shfl(vy0[kHq - 1], lm), vzm = shfl(vz0[kHq - 1], lm);
+    const H wm = SHALLOW ? shfl(w0[kHq - 1], lm) : (H)0;
 #pragma unroll
     for (int q = 0; q < kHq; ++q) {
       const int lev = lev0 + q;
@@ -569,11 +596,13 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
       Fx[q] = lev == 0 ? (H)0 : w2 * (px + vx0[q]);
       Fy[q] = lev == 0 ? (H)0 : w2 * (py + vy0[q]);
       Fz[q] = lev == 0 ? (H)0 : w2 * (pz + vz0[q]);
+      if (SHALLOW) Fr[q] = lev == 0 ? (H)0 : w2 * ((q ? w0[q - 1] : wm) + w0[q]);
     }
   }
   H acr[kHq];
   {
     const H nx = shfl(Fx[0], lp), ny = shfl(Fy[0], lp), nz = shfl(Fz[0], lp);
+    const H nr = SHALLOW ? shfl(Fr[0], lp) : (H)0;
     const H om2 = (H)(2.0 * c.omega);
     const H idz = (H)(1.0 / c.dz);
 #pragma unroll
@@ -590,10 +619,27 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
       Ax[q] += (Fx1 - Fx[q]) * s;
       Ay[q] += (Fy1 - Fy[q]) * s;
       Az[q] += (Fz1 - Fz[q]) * s;
-      // Coriolis 2 Omega zhat x m
-      Ax[q] -= om2 * fy[q];
-      Ay[q] += om2 * fx[q];
-      acr[q] = Ax[q] * rx + Ay[q] * ry + Az[q] * rz;
+      if (SHALLOW) {
+        // traditional approximation: 2 Omega sin(lat) rhat x M, horizontal;
+        // the horizontal equations take the projection of A here and the
+        // vertical one the scalar advection of w
+        const H fc = om2 * rz;
+        Ax[q] += fc * (ry * fz[q] - rz * fy[q]);
+        Ay[q] += fc * (rz * fx[q] - rx * fz[q]);
+        Az[q] += fc * (rx * fy[q] - ry * fx[q]);
+        const H ah = Ax[q] * rx + Ay[q] * ry + Az[q] * rz;
+        Ax[q] -= ah * rx;
+        Ay[q] -= ah * ry;
+        Az[q] -= ah * rz;
+        H Fr1 = q + 1 < kHq ? Fr[q + 1] : nr;
+        if (lev == L - 1) Fr1 = 0;
+        acr[q] = Ar[q] * irc + (Fr1 - Fr[q]) * s;
+      } else {
+        // Coriolis 2 Omega zhat x m
+        Ax[q] -= om2 * fy[q];
+        Ay[q] += om2 * fx[q];
+        acr[q] = Ax[q] * rx + Ay[q] * ry + Az[q] * rz;
+      }
     }
   }
   const H acr_m = shfl(acr[kHq - 1], lm);
@@ -610,9 +656,15 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
   if (!from_t) ld4<VEC>(f.ps + idx, nv, ps);
 #pragma unroll
   for (int q = 0; q < kHq; ++q) {
-    smx[q] -= Ax[q] - acr[q] * rx;
-    smy[q] -= Ay[q] - acr[q] * ry;
-    smz[q] -= Az[q] - acr[q] * rz;
+    if (SHALLOW) {   // A is horizontal already
+      smx[q] -= Ax[q];
+      smy[q] -= Ay[q];
+      smz[q] -= Az[q];
+    } else {
+      smx[q] -= Ax[q] - acr[q] * rx;
+      smy[q] -= Ay[q] - acr[q] * ry;
+      smz[q] -= Az[q] - acr[q] * rz;
+    }
     const H am = q ? acr[q - 1] : acr_m;
     sw[q] = lev0 + q == 0 ? 0.0 : fw[q] - 0.5 * ((double)am + (double)acr[q]);
     // linearisation coefficients
@@ -628,12 +680,12 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
   st4<VEC>(f.Gam + idx, nv, gam);
 }
 
-template <typename H>
+template <typename H, bool SHALLOW = false>
 __device__ __forceinline__ void b_slow(const Fields<H> &f, const Consts &c, const HLane &ln, int from_t) {
   if ((c.L % kHq) == 0)
-    slow_cells<H, true>(f, c, ln, from_t);
+    slow_cells<H, true, SHALLOW>(f, c, ln, from_t);
   else
-    slow_cells<H, false>(f, c, ln, from_t);
+    slow_cells<H, false, SHALLOW>(f, c, ln, from_t);
 }
 
 // ---------------------------------------------------------------------------
@@ -811,7 +863,8 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
       const double irc = 1.0 / rC;
       const double W1 = lev == L - 1 ? 0.0 : (q + 1 < kHq ? W[q + 1] : W_n);
       const double Wl = lev == 0 ? 0.0 : W[q];
-      Dt[q] = (H)((double)dm[q] * irc + ((rI + c.dz) * (rI + c.dz) * W1 - rI * rI * Wl) * (irc * irc / c.dz));
+      const double rI1 = c.shallow ? rI : rI + c.dz;
+      Dt[q] = (H)((double)dm[q] * irc + (rI1 * rI1 * W1 - rI * rI * Wl) * (irc * irc / c.dz));
       // [t] vertical imbalance at interface lev
       const double pm = q ? p[q - 1] : p_m, rm = q ? rho[q - 1] : rho_m;
       FW[q] = lev == 0 ? 0.0 : -(p[q] - pm) / c.dz - 0.5 * c.grav * (rm + rho[q]);
@@ -1132,6 +1185,12 @@ void kb_hmom(const Planet<H> *P, const int2 *tiles, int parity, int div, int fir
   const Consts &c = P[t.x].c;
   b_hmom(f, c, map_hlane(c, t.y), c.dt / div, first);
 }
+// slow terms of the shallow-atmosphere form (single states only)
+template <typename H>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? 2 : 3)))
+void k_slow_shallow(Fields<H> f, Consts c, int from_t) {
+  b_slow<H, true>(f, c, map_hlane(c, xcd_block()), from_t);
+}
 template <typename H, bool LAST>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void k_vert(Fields<H> f, Consts c, int div, int first) {
@@ -1168,7 +1227,10 @@ void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool fir
 }
 template <typename H>
 void launch_slow(const Fields<H> &f, const Consts &c, int wpb, bool from_t, hipStream_t s) {
-  hipLaunchKernelGGL(k_slow<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c, (int)from_t);
+  if (c.shallow)
+    hipLaunchKernelGGL(k_slow_shallow<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c, (int)from_t);
+  else
+    hipLaunchKernelGGL(k_slow<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c, (int)from_t);
 }
 template <typename H>
 void launch_large(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s) {

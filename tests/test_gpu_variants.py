@@ -11,7 +11,7 @@ TOL = 1e-10
 
 
 def _parity(w, precision=0, tol=TOL, names=("T", "u", "v", "w", "p", "rho", "rhotheta")):
-    say(f"[variant] {w.name} g{w.glevel} L{w.n_lev} hydrostatic={w.hydrostatic} "
+    say(f"[variant] {w.name} g{w.glevel} L{w.n_lev} hydrostatic={w.hydrostatic} shallow={w.shallow} "
         f"n_large={w.n_large} precision={precision}")
     st = lib_state(w, precision)
     st.step(w.n_large, w.n_acoustic)
@@ -40,3 +40,40 @@ def test_hydrostatic_mixed_precision_stays_close():
     w = workloads.small_gas_giant(glevel=3, n_lev=20, n_large=3)
     w.hydrostatic = True
     _parity(w, precision=1, tol=1e-5, names=("T", "p", "rho"))
+
+
+@pytest.mark.parametrize("n_lev", [1, 12, 33])
+def test_shallow_earth(n_lev):
+    """Level counts with and without the 4-level vector path of the slow
+    kernel, and one level."""
+    w = small_earth(glevel=3, n_lev=n_lev, n_large=3, noise=1.0)
+    w.shallow = True
+    _parity(w)
+
+
+def test_shallow_gas_giant_with_forcing():
+    w = workloads.small_gas_giant(glevel=3, n_lev=20, n_large=3)
+    w.shallow = True
+    _parity(w)
+
+
+def test_shallow_and_hydrostatic_together():
+    w = small_earth(glevel=3, n_lev=16, n_large=3, noise=1.0)
+    w.shallow = True
+    w.hydrostatic = True
+    _parity(w)
+
+
+def test_shallow_mixed_precision_stays_close():
+    w = workloads.small_gas_giant(glevel=3, n_lev=20, n_large=3)
+    w.shallow = True
+    _parity(w, precision=1, tol=1e-5, names=("T", "p", "rho"))
+
+
+def test_ensembles_reject_the_shallow_form():
+    from paper_1607_05535_amd import thor
+    w = small_earth(glevel=2, n_lev=8, n_large=1)
+    w.shallow = True
+    g = thor.Grid(w.glevel)
+    with pytest.raises(thor.ThorError, match="shallow"):
+        thor.Batch([g], [thor.structs_from_workload(w)])
