@@ -67,6 +67,7 @@ class Numerics:
     energy_fixer: bool = False   # Sec. 3: globally uniform internal-energy fixer
     hydrostatic: bool = False    # Sec. 3: hydrostatic approximation
     shallow: bool = False        # Sec. 3: shallow atmosphere, traditional approximation
+    lagrange_order: int = 1      # Sec. 2.2: order k of the vertical interpolation
 
 
 @dataclass
@@ -123,6 +124,9 @@ class Model:
         self.Cv = pl.Cp - pl.Rd
         self.gamma = pl.Cp / self.Cv
         L = v.n_lev
+        k = self.num.lagrange_order
+        if k not in (1, 3) or L < k + 1:
+            raise ValueError("Lagrange order 1, or 3 with at least 4 levels")
         self.dz = v.z_top / L
         self.zI = np.arange(L + 1) * self.dz
         self.zC = (np.arange(L) + 0.5) * self.dz
@@ -188,7 +192,7 @@ def init_state(model, init, planet_index=0):
 
 
 # ---------------------------------------------------------------------------
-# Vertical helpers (linear Lagrange interpolation, flux divergence in r)
+# Vertical helpers (Lagrange interpolation, flux divergence in r)
 # ---------------------------------------------------------------------------
 def to_interfaces(x):
     """Interior interface values (j = 1..L-1) of a centre field [n, L, ...]."""
@@ -198,6 +202,57 @@ def to_interfaces(x):
 def to_centres(W):
     """Centre values of an interface field [n, L+1]."""
     return 0.5 * (W[:, :-1] + W[:, 1:])
+
+
+def lagrange_weights(nodes, target):
+    """Weights L_j(target) of the Lagrange polynomial through `nodes`
+    (Sec. 2.2): prod over i != j of (target - z_i) / (z_j - z_i)."""
+    w = np.ones(len(nodes))
+    for j, zj in enumerate(nodes):
+        for i, zi in enumerate(nodes):
+            if i != j:
+                w[j] *= (target - zi) / (zj - zi)
+    return w
+
+
+def centre_to_interface_matrix(L, k):
+    """[L-1, L]: interior interfaces j = 1..L-1 (height j dz) from the k + 1
+    centres (heights (i + 1/2) dz) nearest to them: the stencil starts at
+    j - (k + 1) // 2, shifted to stay inside the column."""
+    A = np.zeros((L - 1, L))
+    for j in range(1, L):
+        s = min(max(j - (k + 1) // 2, 0), L - 1 - k)
+        A[j - 1, s:s + k + 1] = lagrange_weights(np.arange(s, s + k + 1) + 0.5, float(j))
+    return A
+
+
+def interface_to_centre_matrix(L, k):
+    """[L, L+1]: centres (height (c + 1/2) dz) from the k + 1 interfaces
+    (heights i dz, ground and lid included) nearest to them: the stencil
+    starts at c - (k - 1) // 2, shifted to stay inside the column."""
+    A = np.zeros((L, L + 1))
+    for c in range(L):
+        s = min(max(c - (k - 1) // 2, 0), L - k)
+        A[c, s:s + k + 1] = lagrange_weights(np.arange(s, s + k + 1, dtype=float), c + 0.5)
+    return A
+
+
+def interp_c2i(model, x):
+    """Interior interface values of a centre field with the model's
+    Lagrange order (order 1: the mean of the two neighbours)."""
+    k = model.num.lagrange_order
+    if k == 1:
+        return to_interfaces(x)
+    return np.einsum("jl,nl...->nj...", centre_to_interface_matrix(x.shape[1], k), x)
+
+
+def interp_i2c(model, W):
+    """Centre values of an interface field with the model's Lagrange
+    order."""
+    k = model.num.lagrange_order
+    if k == 1:
+        return to_centres(W)
+    return np.einsum("cl,nl->nc", interface_to_centre_matrix(W.shape[1] - 1, k), W)
 
 
 def vertical_div(model, F):
@@ -276,7 +331,7 @@ def hyperdiffusion(model, st, p):
     L = model.vert.n_lev
     H_W = np.zeros((G.n, L + 1))
     if L > 1:
-        rhoI = to_interfaces(st.rho)
+        rhoI = interp_c2i(model, st.rho)
         w = st.W[:, 1:L] / rhoI
         rI = model.rI[1:L]
         H_W[:, 1:L] = -op.lap(G, rhoI * Kd * op.lap(G, w, rI), rI)
@@ -307,28 +362,28 @@ def slow_forcing(model, prev, large):
         for q in range(3):
             A[..., q] = op.div(G, v[..., q, None] * prev.M, rC)
         vI = np.zeros((G.n, L + 1, 3))
-        vI[:, 1:L] = to_interfaces(v)
+        vI[:, 1:L] = interp_c2i(model, v)
         A += vertical_div(model, prev.W[..., None] * vI)
         C = 2.0 * Om * rhat[:, None, 2:3] * np.cross(np.broadcast_to(rh, prev.M.shape), prev.M)
         AC = A + C
         S_M = op.proj_h(-large["G_t"] - AC, rhat) + large["H_M"]
-        w = to_centres(prev.W) / prev.rho
+        w = interp_i2c(model, prev.W) / prev.rho
         Ar = op.div(G, w[..., None] * prev.M, rC)
         wI = np.zeros((G.n, L + 1))
-        wI[:, 1:L] = to_interfaces(w)
+        wI[:, 1:L] = interp_c2i(model, w)
         Ar = Ar + vertical_div(model, prev.W * wI)
         S_W = np.zeros((G.n, L + 1))
-        S_W[:, 1:L] = large["I"][:, 1:L] - to_interfaces(Ar) + large["H_W"][:, 1:L]
+        S_W[:, 1:L] = large["I"][:, 1:L] - interp_c2i(model, Ar) + large["H_W"][:, 1:L]
     else:
         # full Cartesian momentum m = M + Wbar rhat and velocity m / rho
-        m = prev.M + to_centres(prev.W)[..., None] * rh
+        m = prev.M + interp_i2c(model, prev.W)[..., None] * rh
         v = m / prev.rho[..., None]
         # advection A_q = div(v_q M) + (1/r^2) d(r^2 W v_q)/dr
         A = np.zeros_like(m)
         for q in range(3):
             A[..., q] = op.div(G, v[..., q, None] * prev.M, rC)
         vI = np.zeros((G.n, L + 1, 3))
-        vI[:, 1:L] = to_interfaces(v)
+        vI[:, 1:L] = interp_c2i(model, v)
         A += vertical_div(model, prev.W[..., None] * vI)
         # Coriolis 2 Omega zhat x m
         C = np.zeros_like(m)
@@ -338,10 +393,10 @@ def slow_forcing(model, prev, large):
         S_M = op.proj_h(-large["G_t"] - AC, rhat) + large["H_M"]
         S_W = np.zeros((G.n, L + 1))
         ACr = op.proj_r(AC, rhat)
-        S_W[:, 1:L] = large["I"][:, 1:L] - to_interfaces(ACr) + large["H_W"][:, 1:L]
+        S_W[:, 1:L] = large["I"][:, 1:L] - interp_c2i(model, ACr) + large["H_W"][:, 1:L]
     thetaC = prev.rth / prev.rho
     thetaI = np.empty((G.n, L + 1))
-    thetaI[:, 1:L] = to_interfaces(thetaC)
+    thetaI[:, 1:L] = interp_c2i(model, thetaC)
     thetaI[:, 0] = thetaC[:, 0]
     thetaI[:, L] = thetaC[:, L - 1]
     Gam = model.gamma * model.eos(prev.rth) / prev.rth
@@ -578,7 +633,8 @@ def model_from_workload(w, G):
     """Oracle model and initial state for a workload recipe (``workloads``)."""
     planet = Planet(w.radius, w.omega, w.gravity, w.Rd, w.Cp, w.p_ref)
     vert = Vertical(w.n_lev, w.z_top)
-    num = Numerics(w.dt, w.diff_D, w.div_damp, w.energy_fixer, w.hydrostatic, w.shallow)
+    num = Numerics(w.dt, w.diff_D, w.div_damp, w.energy_fixer, w.hydrostatic, w.shallow,
+                   w.lagrange_order)
     forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar,
                       w.lapse, w.z_strat, w.dT_strat, w.sigma_strat, w.k_f, w.k_a, w.k_s, w.sigma_b,
                       w.dT_y, w.dtheta_z, w.p_star, w.T_top, w.T_min)

@@ -154,3 +154,72 @@ def test_shallow_and_deep_agree_for_a_thin_atmosphere():
     speed = np.sqrt(out[False]["u"] ** 2 + out[False]["v"] ** 2).max()
     du = max(np.abs(out[True][k] - out[False][k]).max() for k in ("u", "v"))
     assert 1e-6 * speed < du < 0.01 * speed
+
+
+# ---------------------------------------------------------------------------
+# Vertical Lagrange interpolation of order k (Sec. 2.2)
+# ---------------------------------------------------------------------------
+def test_lagrange_weights_reproduce_polynomials_up_to_their_degree():
+    rs = np.random.default_rng(2)
+    for k in (1, 2, 3, 5):
+        nodes = np.sort(rs.uniform(-3, 3, k + 1))
+        t = rs.uniform(-2, 2)
+        w = dy.lagrange_weights(nodes, t)
+        for deg in range(k + 1):
+            assert abs(np.dot(w, nodes ** deg) - t ** deg) < 1e-9 * max(1, abs(t) ** deg)
+        # one degree more is not reproduced in general
+        assert abs(np.dot(w, nodes ** (k + 1)) - t ** (k + 1)) > 1e-9
+
+
+def test_order_one_matrices_are_the_two_point_means():
+    L = 7
+    rs = np.random.default_rng(3)
+    x = rs.normal(size=(5, L))
+    W = rs.normal(size=(5, L + 1))
+    assert np.allclose(x @ dy.centre_to_interface_matrix(L, 1).T, dy.to_interfaces(x), rtol=0, atol=1e-15)
+    assert np.allclose(W @ dy.interface_to_centre_matrix(L, 1).T, dy.to_centres(W), rtol=0, atol=1e-15)
+
+
+def test_cubic_interpolation_is_exact_for_cubics_in_height():
+    """Order 3: interior rows are (-1, 9, 9, -1) / 16 (midpoint of four
+    equally spaced nodes); every row, the shifted ones at the ground and the
+    lid included, reproduces a cubic in z exactly."""
+    L = 9
+    Aci = dy.centre_to_interface_matrix(L, 3)
+    Aic = dy.interface_to_centre_matrix(L, 3)
+    mid = np.array([-1.0, 9.0, 9.0, -1.0]) / 16
+    assert np.allclose(Aci[3, 2:6], mid, rtol=0, atol=1e-15)      # interface 4 from centres 2..5
+    assert np.allclose(Aic[4, 3:7], mid, rtol=0, atol=1e-15)      # centre 4 from interfaces 3..6
+    assert np.allclose(Aci.sum(axis=1), 1) and np.allclose(Aic.sum(axis=1), 1)
+    f = lambda z: 2.0 - 0.3 * z + 0.05 * z ** 2 - 0.01 * z ** 3
+    zc, zi = np.arange(L) + 0.5, np.arange(L + 1.0)
+    assert np.abs(Aci @ f(zc) - f(zi[1:L])).max() < 1e-12
+    assert np.abs(Aic @ f(zi) - f(zc)).max() < 1e-12
+    assert np.abs(dy.centre_to_interface_matrix(L, 1) @ f(zc) - f(zi[1:L])).max() > 1e-3
+
+
+def test_order_three_rest_state_and_closeness_to_order_one():
+    w = small_earth(glevel=2, n_lev=12, n_large=3, noise=0.0)
+    w.lagrange_order = 3
+    model, st = _model(w)
+    f = dy.fields(model, dy.run(model, st, w.n_large, w.n_acoustic))
+    for k in ("u", "v", "w"):
+        assert np.abs(f[k]).max() < 1e-8, k
+    out = {}
+    for order in (1, 3):
+        w = small_earth(glevel=3, n_lev=20, n_large=3, noise=1.0)
+        w.lagrange_order = order
+        model, st = _model(w)
+        st, _, _ = _zonal_flow_state(model, st, 30.0)
+        out[order] = dy.fields(model, dy.run(model, st, w.n_large, w.n_acoustic))
+    speed = np.sqrt(out[1]["u"] ** 2 + out[1]["v"] ** 2).max()
+    du = max(np.abs(out[3][k] - out[1][k]).max() for k in ("u", "v", "w"))
+    assert 1e-9 * speed < du < 0.01 * speed
+
+
+def test_order_three_needs_four_levels():
+    import pytest
+    w = small_earth(glevel=2, n_lev=3)
+    w.lagrange_order = 3
+    with pytest.raises(ValueError):
+        _model(w)

@@ -62,6 +62,7 @@ class Workload:
     energy_fixer: bool = False
     hydrostatic: bool = False
     shallow: bool = False
+    lagrange_order: int = 1
     extra: dict = field(default_factory=dict)
 
     @property
