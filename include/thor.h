@@ -164,6 +164,16 @@ typedef struct {
                       Coriolis force is 2 Omega sin(lat) rhat x (rho v_h).
                       0: the paper's deep atmosphere.  Not available in
                       ensembles. */
+  int lagrange_order; /* order k of the vertical Lagrange interpolation
+                      (Sec. 2.2) used for interface values of centre fields
+                      (theta of the vertical solve, the advected velocity,
+                      the slow forcing of rho v_r, rho in its hyperdiffusion)
+                      and centre values of rho v_r (the advected momentum):
+                      0 or 1 (the paper's runs: the two-point mean) or 3 (cubic,
+                      from the four nearest levels, shifted one level inward
+                      at the ground and the lid; n_lev >= 4).  The buoyancy
+                      of the vertical solve and the diagnostics keep the
+                      two-point mean.  3 is not available in ensembles. */
 } thor_numerics;
 
 /* Physics after each large step (Sec. 5, Eq. im_eq_t): backward-Euler

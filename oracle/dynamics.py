@@ -125,7 +125,7 @@ class Model:
         self.gamma = pl.Cp / self.Cv
         L = v.n_lev
         k = self.num.lagrange_order
-        if k not in (1, 3) or L < k + 1:
+        if k not in (1, 3) or (k == 3 and L < 4):
             raise ValueError("Lagrange order 1, or 3 with at least 4 levels")
         self.dz = v.z_top / L
         self.zI = np.arange(L + 1) * self.dz

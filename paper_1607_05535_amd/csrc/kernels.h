@@ -64,11 +64,13 @@ struct Consts {
   int hlpc, hcpw;         // phase-M mapping: lanes per column, columns per wavefront
   double radius, omega, grav, Rd, Cp, Cv, gamma, p_ref;
   double dz, Kd;
+  double rdz;             // radial spacing of the levels: dz, or 0 (shallow atmosphere)
   double dt;
   int div_damp;
   int energy_fixer;       // 1: uniform internal-energy fixer after the dynamics
   int hydrostatic;        // 1: no vertical acceleration in the acoustic substeps
   int shallow;            // 1: shallow atmosphere (r = radius), traditional Coriolis
+  int vorder;             // order of the vertical Lagrange interpolation (1 or 3)
   int forcing;
   double tau;
   // hot-Jupiter benchmark forcing (Eqs. teq-hj, btrop, tvert)

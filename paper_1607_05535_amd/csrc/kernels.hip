@@ -75,14 +75,11 @@ __device__ __forceinline__ H eos(double rth, const Consts &c) {
   return (H)(c.p_ref * pow(c.Rd * rth / c.p_ref, c.gamma));
 }
 
-// Distance from the planet's centre of level centres and interfaces (the
-// planet radius at every level in the shallow-atmosphere form).
-__device__ __forceinline__ double radius_c(const Consts &c, int lev) {
-  return c.shallow ? c.radius : c.radius + (lev + 0.5) * c.dz;
-}
-__device__ __forceinline__ double radius_i(const Consts &c, int lev) {
-  return c.shallow ? c.radius : c.radius + lev * c.dz;
-}
+// Distance from the planet's centre of level centres and interfaces; the
+// radial spacing rdz is dz, or 0 in the shallow-atmosphere form (the planet
+// radius at every level).
+__device__ __forceinline__ double radius_c(const Consts &c, int lev) { return c.radius + (lev + 0.5) * c.rdz; }
+__device__ __forceinline__ double radius_i(const Consts &c, int lev) { return c.radius + lev * c.rdz; }
 
 // Neighbour ids of a column; a pentagon's missing 6th neighbour points at the
 // column itself (its coefficients are zero).
@@ -144,6 +141,63 @@ __device__ __forceinline__ void ld4(const float *p, int nv, float v[kHq]) {
     for (int q = 0; q < kHq; ++q) v[q] = q < nv ? p[q] : 0.0f;
   }
 }
+// ---------------------------------------------------------------------------
+// Cubic vertical interpolation (the Lagrange interpolation of Sec. 2.2 with
+// k = 3 on the equally spaced levels).  Centre values to interface j from
+// the centres j-2..j+1, weights (-1, 9, 9, -1)/16; at the first interior
+// interface (j = 1) from centres 0..3, (5, 15, -5, 1)/16; at the last
+// (j = L-1) from centres L-4..L-1, (1, -5, 15, 5)/16.  Interface values to
+// centre c the same way: interfaces c-1..c+2, or 0..3 (c = 0), or L-3..L
+// (c = L-1), ground and lid included.  Needs L >= 4.
+// ---------------------------------------------------------------------------
+// The gather mapping's window of a per-level field around a lane's kHq
+// levels: win[i] = value at level lev0 - 3 + i (i = 0..9), from the lane,
+// the lane below (levels lev0-3..lev0-1) and the lane above (lev0+4 ..
+// lev0+6); levels below 0 or from `top` up read as 0 (top = L: for centre
+// fields the column's end, for interface fields the lid, which carries
+// nothing).  Every lane calls it (shuffles).
+template <typename T>
+__device__ __forceinline__ void level_window(const T v[kHq], int lev0, int top, int lm, int lp, T win[10]) {
+  win[0] = shfl(v[1], lm);
+  win[1] = shfl(v[2], lm);
+  win[2] = shfl(v[3], lm);
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) win[3 + q] = v[q];
+  win[7] = shfl(v[0], lp);
+  win[8] = shfl(v[1], lp);
+  win[9] = shfl(v[2], lp);
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const int lev = lev0 - 3 + i;
+    if (lev < 0 || lev >= top) win[i] = (T)0;
+  }
+}
+// Interface j from the centre window (centre j at win[b], b = j - lev0 + 3).
+template <typename T>
+__device__ __forceinline__ T cubic_c2i(const T *win, int j, int L) {
+  const bool bot = j == 1, top = j == L - 1;
+  const T t0 = top ? (T)(1.0 / 16) : (T)0;
+  const T t1 = top ? (T)(-5.0 / 16) : (bot ? (T)0 : (T)(-1.0 / 16));
+  const T t2 = top ? (T)(15.0 / 16) : (bot ? (T)(5.0 / 16) : (T)(9.0 / 16));
+  const T t3 = top ? (T)(5.0 / 16) : (bot ? (T)(15.0 / 16) : (T)(9.0 / 16));
+  const T t4 = top ? (T)0 : (bot ? (T)(-5.0 / 16) : (T)(-1.0 / 16));
+  const T t5 = bot ? (T)(1.0 / 16) : (T)0;
+  // win points at centre j - 3
+  return t0 * win[0] + t1 * win[1] + t2 * win[2] + t3 * win[3] + t4 * win[4] + t5 * win[5];
+}
+// Centre c from the interface window (win points at interface c - 2).
+template <typename T>
+__device__ __forceinline__ T cubic_i2c(const T *win, int c, int L) {
+  const bool bot = c == 0, top = c == L - 1;
+  const T t0 = top ? (T)(1.0 / 16) : (T)0;
+  const T t1 = top ? (T)(-5.0 / 16) : (bot ? (T)0 : (T)(-1.0 / 16));
+  const T t2 = top ? (T)(15.0 / 16) : (bot ? (T)(5.0 / 16) : (T)(9.0 / 16));
+  const T t3 = top ? (T)(5.0 / 16) : (bot ? (T)(15.0 / 16) : (T)(9.0 / 16));
+  const T t4 = top ? (T)0 : (bot ? (T)(-5.0 / 16) : (T)(-1.0 / 16));
+  const T t5 = bot ? (T)(1.0 / 16) : (T)0;
+  return t0 * win[0] + t1 * win[1] + t2 * win[2] + t3 * win[3] + t4 * win[4] + t5 * win[5];
+}
+
 template <bool VEC>
 __device__ __forceinline__ void st4(double *p, int nv, const double v[kHq]) {
   if (VEC) {
@@ -340,7 +394,7 @@ __device__ __forceinline__ double physics_p(const Consts &c, const double *teq, 
 // combined), its solution, and the density / rho-theta updates with the new
 // W; pressure from the nonlinear equation of state (Eq. theta_to_p).
 // ---------------------------------------------------------------------------
-template <typename H, bool LAST>
+template <typename H, bool LAST, int ORD = 1>
 __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, const Lane &ln, double dtau, int first) {
   const int L = c.L, lev = ln.lev, col = ln.col;
   const size_t idx = (size_t)col * L + lev;
@@ -386,7 +440,19 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
 
   const int lm = ln.lane > 0 ? ln.lane - 1 : 0;
   const int lp = ln.lane < 63 ? ln.lane + 1 : 63;
-  const double thI = 0.5 * (shfl(thC, lm) + thC);   // theta at interface lev
+  double thI;   // theta at interface lev
+  if (ORD == 3) {
+    double tw[6];   // centres lev-3 .. lev+2 of the column (0 outside it)
+#pragma unroll
+    for (int o = -3; o <= 2; ++o) {
+      const int src = min(max(ln.lane + o, 0), 63);
+      const double v = shfl(thC, src);
+      tw[o + 3] = (lev + o < 0 || lev + o >= L) ? 0.0 : v;
+    }
+    thI = cubic_c2i(tw, lev, L);
+  } else {
+    thI = 0.5 * (shfl(thC, lm) + thC);
+  }
   const double thI_m = shfl(thI, lm);
   const double thI_p = shfl(thI, lp);
   const double gam_m = shfl(gam, lm);
@@ -394,7 +460,7 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
   const double rhs_m = shfl(rhs, lm);
 
   const double dz = c.dz;
-  const double rI = radius_i(c, lev), rI1 = c.shallow ? rI : rI + dz;
+  const double rI = radius_i(c, lev), rI1 = rI + c.rdz;
   const double rC = radius_c(c, lev);
   const double irc2dz = 1.0 / (rC * rC * dz);
   const double gp = rI1 * rI1 * irc2dz, gm = rI * rI * irc2dz;
@@ -486,7 +552,7 @@ __device__ __forceinline__ void b_friction(const Fields<H> &f, const Consts &c, 
 // full Cartesian momentum, Coriolis, projections (Eqs. mom, proj_h, proj_r),
 // and the linearisation coefficients theta_L and gamma p / (rho theta).
 // ---------------------------------------------------------------------------
-template <typename H, bool VEC, bool SHALLOW>
+template <typename H, bool VEC, bool SHALLOW, int ORD>
 __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, const HLane &ln, int from_t) {
   const int L = c.L, col = ln.col, nv = ln.nv, lev0 = ln.lev0;
   const int lane = threadIdx.x & 63;
@@ -516,6 +582,8 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
     ld4<VEC>(W + idx, nv, Wk);
     if (lev0 == 0) Wk[0] = 0.0;
     const double Wn = shfl(Wk[0], lp);   // interface lev0 + kHq: first value of the next lane
+    double Wwin[10];
+    if (ORD == 3) level_window(Wk, lev0, L, lm, lp, Wwin);
     ld4<VEC>(rho + idx, nv, rho0);
     H mx0[kHq], my0[kHq], mz0[kHq];
     ld4<VEC>(Mx + idx, nv, mx0);
@@ -525,7 +593,7 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
 #pragma unroll
     for (int q = 0; q < kHq; ++q) {
       const double up = lev0 + q == L - 1 ? 0.0 : (q + 1 < kHq ? Wk[q + 1] : Wn);
-      const H wbar = (H)(0.5 * (Wk[q] + up));
+      const H wbar = ORD == 3 ? (H)cubic_i2c(Wwin + q + 1, lev0 + q, L) : (H)(0.5 * (Wk[q] + up));
       if (SHALLOW) {
         fx[q] = mx0[q];
         fy[q] = my0[q];
@@ -558,6 +626,8 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
     ld4<VEC>(W + nj, nv, wn);
     if (lev0 == 0) wn[0] = 0.0;
     const double wnn = shfl(wn[0], lp);
+    double wwin[10];
+    if (ORD == 3) level_window(wn, lev0, L, lm, lp, wwin);
     ld4<VEC>(rho + nj, nv, rj);
     ld4<VEC>(Mx + nj, nv, mxj);
     ld4<VEC>(My + nj, nv, myj);
@@ -568,7 +638,7 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
 #pragma unroll
     for (int q = 0; q < kHq; ++q) {
       const double up = lev0 + q == L - 1 ? 0.0 : (q + 1 < kHq ? wn[q + 1] : wnn);
-      const H wb = (H)(0.5 * (wn[q] + up));
+      const H wb = ORD == 3 ? (H)cubic_i2c(wwin + q + 1, lev0 + q, L) : (H)(0.5 * (wn[q] + up));
       const H t = (cx * mxj[q] + cy * myj[q] + cz * mzj[q]) / (H)rj[q];
       if (SHALLOW) {
         Ax[q] += mxj[q] * t;
@@ -584,7 +654,24 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
   }
   // vertical flux divergence: r^2 W v_q at the interfaces
   H Fx[kHq], Fy[kHq], Fz[kHq], Fr[kHq];
-  {
+  if (ORD == 3) {
+    // r^2 W times the cubic interface value of v_q (and of w)
+    H xw[10], yw[10], zw[10], ww[10];
+    level_window(vx0, lev0, L, lm, lp, xw);
+    level_window(vy0, lev0, L, lm, lp, yw);
+    level_window(vz0, lev0, L, lm, lp, zw);
+    if (SHALLOW) level_window(w0, lev0, L, lm, lp, ww);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const int lev = lev0 + q;
+      const H rI = (H)radius_i(c, lev);
+      const H w2 = (H)Wk[q] * rI * rI;
+      Fx[q] = lev == 0 ? (H)0 : w2 * cubic_c2i(xw + q, lev, L);
+      Fy[q] = lev == 0 ? (H)0 : w2 * cubic_c2i(yw + q, lev, L);
+      Fz[q] = lev == 0 ? (H)0 : w2 * cubic_c2i(zw + q, lev, L);
+      if (SHALLOW) Fr[q] = lev == 0 ? (H)0 : w2 * cubic_c2i(ww + q, lev, L);
+    }
+  } else {
     const H vxm = shfl(vx0[kHq - 1], lm), vym = shfl(vy0[kHq - 1], lm), vzm = shfl(vz0[kHq - 1], lm);
     const H wm = SHALLOW ? shfl(w0[kHq - 1], lm) : (H)0;
 #pragma unroll
@@ -643,6 +730,8 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
     }
   }
   const H acr_m = shfl(acr[kHq - 1], lm);
+  H aw[10];
+  if (ORD == 3) level_window(acr, lev0, L, lm, lp, aw);
   if (!ln.store) return;
   H smx[kHq], smy[kHq], smz[kHq], thl[kHq], gam[kHq];
   double sw[kHq], fw[kHq], rth0[kHq], pt[kHq];
@@ -666,7 +755,10 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
       smz[q] -= Az[q] - acr[q] * rz;
     }
     const H am = q ? acr[q - 1] : acr_m;
-    sw[q] = lev0 + q == 0 ? 0.0 : fw[q] - 0.5 * ((double)am + (double)acr[q]);
+    if (ORD == 3)
+      sw[q] = lev0 + q == 0 ? 0.0 : fw[q] - (double)cubic_c2i(aw + q, lev0 + q, L);
+    else
+      sw[q] = lev0 + q == 0 ? 0.0 : fw[q] - 0.5 * ((double)am + (double)acr[q]);
     // linearisation coefficients
     const double p0 = pt[q] + (from_t ? 0.0 : (double)ps[q]);
     thl[q] = (H)(rth0[q] / rho0[q]);
@@ -680,12 +772,12 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
   st4<VEC>(f.Gam + idx, nv, gam);
 }
 
-template <typename H, bool SHALLOW = false>
+template <typename H, bool SHALLOW = false, int ORD = 1>
 __device__ __forceinline__ void b_slow(const Fields<H> &f, const Consts &c, const HLane &ln, int from_t) {
   if ((c.L % kHq) == 0)
-    slow_cells<H, true, SHALLOW>(f, c, ln, from_t);
+    slow_cells<H, true, SHALLOW, ORD>(f, c, ln, from_t);
   else
-    slow_cells<H, false, SHALLOW>(f, c, ln, from_t);
+    slow_cells<H, false, SHALLOW, ORD>(f, c, ln, from_t);
 }
 
 // ---------------------------------------------------------------------------
@@ -694,17 +786,37 @@ __device__ __forceinline__ void b_slow(const Fields<H> &f, const Consts &c, cons
 // grad p[t], the [t] vertical imbalance and the divergence-damping terms of
 // Phi[t].
 // ---------------------------------------------------------------------------
+// Density at the interfaces lev0 .. lev0 + kHq - 1 of a lane's levels (the
+// mean of the two neighbouring centres, or the cubic interpolation): the
+// interface density of the hyperdiffusion of rho v_r.  Every lane calls it.
+template <bool VEC>
+__device__ __forceinline__ void interface_rho(const Consts &c, const double rho[kHq], int lev0, int lm, int lp,
+                                              double rhoI[kHq]) {
+  if (c.vorder == 3) {
+    double win[10];
+    level_window(rho, lev0, c.L, lm, lp, win);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) rhoI[q] = cubic_c2i(win + q, lev0 + q, c.L);
+  } else {
+    const double rho_m = shfl(rho[kHq - 1], lm);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) rhoI[q] = 0.5 * ((q ? rho[q - 1] : rho_m) + rho[q]);
+  }
+}
+
 template <typename H, bool VEC>
 __device__ __forceinline__ void large0_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
   const int L = c.L, lev0 = ln.lev0, nv = ln.nv;
   const size_t idx = (size_t)ln.col * L + lev0;
   const int lane = threadIdx.x & 63;
   const int lm = lane > 0 ? lane - 1 : 0;
+  const int lp = lane < 63 ? lane + 1 : 63;
   double rho[kHq], rth[kHq], W[kHq];
   ld4<VEC>(f.rho_t + idx, nv, rho);
   ld4<VEC>(f.rth_t + idx, nv, rth);
   ld4<VEC>(f.W_t + idx, nv, W);
-  const double rho_m = shfl(rho[kHq - 1], lm);
+  double rhoI[kHq];   // rho at interfaces lev0 .. lev0 + 3
+  interface_rho<VEC>(c, rho, lev0, lm, lp, rhoI);
   if (!ln.store) return;
   H mx[kHq], my[kHq], mz[kHq];
   ld4<VEC>(f.Mx_t + idx, nv, mx);
@@ -719,8 +831,7 @@ __device__ __forceinline__ void large0_cells(const Fields<H> &f, const Consts &c
     vx[q] = (double)mx[q] * irho;
     vy[q] = (double)my[q] * irho;
     vz[q] = (double)mz[q] * irho;
-    const double rm = q ? rho[q - 1] : rho_m;
-    wI[q] = lev0 + q == 0 ? 0.0 : W[q] / (0.5 * (rm + rho[q]));
+    wI[q] = lev0 + q == 0 ? 0.0 : W[q] / rhoI[q];
   }
   st4<VEC>(f.p_t + idx, nv, p);
   st4<VEC>(f.T + idx, nv, T);
@@ -761,6 +872,8 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
   ld4<VEC>(f.p_t + idx, nv, p);
   ld4<VEC>(f.W_t + idx, nv, W);
   const double rho_m = shfl(rho[kHq - 1], lm), p_m = shfl(p[kHq - 1], lm), W_n = shfl(W[0], lp);
+  double rhoI[kHq];   // rho at interfaces lev0 .. lev0 + 3
+  interface_rho<VEC>(c, rho, lev0, lm, lp, rhoI);
   if (!ln.store) return;
   int nb[6];
   load_nbr(f.nbr, col, nb);
@@ -797,8 +910,7 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
     for (int q = 0; q < kHq; ++q) {
       const int lev = lev0 + q;
       const double rI = radius_i(c, lev);
-      const double rm = q ? rho[q - 1] : rho_m;
-      l[q] = lev == 0 ? 0.0 : 0.5 * (rm + rho[q]) * Kd / (rI * rI) * l[q];
+      l[q] = lev == 0 ? 0.0 : rhoI[q] * Kd / (rI * rI) * l[q];
     }
     st4<VEC>(f.Xw + idx, nv, l);
   }
@@ -863,7 +975,7 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
       const double irc = 1.0 / rC;
       const double W1 = lev == L - 1 ? 0.0 : (q + 1 < kHq ? W[q + 1] : W_n);
       const double Wl = lev == 0 ? 0.0 : W[q];
-      const double rI1 = c.shallow ? rI : rI + c.dz;
+      const double rI1 = rI + c.rdz;
       Dt[q] = (H)((double)dm[q] * irc + (rI1 * rI1 * W1 - rI * rI * Wl) * (irc * irc / c.dz));
       // [t] vertical imbalance at interface lev
       const double pm = q ? p[q - 1] : p_m, rm = q ? rho[q - 1] : rho_m;
@@ -1185,16 +1297,24 @@ void kb_hmom(const Planet<H> *P, const int2 *tiles, int parity, int div, int fir
   const Consts &c = P[t.x].c;
   b_hmom(f, c, map_hlane(c, t.y), c.dt / div, first);
 }
-// slow terms of the shallow-atmosphere form (single states only)
-template <typename H>
-__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? 2 : 3)))
-void k_slow_shallow(Fields<H> f, Consts c, int from_t) {
-  b_slow<H, true>(f, c, map_hlane(c, xcd_block()), from_t);
+// slow terms of the shallow-atmosphere form and of the cubic vertical
+// interpolation (single states only)
+template <typename H, bool SHALLOW, int ORD>
+__global__ __launch_bounds__(kMaxBlock)
+__attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? (SHALLOW && ORD == 3 ? 1 : 2) : (SHALLOW && ORD == 3 ? 2 : 3))))
+void k_slow_var(Fields<H> f, Consts c, int from_t) {
+  b_slow<H, SHALLOW, ORD>(f, c, map_hlane(c, xcd_block()), from_t);
 }
 template <typename H, bool LAST>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void k_vert(Fields<H> f, Consts c, int div, int first) {
   b_vert<H, LAST>(f, c, map_lane(c, xcd_block()), c.dt / div, first);
+}
+// phase V with the cubic interface theta (single states only)
+template <typename H, bool LAST>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? 3 : 4)))
+void k_vert3(Fields<H> f, Consts c, int div, int first) {
+  b_vert<H, LAST, 3>(f, c, map_lane(c, xcd_block()), c.dt / div, first);
 }
 template <typename H, bool LAST>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4)))
@@ -1217,20 +1337,32 @@ void launch_hmom(const Fields<H> &f, const Consts &c, int wpb, int div, bool fir
 template <typename H>
 void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, bool last,
                  hipStream_t s) {
+  const dim3 g(n_blocks(c, wpb)), b(64 * wpb);
   if (last) {
-    hipLaunchKernelGGL((k_vert<H, true>), dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c, div, (int)first);
+    if (c.vorder == 3)
+      hipLaunchKernelGGL((k_vert3<H, true>), g, b, 0, s, f, c, div, (int)first);
+    else
+      hipLaunchKernelGGL((k_vert<H, true>), g, b, 0, s, f, c, div, (int)first);
     if (c.forcing == THOR_FORCING_HELD_SUAREZ)
       hipLaunchKernelGGL(k_friction<H>, dim3(n_blocks(c, 4)), dim3(256), 0, s, f, c);
   } else {
-    hipLaunchKernelGGL((k_vert<H, false>), dim3(n_blocks(c, wpb)), dim3(64 * wpb), 0, s, f, c, div, (int)first);
+    if (c.vorder == 3)
+      hipLaunchKernelGGL((k_vert3<H, false>), g, b, 0, s, f, c, div, (int)first);
+    else
+      hipLaunchKernelGGL((k_vert<H, false>), g, b, 0, s, f, c, div, (int)first);
   }
 }
 template <typename H>
 void launch_slow(const Fields<H> &f, const Consts &c, int wpb, bool from_t, hipStream_t s) {
-  if (c.shallow)
-    hipLaunchKernelGGL(k_slow_shallow<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c, (int)from_t);
+  const dim3 g(n_blocks_h(c, wpb)), b(64 * wpb);
+  if (c.vorder == 3 && c.shallow)
+    hipLaunchKernelGGL((k_slow_var<H, true, 3>), g, b, 0, s, f, c, (int)from_t);
+  else if (c.vorder == 3)
+    hipLaunchKernelGGL((k_slow_var<H, false, 3>), g, b, 0, s, f, c, (int)from_t);
+  else if (c.shallow)
+    hipLaunchKernelGGL((k_slow_var<H, true, 1>), g, b, 0, s, f, c, (int)from_t);
   else
-    hipLaunchKernelGGL(k_slow<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c, (int)from_t);
+    hipLaunchKernelGGL(k_slow<H>, g, b, 0, s, f, c, (int)from_t);
 }
 template <typename H>
 void launch_large(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s) {

@@ -141,9 +141,11 @@ bool validate(const thor_planet *pl, const thor_vertical *v, const thor_numerics
   }
   if (!(num->dt > 0) || !(num->diff_D >= 0) || (num->precision != THOR_FP64 && num->precision != THOR_MIXED) ||
       (num->div_damp != 0 && num->div_damp != 1) || (num->energy_fixer != 0 && num->energy_fixer != 1) ||
-      (num->hydrostatic != 0 && num->hydrostatic != 1) || (num->shallow != 0 && num->shallow != 1)) {
+      (num->hydrostatic != 0 && num->hydrostatic != 1) || (num->shallow != 0 && num->shallow != 1) ||
+      (num->lagrange_order < 0 || num->lagrange_order > 3 || num->lagrange_order == 2) ||
+      (num->lagrange_order == 3 && v->n_lev < 4)) {
     set_error("thor_state_init: numerics need dt > 0, diff_D >= 0, precision FP64|MIXED, div_damp 0|1, "
-              "energy_fixer 0|1, hydrostatic 0|1, shallow 0|1");
+              "energy_fixer 0|1, hydrostatic 0|1, shallow 0|1, lagrange_order 0, 1 or 3 (3: n_lev >= 4)");
     return false;
   }
   if (fo->kind != THOR_FORCING_NONE && fo->kind != THOR_FORCING_NEWTONIAN && fo->kind != THOR_FORCING_HOT_JUPITER &&
@@ -503,6 +505,8 @@ int thor_state_init(const thor_grid *g, const thor_planet *pl, const thor_vertic
   c.energy_fixer = num->energy_fixer;
   c.hydrostatic = num->hydrostatic;
   c.shallow = num->shallow;
+  c.rdz = num->shallow ? 0.0 : c.dz;
+  c.vorder = num->lagrange_order == 3 ? 3 : 1;
   c.forcing = fo->kind;
   c.tau = (fo->kind == THOR_FORCING_NEWTONIAN || fo->kind == THOR_FORCING_HOT_JUPITER) ? fo->tau : 1.0;
   c.hs_kf = fo->k_f;
@@ -812,8 +816,9 @@ int thor_batch_init(int n, const thor_grid *const *grids, const thor_planet *pl,
   if (dev_bytes < need) { set_error("thor_batch_init: dev_bytes smaller than thor_batch_bytes"); return THOR_ENOMEM; }
   for (int i = 0; i < n; ++i) {
     if (!validate(&pl[i], &v[i], &num[i], &fo[i], &in[i])) return THOR_EINVAL;
-    if (num[i].energy_fixer || num[i].shallow) {
-      set_error("thor_batch_init: the energy fixer and the shallow-atmosphere form are not available in ensembles");
+    if (num[i].energy_fixer || num[i].shallow || num[i].lagrange_order == 3) {
+      set_error("thor_batch_init: the energy fixer, the shallow-atmosphere form and cubic vertical "
+                "interpolation are not available in ensembles");
       return THOR_EINVAL;
     }
   }

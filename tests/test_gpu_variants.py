@@ -11,7 +11,7 @@ TOL = 1e-10
 
 
 def _parity(w, precision=0, tol=TOL, names=("T", "u", "v", "w", "p", "rho", "rhotheta")):
-    say(f"[variant] {w.name} g{w.glevel} L{w.n_lev} hydrostatic={w.hydrostatic} shallow={w.shallow} "
+    say(f"[variant] {w.name} g{w.glevel} L{w.n_lev} hydrostatic={w.hydrostatic} shallow={w.shallow} order={w.lagrange_order} "
         f"n_large={w.n_large} precision={precision}")
     st = lib_state(w, precision)
     st.step(w.n_large, w.n_acoustic)
@@ -77,3 +77,51 @@ def test_ensembles_reject_the_shallow_form():
     g = thor.Grid(w.glevel)
     with pytest.raises(thor.ThorError, match="shallow"):
         thor.Batch([g], [thor.structs_from_workload(w)])
+
+
+@pytest.mark.parametrize("n_lev", [4, 12, 33])
+def test_cubic_vertical_interpolation_earth(n_lev):
+    """Order-3 Lagrange interpolation: the fewest levels it allows, the
+    4-level vector path, and ragged lanes."""
+    w = small_earth(glevel=3, n_lev=n_lev, n_large=3, noise=1.0)
+    w.lagrange_order = 3
+    _parity(w)
+
+
+def test_cubic_vertical_interpolation_gas_giant_with_forcing():
+    w = workloads.small_gas_giant(glevel=3, n_lev=20, n_large=3)
+    w.lagrange_order = 3
+    _parity(w)
+
+
+def test_cubic_shallow_hydrostatic_together():
+    w = small_earth(glevel=3, n_lev=16, n_large=3, noise=1.0)
+    w.lagrange_order = 3
+    w.shallow = True
+    w.hydrostatic = True
+    _parity(w)
+
+
+def test_cubic_mixed_precision_stays_close():
+    w = workloads.small_gas_giant(glevel=3, n_lev=20, n_large=3)
+    w.lagrange_order = 3
+    _parity(w, precision=1, tol=1e-5, names=("T", "p", "rho"))
+
+
+def test_order_zero_is_order_one_and_bad_orders_are_rejected():
+    import numpy as np
+    from paper_1607_05535_amd import thor
+    outs = []
+    for order in (0, 1):
+        w = small_earth(glevel=2, n_lev=8, n_large=2, noise=1.0)
+        w.lagrange_order = order
+        st = lib_state(w)
+        st.step(w.n_large, w.n_acoustic)
+        outs.append(lib_fields(st, ("T", "u")))
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k])
+    for order, n_lev in ((2, 8), (3, 3), (4, 8)):
+        w = small_earth(glevel=2, n_lev=n_lev, n_large=1)
+        w.lagrange_order = order
+        with pytest.raises(thor.ThorError, match="lagrange_order"):
+            lib_state(w)

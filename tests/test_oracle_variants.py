@@ -223,3 +223,8 @@ def test_order_three_needs_four_levels():
     w.lagrange_order = 3
     with pytest.raises(ValueError):
         _model(w)
+
+
+def test_order_one_allows_a_single_level():
+    w = small_earth(glevel=2, n_lev=1)
+    _model(w)
