@@ -354,6 +354,7 @@ def main():
     ap.add_argument("--no-hot-jupiter", action="store_true")
     ap.add_argument("--no-zonal", action="store_true")
     ap.add_argument("--no-energy-fixer", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -419,6 +420,17 @@ def main():
         out["energy_fixer"] = {"workload": "the g6 L32 workload with the uniform internal-energy fixer",
                                "value": updates / Tf, "ms_per_step": Tf / args.steps * 1e3,
                                "overhead_vs_fp64": Tf / T64 - 1.0}
+    if not args.no_variants:
+        # the switchable approximations of the g6 L32 workload, FP64
+        out["variants"] = {}
+        for name, attr, val in (("hydrostatic", "hydrostatic", True), ("shallow", "shallow", True),
+                                ("cubic_vertical_interpolation", "lagrange_order", 3)):
+            wv = workloads.gas_giant_c2()
+            setattr(wv, attr, val)
+            kv = max(1, args.steps // 2)
+            Tv, _, _, _ = run_gpu(wv, 0, kv, args.warmup)
+            out["variants"][name] = {"value": wv.cells * subs * kv / Tv, "unit": "cell-updates/s",
+                                     "ms_per_step": Tv / kv * 1e3}
     if not args.no_hot_jupiter:
         out["hot_jupiter"] = run_physics_case(
             workloads.hot_jupiter(glevel=5, n_lev=37),
