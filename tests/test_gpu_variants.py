@@ -125,3 +125,36 @@ def test_order_zero_is_order_one_and_bad_orders_are_rejected():
         w.lagrange_order = order
         with pytest.raises(thor.ThorError, match="lagrange_order"):
             lib_state(w)
+
+
+@pytest.mark.parametrize("switches", [
+    dict(energy_fixer=True, hydrostatic=True),
+    dict(shallow=True, lagrange_order=3),
+    dict(energy_fixer=True, shallow=True, lagrange_order=3, forcing_kind=1)])
+def test_switches_under_graphs_checkpoints_and_autotune(switches):
+    """With the switches on: graph replays equal eager launches bitwise,
+    a checkpoint restart equals a straight run bitwise, and autotuning
+    leaves the state as it found it."""
+    import numpy as np
+    from paper_1607_05535_amd import thor
+    w = small_earth(glevel=3, n_lev=16, n_large=4, noise=1.0)
+    for k, v in switches.items():
+        setattr(w, k, v)
+    say(f"[variant] runtime checks {switches}")
+    a = lib_state(w)
+    a.step(4, 6)
+    ref = a.export()[0]
+    b = lib_state(w)
+    thor.thor_set_timing(b.handle, 1)      # eager launches
+    b.step(4, 6)
+    thor.thor_set_timing(b.handle, 0)
+    assert np.array_equal(b.export()[0], ref)
+    c = lib_state(w)
+    c.step(2, 6)
+    blob = c.export()[0]
+    d = lib_state(w)
+    d.load(blob)
+    thor.thor_autotune(d.handle, 6)
+    assert np.array_equal(d.export()[0], blob)
+    d.step(2, 6)
+    assert np.array_equal(d.export()[0], ref)
