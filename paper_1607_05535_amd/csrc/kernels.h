@@ -71,6 +71,7 @@ struct Consts {
   int hydrostatic;        // 1: no vertical acceleration in the acoustic substeps
   int shallow;            // 1: shallow atmosphere (r = radius), traditional Coriolis
   int vorder;             // order of the vertical Lagrange interpolation (1 or 3)
+  int vnl, vlpc, vcpw;    // phase V: levels per lane (1 or 2); with 2, lanes per column and columns per wavefront
   int forcing;
   double tau;
   // hot-Jupiter benchmark forcing (Eqs. teq-hj, btrop, tvert)

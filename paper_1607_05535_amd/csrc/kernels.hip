@@ -334,18 +334,17 @@ __device__ __forceinline__ void b_hmom(const Fields<H> &f, const Consts &c, cons
 
 // ---------------------------------------------------------------------------
 // Physics after the dynamics (Sec. 5), backward Euler at fixed density, on
-// one cell of a column whose levels sit on consecutive lanes (every lane of
-// the wavefront calls it, since the lowest cell is read by shuffle): the
-// relaxation of T (Eq. im_eq_t) for the configured forcing.  Takes and
-// returns the cell's pressure; sigma receives p / p_s of the input state
-// (Held-Suarez only, for the friction).
+// one cell: the relaxation of T (Eq. im_eq_t) for the configured forcing.
+// Takes and returns the cell's pressure; p0, T0 are the pressure and
+// temperature of the column's lowest cell (for p_s); sigma receives p / p_s
+// of the input state (Held-Suarez only, for the friction).
 //   NEWTONIAN:   K_T = 1 / tau toward the day/night T_eq;
 //   HOT_JUPITER: K_T = 1 / tau toward Eqs. teq-hj, btrop, tvert, sigma from
 //                the surface pressure the lowest cell implies at constant T;
 //   HELD_SUAREZ: K_T and T_eq of Sec. 5 with the same sigma.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double physics_p(const Consts &c, const double *teq, int col, int lev, int lane,
-                                            double rho, double p, double &sigma) {
+__device__ __forceinline__ double physics_p(const Consts &c, const double *teq, int col, int lev, double rho,
+                                            double p, double p0, double T0, double &sigma) {
   const double dz = c.dz;
   if (c.forcing == THOR_FORCING_NEWTONIAN) {
     const double kt = c.dt / c.tau;
@@ -355,8 +354,6 @@ __device__ __forceinline__ double physics_p(const Consts &c, const double *teq, 
   } else if (c.forcing == THOR_FORCING_HOT_JUPITER) {
     const double kt = c.dt / c.tau;
     const double T = p / (rho * c.Rd);
-    const int l0 = lane - lev;
-    const double p0 = shfl(p, l0), T0 = shfl(T, l0);
     const double ps = p0 * exp(c.grav * (0.5 * dz) / (c.Rd * T0));
     const double z = (lev + 0.5) * dz, zs = c.hj_zstrat;
     double Teq;
@@ -372,8 +369,6 @@ __device__ __forceinline__ double physics_p(const Consts &c, const double *teq, 
     p = rho * c.Rd * Tn;
   } else if (c.forcing == THOR_FORCING_HELD_SUAREZ) {
     const double T = p / (rho * c.Rd);
-    const int l0 = lane - lev;
-    const double p0 = shfl(p, l0), T0 = shfl(T, l0);
     const double ps = p0 * exp(c.grav * (0.5 * dz) / (c.Rd * T0));
     sigma = p / ps;
     const double s2 = teq[col] * teq[col], c2 = 1.0 - s2;
@@ -517,7 +512,9 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
   double p = c.p_ref * pow(c.Rd * rth_new / c.p_ref, c.gamma);
   double hs_sigma = 0.0;
   if (LAST && c.forcing != THOR_FORCING_NONE) {
-    p = physics_p(c, f.teq, col, lev, ln.lane, rho_new, p, hs_sigma);
+    const int l0 = ln.lane - lev;   // the column's lowest cell
+    const double p0 = shfl(p, l0), T0 = shfl(p / (rho_new * c.Rd), l0);
+    p = physics_p(c, f.teq, col, lev, rho_new, p, p0, T0, hs_sigma);
     rth_new = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
   }
   const double D3 = Drho + (gp * Wp - gm * Wn);
@@ -529,6 +526,214 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
     // after the last substep D is not read again; the Held-Suarez friction
     // takes sigma from it
     f.D[idx] = (H)(LAST && c.forcing == THOR_FORCING_HELD_SUAREZ ? hs_sigma : D3);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Phase V with two levels per lane (32 < L <= 64: with one level per lane a
+// wavefront would hold a single column and leave 64 - L lanes idle).  Lane
+// `sub` of a column owns levels 2 sub and 2 sub + 1 and the tridiagonal rows
+// of interfaces 2 sub and 2 sub + 1; ceil(L / 2) lanes per column,
+// floor(64 / ceil(L / 2)) columns per wavefront.  The same arithmetic as
+// b_vert per cell; the solve first eliminates the odd rows inside each lane
+// (one step of cyclic reduction), runs cyclic reduction on the even rows
+// across the lanes, then recovers the odd unknowns.
+// ---------------------------------------------------------------------------
+struct Lane2 {
+  int lane, sub, lev0, col;
+  bool real_col;   // lane belongs to one of the wavefront's columns
+  bool store;      // ... and that column exists
+};
+
+__device__ __forceinline__ Lane2 map_lane2(const Consts &c, int lb) {
+  Lane2 r;
+  r.lane = threadIdx.x & 63;
+  const int wave = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int cw = r.lane / c.vlpc;
+  r.sub = r.lane - cw * c.vlpc;
+  r.lev0 = 2 * r.sub;
+  int col = wave * c.vcpw + cw;
+  r.real_col = cw < c.vcpw;
+  r.store = r.real_col && col < c.N;
+  r.col = col < c.N ? col : c.N - 1;
+  return r;
+}
+
+template <typename H, bool LAST>
+__device__ __forceinline__ void b_vert2(const Fields<H> &f, const Consts &c, const Lane2 &ln, double dtau,
+                                        int first) {
+  const int L = c.L, col = ln.col, lev0 = ln.lev0;
+  const int lm = ln.lane > 0 ? ln.lane - 1 : 0;
+  const int lp = ln.lane < 63 ? ln.lane + 1 : 63;
+  int nb[6];
+  load_nbr(f.nbr, col, nb);
+  const H *dc = f.dc + (size_t)col * 21;
+  const double *rho_in = first ? f.rho_t : f.rho;
+  const double *rth_in = first ? f.rth_t : f.rth;
+  const double *W_in = first ? f.W_t : f.W;
+  const double dz = c.dz;
+  const double c1 = dtau / dz, c2 = 0.5 * c.grav * dtau;
+
+  // per level of the lane (q = 0, 1); a level past the column's top is
+  // loaded from the top level and never stored
+  double Drho[2], rho_hat[2], rth_hat[2], phs[2], rhs[2], gam[2], thC[2], pt[2], rt[2], d0[2];
+  // radial factors of cell k: g+ = r_I(k+1)^2 / (r_C^2 dz), g- = r_I(k)^2 / (r_C^2 dz)
+  auto gpm = [&](int k, double &gpk, double &gmk) {
+    const double rI = radius_i(c, k), rI1 = rI + c.rdz;
+    const double rC = radius_c(c, k);
+    const double irc2dz = 1.0 / (rC * rC * dz);
+    gpk = rI1 * rI1 * irc2dz;
+    gmk = rI * rI * irc2dz;
+  };
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int lev = min(lev0 + q, L - 1);
+    const size_t idx = (size_t)col * L + lev;
+    H drho, dth;
+    {
+      H mx = f.Mx[idx], my = f.My[idx], mz = f.Mz[idx];
+      H t = dc[0] * mx + dc[1] * my + dc[2] * mz;
+      drho = t;
+      dth = f.thL[idx] * t;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        size_t nj = (size_t)nb[j] * L + lev;
+        H u = dc[3 * (j + 1)] * f.Mx[nj] + dc[3 * (j + 1) + 1] * f.My[nj] + dc[3 * (j + 1) + 2] * f.Mz[nj];
+        drho += u;
+        dth += f.thL[nj] * u;
+      }
+      const H ir = (H)1 / (H)radius_c(c, lev);
+      drho *= ir;
+      dth *= ir;
+    }
+    const double rho0 = rho_in[idx];
+    const double rth0 = rth_in[idx];
+    const double Wj = lev == 0 ? 0.0 : W_in[idx];
+    const double ps_in = first ? 0.0 : (double)f.ps[idx];
+    pt[q] = f.p_t[idx];
+    gam[q] = (double)f.Gam[idx];
+    thC[q] = (double)f.thL[idx];
+    Drho[q] = (double)drho;
+    const double Dth = (double)dth;
+    const double Hrth = f.Hrth[idx];
+    rho_hat[q] = rho0 + dtau * (-Drho[q] + f.Hrho[idx]);
+    rth_hat[q] = rth0 + dtau * (-Dth + Hrth);
+    phs[q] = ps_in + dtau * gam[q] * (-Dth + Hrth);
+    rt[q] = f.rho_t[idx];
+    rhs[q] = rho_hat[q] - rt[q];
+    d0[q] = c.hydrostatic ? 0.0 : Wj + dtau * f.SW[idx];
+  }
+  // values of level lev0 - 1 (the lane below's second level)
+  const double thC_m = shfl(thC[1], lm), gam_m0 = shfl(gam[1], lm), phs_m0 = shfl(phs[1], lm);
+  const double rhs_m0 = shfl(rhs[1], lm);
+  if (c.hydrostatic) {
+    // the [t] imbalance of interfaces lev0 and lev0 + 1
+    const double pt_m0 = shfl(pt[1], lm), rt_m0 = shfl(rt[1], lm);
+    d0[0] = dtau * (-(pt[0] - pt_m0) / dz - 0.5 * c.grav * (rt_m0 + rt[0]));
+    d0[1] = dtau * (-(pt[1] - pt[0]) / dz - 0.5 * c.grav * (rt[0] + rt[1]));
+  }
+  // theta at interfaces lev0, lev0 + 1, and at lev0 - 1, lev0 + 2
+  double thI[2];
+  thI[0] = 0.5 * (thC_m + thC[0]);
+  thI[1] = 0.5 * (thC[0] + thC[1]);
+  const double thI_lo = shfl(thI[1], lm), thI_hi = shfl(thI[0], lp);
+
+  double a[2], b[2], cc[2], d[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int lev = lev0 + q;
+    const double thIm = q ? thI[0] : thI_lo, thIp = q ? thI_hi : thI[1];
+    const double gamm = q ? gam[0] : gam_m0, phsm = q ? phs[0] : phs_m0, rhsm = q ? rhs[0] : rhs_m0;
+    double gpq, gmq, gpm1, gmm1;
+    gpm(min(lev, L - 1), gpq, gmq);
+    gpm(max(min(lev, L - 1) - 1, 0), gpm1, gmm1);
+    const double ap = dtau * gpq, am = dtau * gmq, apm = dtau * gpm1, amm = dtau * gmm1;
+    a[q] = 0.0;
+    b[q] = 1.0;
+    cc[q] = 0.0;
+    d[q] = 0.0;
+    if (ln.real_col && lev > 0 && lev < L) {
+      a[q] = lev == 1 ? 0.0 : -c1 * gamm * amm * thIm + c2 * amm;
+      b[q] = c.hydrostatic ? c1 * thI[q] * (gam[q] * am + gamm * apm) + c2 * (am - apm)
+                           : 1.0 + c1 * thI[q] * (gam[q] * am + gamm * apm) + c2 * (am - apm);
+      cc[q] = lev == L - 1 ? 0.0 : -c1 * gam[q] * ap * thIp - c2 * ap;
+      d[q] = d0[q] - c1 * (phs[q] - phsm) - c2 * (rhsm + rhs[q]);
+    }
+  }
+  // eliminate the odd rows: the lane's row 2 sub + 1 and the lane below's
+  const int lpc = c.vlpc;
+  const bool lo1 = ln.real_col && ln.sub > 0;
+  const double r1 = 1.0 / b[1];
+  const double a1p = shfl(a[1], lm), b1p = shfl(b[1], lm), c1p = shfl(cc[1], lm), d1p = shfl(d[1], lm);
+  const double r1p = 1.0 / b1p;
+  double A = lo1 ? -a[0] * a1p * r1p : 0.0;
+  double B = b[0] - (lo1 ? a[0] * c1p * r1p : 0.0) - cc[0] * a[1] * r1;
+  double C = -cc[0] * cc[1] * r1;
+  double D = d[0] - (lo1 ? a[0] * d1p * r1p : 0.0) - cc[0] * d[1] * r1;
+  // cyclic reduction of the even rows across the column's lanes
+  for (int s = 1; s < lpc; s <<= 1) {
+    const bool lo = ln.real_col && ln.sub >= s, hi = ln.real_col && ln.sub + s < lpc;
+    const int sl = lo ? ln.lane - s : ln.lane;
+    const int sh = hi ? ln.lane + s : ln.lane;
+    const double rb = 1.0 / B;
+    const double a_l = shfl(A, sl), rb_l = shfl(rb, sl), c_l = shfl(C, sl), d_l = shfl(D, sl);
+    const double a_h = shfl(A, sh), rb_h = shfl(rb, sh), c_h = shfl(C, sh), d_h = shfl(D, sh);
+    const double k1 = lo ? A * rb_l : 0.0;
+    const double k2 = hi ? C * rb_h : 0.0;
+    const double na = lo ? -a_l * k1 : 0.0;
+    const double nc = hi ? -c_h * k2 : 0.0;
+    B = B - (lo ? c_l * k1 : 0.0) - (hi ? a_h * k2 : 0.0);
+    D = D - (lo ? d_l * k1 : 0.0) - (hi ? d_h * k2 : 0.0);
+    A = na;
+    C = nc;
+  }
+  const double x0 = D / B;                                     // interface lev0
+  const bool hi1 = ln.real_col && ln.sub + 1 < lpc;
+  const double x2n = shfl(x0, lp);
+  const double x2 = hi1 ? x2n : 0.0;                           // interface lev0 + 2
+  const double x1 = (d[1] - a[1] * x0 - cc[1] * x2) * r1;      // interface lev0 + 1
+  double Wn[2], Wp[2];
+  Wn[0] = lev0 == 0 ? 0.0 : x0;
+  Wn[1] = lev0 + 1 < L ? x1 : 0.0;
+  Wp[0] = Wn[1];
+  Wp[1] = lev0 + 2 < L ? x2 : 0.0;
+
+  double rho_new[2], rth_new[2], p[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const double thIp = q ? thI_hi : thI[1];
+    double gpq, gmq;
+    gpm(min(lev0 + q, L - 1), gpq, gmq);
+    const double ap = dtau * gpq, am = dtau * gmq;
+    rho_new[q] = rho_hat[q] - ap * Wp[q] + am * Wn[q];
+    rth_new[q] = rth_hat[q] - ap * thIp * Wp[q] + am * thI[q] * Wn[q];
+    p[q] = c.p_ref * pow(c.Rd * rth_new[q] / c.p_ref, c.gamma);
+  }
+  double hs_sigma[2] = {0.0, 0.0};
+  if (LAST && c.forcing != THOR_FORCING_NONE) {
+    const int l0 = ln.lane - ln.sub;   // the column's first lane holds its lowest cell
+    const double p0 = shfl(p[0], l0), T0 = shfl(p[0] / (rho_new[0] * c.Rd), l0);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int lev = min(lev0 + q, L - 1);
+      p[q] = physics_p(c, f.teq, col, lev, rho_new[q], p[q], p0, T0, hs_sigma[q]);
+      rth_new[q] = c.p_ref / c.Rd * pow(p[q] / c.p_ref, 1.0 / c.gamma);
+    }
+  }
+  if (!ln.store) return;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int lev = lev0 + q;
+    if (lev >= L) continue;
+    const size_t idx = (size_t)col * L + lev;
+    double gpq, gmq;
+    gpm(lev, gpq, gmq);
+    const double D3 = Drho[q] + (gpq * Wp[q] - gmq * Wn[q]);
+    f.rho[idx] = rho_new[q];
+    f.rth[idx] = rth_new[q];
+    f.W[idx] = Wn[q];
+    f.ps[idx] = (H)(p[q] - pt[q]);
+    f.D[idx] = (H)(LAST && c.forcing == THOR_FORCING_HELD_SUAREZ ? hs_sigma[q] : D3);
   }
 }
 
@@ -1233,7 +1438,9 @@ __global__ __launch_bounds__(256) void k_fixphys(Fields<H> f, Consts c, const do
   const double p0 = c.p_ref * pow(c.Rd * f.rth[idx] / c.p_ref, c.gamma);
   double p = rho * c.Rd * (p0 / (rho * c.Rd) + *dT);
   double sigma = 0.0;
-  p = physics_p(c, f.teq, ln.col, ln.lev, ln.lane, rho, p, sigma);
+  const int l0 = ln.lane - ln.lev;   // the column's lowest cell
+  const double pl0 = shfl(p, l0), Tl0 = shfl(p / (rho * c.Rd), l0);
+  p = physics_p(c, f.teq, ln.col, ln.lev, rho, p, pl0, Tl0, sigma);
   if (!ln.store) return;
   f.rth[idx] = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
   if (c.forcing == THOR_FORCING_HELD_SUAREZ) f.D[idx] = (H)sigma;
@@ -1310,6 +1517,12 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void k_vert(Fields<H> f, Consts c, int div, int first) {
   b_vert<H, LAST>(f, c, map_lane(c, xcd_block()), c.dt / div, first);
 }
+// phase V with two levels per lane (single states, 32 < L <= 64)
+template <typename H, bool LAST>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? 2 : 3)))
+void k_vert2(Fields<H> f, Consts c, int div, int first) {
+  b_vert2<H, LAST>(f, c, map_lane2(c, xcd_block()), c.dt / div, first);
+}
 // phase V with the cubic interface theta (single states only)
 template <typename H, bool LAST>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? 3 : 4)))
@@ -1337,16 +1550,20 @@ void launch_hmom(const Fields<H> &f, const Consts &c, int wpb, int div, bool fir
 template <typename H>
 void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, bool last,
                  hipStream_t s) {
-  const dim3 g(n_blocks(c, wpb)), b(64 * wpb);
+  const dim3 g(c.vnl == 2 ? n_blocks_for(c.N, c.vcpw, wpb) : n_blocks(c, wpb)), b(64 * wpb);
   if (last) {
-    if (c.vorder == 3)
+    if (c.vnl == 2)
+      hipLaunchKernelGGL((k_vert2<H, true>), g, b, 0, s, f, c, div, (int)first);
+    else if (c.vorder == 3)
       hipLaunchKernelGGL((k_vert3<H, true>), g, b, 0, s, f, c, div, (int)first);
     else
       hipLaunchKernelGGL((k_vert<H, true>), g, b, 0, s, f, c, div, (int)first);
     if (c.forcing == THOR_FORCING_HELD_SUAREZ)
       hipLaunchKernelGGL(k_friction<H>, dim3(n_blocks(c, 4)), dim3(256), 0, s, f, c);
   } else {
-    if (c.vorder == 3)
+    if (c.vnl == 2)
+      hipLaunchKernelGGL((k_vert2<H, false>), g, b, 0, s, f, c, div, (int)first);
+    else if (c.vorder == 3)
       hipLaunchKernelGGL((k_vert3<H, false>), g, b, 0, s, f, c, div, (int)first);
     else
       hipLaunchKernelGGL((k_vert<H, false>), g, b, 0, s, f, c, div, (int)first);

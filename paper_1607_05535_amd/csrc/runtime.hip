@@ -507,6 +507,12 @@ int thor_state_init(const thor_grid *g, const thor_planet *pl, const thor_vertic
   c.shallow = num->shallow;
   c.rdz = num->shallow ? 0.0 : c.dz;
   c.vorder = num->lagrange_order == 3 ? 3 : 1;
+  // phase V packs two levels per lane where one per lane would leave a
+  // wavefront with a single column (linear interpolation only; FP64, where
+  // it measured faster; thor_autotune times both)
+  c.vnl = (c.L > 32 && c.vorder == 1 && num->precision == THOR_FP64) ? 2 : 1;
+  c.vlpc = (c.L + 1) / 2;
+  c.vcpw = 64 / c.vlpc;
   c.forcing = fo->kind;
   c.tau = (fo->kind == THOR_FORCING_NEWTONIAN || fo->kind == THOR_FORCING_HOT_JUPITER) ? fo->tau : 1.0;
   c.hs_kf = fo->k_f;
@@ -581,10 +587,15 @@ int thor_autotune(thor_state *s, int n_acoustic, int *iters_out) {
   if (rc != THOR_OK && rc != THOR_ENONFINITE) return rc;
   const int parity0 = s->parity;
   const bool timing0 = s->timing;
+  // phase V may also choose between one and two levels per lane (L > 32)
+  const bool two_ok = s->c.L > 32 && s->c.vorder == 1;
   for (int fam = 0; fam < FAM_COUNT; ++fam) {
     double best = 1e30;
-    int best_it = s->wpb[fam];
-    for (int it : cand) {
+    int best_it = s->wpb[fam], best_nl = s->c.vnl;
+    for (int k = 0; k < 8; ++k) {
+      const int it = cand[k & 3], nl = k < 4 ? 1 : 2;
+      if (nl == 2 && !(fam == FAM_VERT && two_ok)) continue;
+      if (fam == FAM_VERT) s->c.vnl = nl;
       s->wpb[fam] = it;
       s->timing = true;
       s->timed.clear();
@@ -603,9 +614,11 @@ int thor_autotune(thor_state *s, int n_acoustic, int *iters_out) {
       if (cnt > 0 && ms < best) {
         best = ms;
         best_it = it;
+        best_nl = s->c.vnl;
       }
     }
     s->wpb[fam] = best_it;
+    s->c.vnl = best_nl;
   }
   s->timing = timing0;
   s->timed.clear();
