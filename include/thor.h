@@ -292,9 +292,19 @@ int thor_state_import(thor_state *s, const void *blob, size_t bytes);
  * i.e. column groups of 1-8 x floor(64 / n_lev) columns) inside real large
  * steps with n_acoustic substeps on this state, keep the fastest, and restore
  * the state from a checkpoint taken before tuning (the state is unchanged).
+ * For 32 < n_lev <= 64 with linear interpolation the "vert" family also
+ * tries two levels per lane (thor_set_vert_levels_per_lane).
  * Synchronises.  wpb_out (4 ints, may be NULL) receives the choice in the
  * order above.  EINVAL: n_acoustic < 2 or odd. */
 int thor_autotune(thor_state *s, int n_acoustic, int *wpb_out);
+
+/* Work mapping of the acoustic phase V (the column tridiagonal): 1 level per
+ * lane (floor(64 / n_lev) columns per wavefront) or 2 levels per lane
+ * (ceil(n_lev / 2) lanes per column), the same arithmetic either way up to
+ * rounding.  The default is 2 for FP64 states with 32 < n_lev <= 64 and
+ * lagrange_order 1, else 1; thor_autotune may change it.  EINVAL: nl not 1
+ * or 2, or 2 where n_lev <= 32 or lagrange_order is 3.  Synchronises. */
+int thor_set_vert_levels_per_lane(thor_state *s, int nl);
 
 /* Mean duration [ms] of the last n kernel launches of the named kernel family
  * recorded with HIP events when timing is on (see thor_set_timing).  Used to

@@ -661,6 +661,21 @@ int thor_state_import(thor_state *s, const void *blob, size_t bytes) {
   return hip_ok(hipStreamSynchronize(s->stream), "import synchronize") ? THOR_OK : THOR_EHIP;
 }
 
+int thor_set_vert_levels_per_lane(thor_state *s, int nl) {
+  clear_error();
+  if (!s) { set_error("thor_set_vert_levels_per_lane: NULL state"); return THOR_EINVAL; }
+  if (nl != 1 && (nl != 2 || s->c.L <= 32 || s->c.vorder != 1)) {
+    set_error("thor_set_vert_levels_per_lane: 1, or 2 with 33..64 levels and linear interpolation");
+    return THOR_EINVAL;
+  }
+  if (!hip_ok(hipStreamSynchronize(s->stream), "vert mapping synchronize")) return THOR_EHIP;
+  if (s->c.vnl != nl) {
+    s->c.vnl = nl;
+    drop_graphs(s);   // captured launches carry the old mapping
+  }
+  return THOR_OK;
+}
+
 int thor_set_timing(thor_state *s, int on) {
   clear_error();
   if (!s) { set_error("thor_set_timing: NULL state"); return THOR_EINVAL; }

@@ -24,6 +24,7 @@ EXPORTED = ["thor_last_error", "thor_grid_params_default", "thor_grid_build", "t
             "thor_grid_export", "thor_grid_coefficients", "thor_grid_damping_coefficients", "thor_grid_free", "thor_state_bytes",
             "thor_state_init", "thor_step", "thor_diag", "thor_state_blob_bytes",
             "thor_state_import", "thor_set_timing", "thor_kernel_time", "thor_state_free",
+            "thor_set_vert_levels_per_lane",
             "thor_autotune", "thor_batch_bytes", "thor_batch_init", "thor_batch_step",
             "thor_batch_member", "thor_batch_autotune", "thor_batch_free",
             "thor_mlp_bytes", "thor_mlp_init", "thor_mlp_param_count", "thor_mlp_set_params",
@@ -116,6 +117,7 @@ def lib():
     L.thor_state_blob_bytes.restype = ctypes.c_size_t
     L.thor_state_import.argtypes = [vp, vp, ctypes.c_size_t]
     L.thor_set_timing.argtypes = [vp, ctypes.c_int]
+    L.thor_set_vert_levels_per_lane.argtypes = [vp, ctypes.c_int]
     L.thor_kernel_time.argtypes = [vp, ctypes.c_char_p, dp, ip]
     L.thor_autotune.argtypes = [vp, ctypes.c_int, ip]
     L.thor_state_free.argtypes = [vp]
@@ -252,6 +254,10 @@ def thor_state_import(sh, blob):
 
 def thor_set_timing(sh, on):
     _check(lib().thor_set_timing(sh, int(on)))
+
+
+def thor_set_vert_levels_per_lane(sh, nl):
+    _check(lib().thor_set_vert_levels_per_lane(sh, int(nl)))
 
 
 def thor_kernel_time(sh, name):

@@ -119,3 +119,36 @@ def test_held_suarez_forcing():
     friction, 37 layers to 32 km) on g3 with a step scaled to the coarser grid."""
     w = workloads.held_suarez(glevel=3, n_lev=37, n_large=4, dt=3000.0, noise_amp=1.0)
     _compare(w)
+
+
+@pytest.mark.parametrize("nl", [1, 2])
+@pytest.mark.parametrize("case", ["held_suarez_37", "earth_48", "earth_33_hydrostatic"])
+def test_both_phase_v_mappings_above_32_levels(nl, case):
+    """One and two levels per lane in phase V (the autotuner chooses between
+    them for 33-64 levels): both match the oracle, with forcing in the last
+    substep and with the hydrostatic rows."""
+    from paper_1607_05535_amd import thor
+    if case == "held_suarez_37":
+        w = workloads.held_suarez(glevel=3, n_lev=37, n_large=3, dt=3000.0, noise_amp=1.0)
+    elif case == "earth_48":
+        w = small_earth(glevel=3, n_lev=48, n_large=2)
+    else:
+        w = small_earth(glevel=3, n_lev=33, n_large=2)
+        w.hydrostatic = True
+    say(f"[parity] {w.name} phase V with {nl} level(s) per lane")
+    st = lib_state(w)
+    thor.thor_set_vert_levels_per_lane(st.handle, nl)
+    st.step(w.n_large, w.n_acoustic)
+    err = rel_errors(lib_fields(st), oracle_fields(w))
+    say(f"         errors {err}")
+    for k, e in err.items():
+        assert e < TOL, (k, e)
+
+
+def test_vert_mapping_argument_errors():
+    from paper_1607_05535_amd import thor
+    st = lib_state(small_earth(glevel=2, n_lev=20, n_large=1))
+    for nl in (0, 2, 3):
+        with pytest.raises(thor.ThorError, match="levels_per_lane"):
+            thor.thor_set_vert_levels_per_lane(st.handle, nl)
+    thor.thor_set_vert_levels_per_lane(st.handle, 1)
