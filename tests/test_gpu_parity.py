@@ -152,3 +152,20 @@ def test_vert_mapping_argument_errors():
         with pytest.raises(thor.ThorError, match="levels_per_lane"):
             thor.thor_set_vert_levels_per_lane(st.handle, nl)
     thor.thor_set_vert_levels_per_lane(st.handle, 1)
+
+
+@pytest.mark.parametrize("glevel", [0, 1])
+def test_smallest_grids(glevel):
+    """The icosahedron itself (12 pentagon columns, whose two-rings cover
+    the whole sphere) and its first bisection (42 columns)."""
+    w = small_earth(glevel=glevel, n_lev=9, n_large=2, noise=1.0)
+    w.dt = 600.0 * 2 ** (4 - glevel)
+    _compare(w)
+
+
+def test_zero_large_steps_leave_the_state_unchanged():
+    w = small_earth(glevel=2, n_lev=8, n_large=0)
+    st = lib_state(w)
+    before = st.export()[0]
+    st.step(0, w.n_acoustic)
+    assert np.array_equal(st.export()[0], before)
