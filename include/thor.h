@@ -301,9 +301,10 @@ int thor_autotune(thor_state *s, int n_acoustic, int *wpb_out);
 /* Work mapping of the acoustic phase V (the column tridiagonal): 1 level per
  * lane (floor(64 / n_lev) columns per wavefront) or 2 levels per lane
  * (ceil(n_lev / 2) lanes per column), the same arithmetic either way up to
- * rounding.  The default is 2 for FP64 states with 32 < n_lev <= 64 and
- * lagrange_order 1, else 1; thor_autotune may change it.  EINVAL: nl not 1
- * or 2, or 2 where n_lev <= 32 or lagrange_order is 3.  Synchronises. */
+ * rounding.  The default is 1, the ensemble kernels' mapping, so that a
+ * planet run alone equals its ensemble member bitwise; thor_autotune may
+ * choose 2 (then the two agree to rounding).  EINVAL: nl not 1 or 2, or 2
+ * where n_lev <= 32 or lagrange_order is 3.  Synchronises. */
 int thor_set_vert_levels_per_lane(thor_state *s, int nl);
 
 /* Mean duration [ms] of the last n kernel launches of the named kernel family

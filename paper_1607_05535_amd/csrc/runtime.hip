@@ -507,10 +507,11 @@ int thor_state_init(const thor_grid *g, const thor_planet *pl, const thor_vertic
   c.shallow = num->shallow;
   c.rdz = num->shallow ? 0.0 : c.dz;
   c.vorder = num->lagrange_order == 3 ? 3 : 1;
-  // phase V packs two levels per lane where one per lane would leave a
-  // wavefront with a single column (linear interpolation only; FP64, where
-  // it measured faster; thor_autotune times both)
-  c.vnl = (c.L > 32 && c.vorder == 1 && num->precision == THOR_FP64) ? 2 : 1;
+  // phase V: one level per lane, as in the ensemble kernels (a planet's
+  // results then equal its ensemble member's bitwise); thor_autotune may
+  // pack two levels per lane where one per lane leaves a wavefront with a
+  // single column
+  c.vnl = 1;
   c.vlpc = (c.L + 1) / 2;
   c.vcpw = 64 / c.vlpc;
   c.forcing = fo->kind;
