@@ -68,7 +68,8 @@ template <typename H>
 __global__ __launch_bounds__(256) void k_fields(Fields<H> f, Consts c, float *out) {
   const CLane ln = clane(c.N, c.L);
   const int L = c.L;
-  const size_t idx = (size_t)ln.col * L + ln.lev;
+  const size_t idx = (size_t)ln.col * c.S + ln.lev;   // state (row stride S)
+  const size_t oi = (size_t)ln.col * L + ln.lev;      // output, [f][col][lev]
   const int lp = ln.lane < 63 ? ln.lane + 1 : 63;
   const double W = ln.lev == 0 ? 0.0 : f.W_t[idx];
   double W1 = __shfl(W, lp, 64);
@@ -81,11 +82,11 @@ __global__ __launch_bounds__(256) void k_fields(Fields<H> f, Consts c, float *ou
   east_north(rh[0], rh[1], rh[2], e, n);
   const double vx = (double)f.Mx_t[idx] / rho, vy = (double)f.My_t[idx] / rho, vz = (double)f.Mz_t[idx] / rho;
   const size_t NL = (size_t)c.N * L;
-  out[idx] = (float)(p / (rho * c.Rd));
-  out[NL + idx] = (float)(e[0] * vx + e[1] * vy + e[2] * vz);
-  out[2 * NL + idx] = (float)(n[0] * vx + n[1] * vy + n[2] * vz);
-  out[3 * NL + idx] = (float)(0.5 * (W + W1) / rho);
-  out[4 * NL + idx] = (float)p;
+  out[oi] = (float)(p / (rho * c.Rd));
+  out[NL + oi] = (float)(e[0] * vx + e[1] * vy + e[2] * vz);
+  out[2 * NL + oi] = (float)(n[0] * vx + n[1] * vy + n[2] * vz);
+  out[3 * NL + oi] = (float)(0.5 * (W + W1) / rho);
+  out[4 * NL + oi] = (float)p;
 }
 
 // Coarse state from a fine one: area-weighted T and p, mass-weighted
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(256) void k_restrict(Fields<H> ff, Consts cf, Field
   const int a = off[ln.col], b = off[ln.col + 1];
   for (int i = a; i < b; ++i) {
     const int fcol = list[i];
-    const size_t fi = (size_t)fcol * L + ln.lev;
+    const size_t fi = (size_t)fcol * cf.S + ln.lev;
     const double W = ln.lev == 0 ? 0.0 : ff.W_t[fi];
     double W1 = __shfl(W, lp, 64);
     if (ln.lev == L - 1) W1 = 0.0;
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(256) void k_restrict(Fields<H> ff, Consts cf, Field
   const double mw = rho * (smw / sM);   // rho w at the centre
   const double mw_m = __shfl(mw, lm, 64);
   if (!ln.store) return;
-  const size_t ci = (size_t)ln.col * L + ln.lev;
+  const size_t ci = (size_t)ln.col * cc.S + ln.lev;
   fc.rho_t[ci] = rho;
   fc.rth_t[ci] = cc.p_ref / cc.Rd * pow(p / cc.p_ref, 1.0 / cc.gamma);
   fc.Mx_t[ci] = (H)(rho * vx);
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(256) void k_apply(Fields<H> f, Consts c, const floa
   const int L = c.L;
   const int k = ln.lev;
   const int lm = ln.lane > 0 ? ln.lane - 1 : 0;
-  const size_t idx = (size_t)ln.col * L + k;
+  const size_t idx = (size_t)ln.col * c.S + k;
   const float *y = Y + (size_t)ln.col * kF * L;
   const float yT = y[k], yu = y[L + k], yv = y[2 * L + k], yw = y[3 * L + k], yp = y[4 * L + k];
   float m = fmaxf(fmaxf(fabsf(yT), fabsf(yu)), fmaxf(fmaxf(fabsf(yv), fabsf(yw)), fabsf(yp)));

@@ -61,6 +61,7 @@ struct Fields {
 
 struct Consts {
   int N, L, cpw;          // columns, levels, columns per wavefront
+  int S;                  // row stride of the per-cell state arrays (L rounded up to a multiple of 4)
   int hlpc, hcpw;         // phase-M mapping: lanes per column, columns per wavefront
   double radius, omega, grav, Rd, Cp, Cv, gamma, p_ref;
   double dz, Kd;

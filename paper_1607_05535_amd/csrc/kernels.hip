@@ -30,8 +30,11 @@
 #include "internal.h"
 #include "kernels.h"
 
-// Wavefronts per SIMD that the phase-M kernel is compiled for (register cap
-// 512 / n): its two-ring gathers need many loads in flight per wavefront.
+// Wavefronts per SIMD that the phase-M kernel is compiled for, as both the
+// minimum and the maximum (register budget 512 / n): scheduled for that
+// budget the two-ring gathers keep many loads in flight per wavefront
+// (FP64: 33 us at 2 against 36 us at 3 and 43 us when the compiler is left
+// to aim for 4, at g6 L32).
 #define HMOM_OCC_D 2
 #define HMOM_OCC_F 4
 
@@ -119,7 +122,8 @@ __device__ __forceinline__ HLane map_hlane(const Consts &c, int lb) {
 }
 
 // kHq consecutive values starting at p.  VEC: p is 16-byte aligned and all
-// kHq are valid (L a multiple of kHq); else only the first nv are read.
+// kHq are readable (the state rows have stride S, a multiple of kHq; levels
+// from L up are padding); else only the first nv are read.
 template <bool VEC>
 __device__ __forceinline__ void ld4(const double *p, int nv, double v[kHq]) {
   if (VEC) {
@@ -224,7 +228,7 @@ template <typename H, bool VEC>
 __device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, const HLane &ln, double dtau,
                                            int first) {
   const int L = c.L, col = ln.col, nv = ln.nv;
-  const size_t idx = (size_t)col * L + ln.lev0;
+  const size_t idx = (size_t)col * c.S + ln.lev0;
   int nb[6];
   load_nbr(f.nbr, col, nb);
   const H *dc = f.dc + (size_t)col * 21;
@@ -241,7 +245,7 @@ __device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, 
 #pragma unroll 2
     for (int j = 0; j < 6; ++j) {
       H sj[kHq];
-      ld4<VEC>(f.ps + (size_t)nb[j] * L + ln.lev0, nv, sj);
+      ld4<VEC>(f.ps + (size_t)nb[j] * c.S + ln.lev0, nv, sj);
       const H cx = dc[3 * (j + 1)], cy = dc[3 * (j + 1) + 1], cz = dc[3 * (j + 1) + 2];
 #pragma unroll
       for (int q = 0; q < kHq; ++q) {
@@ -279,7 +283,7 @@ __device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, 
     for (int m = 0; m < kRing2; ++m) {
       const int cm = ring[m];
       H dm[kHq];
-      ld4<VEC>(D + (size_t)cm * L + ln.lev0, nv, dm);
+      ld4<VEC>(D + (size_t)cm * c.S + ln.lev0, nv, dm);
       const H wx = dw[3 * m], wy = dw[3 * m + 1], wz = dw[3 * m + 2];
 #pragma unroll
       for (int q = 0; q < kHq; ++q) {
@@ -326,10 +330,7 @@ template <typename H>
 __device__ __forceinline__ void b_hmom(const Fields<H> &f, const Consts &c, const HLane &ln, double dtau,
                                        int first) {
   if (!ln.store) return;
-  if ((c.L % kHq) == 0)
-    hmom_cells<H, true>(f, c, ln, dtau, first);
-  else
-    hmom_cells<H, false>(f, c, ln, dtau, first);
+  hmom_cells<H, true>(f, c, ln, dtau, first);   // rows of stride S: whole groups of kHq
 }
 
 // ---------------------------------------------------------------------------
@@ -392,7 +393,7 @@ __device__ __forceinline__ double physics_p(const Consts &c, const double *teq, 
 template <typename H, bool LAST, int ORD = 1>
 __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, const Lane &ln, double dtau, int first) {
   const int L = c.L, lev = ln.lev, col = ln.col;
-  const size_t idx = (size_t)col * L + lev;
+  const size_t idx = (size_t)col * c.S + lev;
   int nb[6];
   load_nbr(f.nbr, col, nb);
   const H *dc = f.dc + (size_t)col * 21;
@@ -406,7 +407,7 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
     dth = f.thL[idx] * t;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      size_t nj = (size_t)nb[j] * L + lev;
+      size_t nj = (size_t)nb[j] * c.S + lev;
       H u = dc[3 * (j + 1)] * f.Mx[nj] + dc[3 * (j + 1) + 1] * f.My[nj] + dc[3 * (j + 1) + 2] * f.Mz[nj];
       drho += u;
       dth += f.thL[nj] * u;
@@ -588,7 +589,7 @@ __device__ __forceinline__ void b_vert2(const Fields<H> &f, const Consts &c, con
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int lev = min(lev0 + q, L - 1);
-    const size_t idx = (size_t)col * L + lev;
+    const size_t idx = (size_t)col * c.S + lev;
     H drho, dth;
     {
       H mx = f.Mx[idx], my = f.My[idx], mz = f.Mz[idx];
@@ -597,7 +598,7 @@ __device__ __forceinline__ void b_vert2(const Fields<H> &f, const Consts &c, con
       dth = f.thL[idx] * t;
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
-        size_t nj = (size_t)nb[j] * L + lev;
+        size_t nj = (size_t)nb[j] * c.S + lev;
         H u = dc[3 * (j + 1)] * f.Mx[nj] + dc[3 * (j + 1) + 1] * f.My[nj] + dc[3 * (j + 1) + 2] * f.Mz[nj];
         drho += u;
         dth += f.thL[nj] * u;
@@ -725,7 +726,7 @@ __device__ __forceinline__ void b_vert2(const Fields<H> &f, const Consts &c, con
   for (int q = 0; q < 2; ++q) {
     const int lev = lev0 + q;
     if (lev >= L) continue;
-    const size_t idx = (size_t)col * L + lev;
+    const size_t idx = (size_t)col * c.S + lev;
     double gpq, gmq;
     gpm(lev, gpq, gmq);
     const double D3 = Drho[q] + (gpq * Wp[q] - gmq * Wn[q]);
@@ -743,7 +744,7 @@ __device__ __forceinline__ void b_vert2(const Fields<H> &f, const Consts &c, con
 template <typename H>
 __device__ __forceinline__ void b_friction(const Fields<H> &f, const Consts &c, const Lane &ln) {
   if (!ln.store || c.forcing != THOR_FORCING_HELD_SUAREZ) return;
-  const size_t idx = (size_t)ln.col * c.L + ln.lev;
+  const size_t idx = (size_t)ln.col * c.S + ln.lev;
   const double sigma = (double)f.D[idx];
   const double kv = c.hs_kf * fmax(0.0, (sigma - c.hs_sb) / (1.0 - c.hs_sb));
   const double den = 1.0 + kv * c.dt;
@@ -763,7 +764,7 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
   const int lane = threadIdx.x & 63;
   const int lm = lane > 0 ? lane - 1 : 0;
   const int lp = lane < 63 ? lane + 1 : 63;
-  const size_t idx = (size_t)col * L + lev0;
+  const size_t idx = (size_t)col * c.S + lev0;
   const double *rho = from_t ? f.rho_t : f.rho;
   const double *rth = from_t ? f.rth_t : f.rth;
   const double *W = from_t ? f.W_t : f.W;
@@ -825,7 +826,7 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
   }
 #pragma unroll 1
   for (int j = 0; j < 6; ++j) {
-    const size_t nj = (size_t)nb[j] * L + lev0;
+    const size_t nj = (size_t)nb[j] * c.S + lev0;
     double wn[kHq], rj[kHq];
     H mxj[kHq], myj[kHq], mzj[kHq];
     ld4<VEC>(W + nj, nv, wn);
@@ -979,10 +980,7 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
 
 template <typename H, bool SHALLOW = false, int ORD = 1>
 __device__ __forceinline__ void b_slow(const Fields<H> &f, const Consts &c, const HLane &ln, int from_t) {
-  if ((c.L % kHq) == 0)
-    slow_cells<H, true, SHALLOW, ORD>(f, c, ln, from_t);
-  else
-    slow_cells<H, false, SHALLOW, ORD>(f, c, ln, from_t);
+  slow_cells<H, true, SHALLOW, ORD>(f, c, ln, from_t);   // rows of stride S: whole groups of kHq
 }
 
 // ---------------------------------------------------------------------------
@@ -1012,7 +1010,7 @@ __device__ __forceinline__ void interface_rho(const Consts &c, const double rho[
 template <typename H, bool VEC>
 __device__ __forceinline__ void large0_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
   const int L = c.L, lev0 = ln.lev0, nv = ln.nv;
-  const size_t idx = (size_t)ln.col * L + lev0;
+  const size_t idx = (size_t)ln.col * c.S + lev0;
   const int lane = threadIdx.x & 63;
   const int lm = lane > 0 ? lane - 1 : 0;
   const int lp = lane < 63 ? lane + 1 : 63;
@@ -1049,7 +1047,7 @@ __device__ __forceinline__ void large0_cells(const Fields<H> &f, const Consts &c
 // sum_j l_j (s_j - s_0) at kHq consecutive levels: the Laplacian without
 // its 1/r^2.
 template <bool VEC, typename T, typename H>
-__device__ __forceinline__ void lap4(const T *s, const int nb[6], const H *lc, int L, int lev0, int nv, size_t idx,
+__device__ __forceinline__ void lap4(const T *s, const int nb[6], const H *lc, int S, int lev0, int nv, size_t idx,
                                      T out[kHq]) {
   T s0[kHq];
   ld4<VEC>(s + idx, nv, s0);
@@ -1058,7 +1056,7 @@ __device__ __forceinline__ void lap4(const T *s, const int nb[6], const H *lc, i
 #pragma unroll 2
   for (int j = 0; j < 6; ++j) {
     T sj[kHq];
-    ld4<VEC>(s + (size_t)nb[j] * L + lev0, nv, sj);
+    ld4<VEC>(s + (size_t)nb[j] * S + lev0, nv, sj);
     const T w = (T)lc[j];
 #pragma unroll
     for (int q = 0; q < kHq; ++q) out[q] += w * (sj[q] - s0[q]);
@@ -1068,7 +1066,7 @@ __device__ __forceinline__ void lap4(const T *s, const int nb[6], const H *lc, i
 template <typename H, bool VEC>
 __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
   const int L = c.L, lev0 = ln.lev0, nv = ln.nv, col = ln.col;
-  const size_t idx = (size_t)col * L + lev0;
+  const size_t idx = (size_t)col * c.S + lev0;
   const int lane = threadIdx.x & 63;
   const int lm = lane > 0 ? lane - 1 : 0;
   const int lp = lane < 63 ? lane + 1 : 63;
@@ -1093,7 +1091,7 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
   }
   {
     double l[kHq];
-    lap4<VEC>(f.rho_t, nb, lch, L, lev0, nv, idx, l);
+    lap4<VEC>(f.rho_t, nb, lch, c.S, lev0, nv, idx, l);
 #pragma unroll
     for (int q = 0; q < kHq; ++q) l[q] = irc2[q] * l[q];
     st4<VEC>(f.Xrho + idx, nv, l);
@@ -1103,14 +1101,14 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
 #pragma unroll 1
   for (int k = 0; k < 4; ++k) {
     double l[kHq];
-    lap4<VEC>(vsrc[k], nb, lch, L, lev0, nv, idx, l);
+    lap4<VEC>(vsrc[k], nb, lch, c.S, lev0, nv, idx, l);
 #pragma unroll
     for (int q = 0; q < kHq; ++q) l[q] = rho[q] * Kd * irc2[q] * l[q];
     st4<VEC>(vdst[k] + idx, nv, l);
   }
   {
     double l[kHq];
-    lap4<VEC>(f.wI, nb, lch, L, lev0, nv, idx, l);
+    lap4<VEC>(f.wI, nb, lch, c.S, lev0, nv, idx, l);
 #pragma unroll
     for (int q = 0; q < kHq; ++q) {
       const int lev = lev0 + q;
@@ -1127,7 +1125,7 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
 #pragma unroll 2
     for (int j = 0; j < 6; ++j) {
       double pj[kHq];
-      ld4<VEC>(f.p_t + (size_t)nb[j] * L + lev0, nv, pj);
+      ld4<VEC>(f.p_t + (size_t)nb[j] * c.S + lev0, nv, pj);
       const double cx = dch[3 * (j + 1)], cy = dch[3 * (j + 1) + 1], cz = dch[3 * (j + 1) + 2];
 #pragma unroll
       for (int q = 0; q < kHq; ++q) {
@@ -1163,7 +1161,7 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
     for (int q = 0; q < kHq; ++q) dm[q] = dch[0] * mx[q] + dch[1] * my[q] + dch[2] * mz[q];
 #pragma unroll 2
     for (int j = 0; j < 6; ++j) {
-      const size_t nj = (size_t)nb[j] * L + lev0;
+      const size_t nj = (size_t)nb[j] * c.S + lev0;
       ld4<VEC>(f.Mx_t + nj, nv, mx);
       ld4<VEC>(f.My_t + nj, nv, my);
       ld4<VEC>(f.Mz_t + nj, nv, mz);
@@ -1195,7 +1193,7 @@ template <typename H, bool VEC>
 __device__ __forceinline__ void large2_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
   if (!ln.store) return;
   const int L = c.L, lev0 = ln.lev0, nv = ln.nv, col = ln.col;
-  const size_t idx = (size_t)col * L + lev0;
+  const size_t idx = (size_t)col * c.S + lev0;
   int nb[6];
   load_nbr(f.nbr, col, nb);
   const H *lch = f.lc + (size_t)col * 6;
@@ -1207,16 +1205,16 @@ __device__ __forceinline__ void large2_cells(const Fields<H> &f, const Consts &c
   }
   {
     double l[kHq];
-    lap4<VEC>(f.Xrho, nb, lch, L, lev0, nv, idx, l);
+    lap4<VEC>(f.Xrho, nb, lch, c.S, lev0, nv, idx, l);
 #pragma unroll
     for (int q = 0; q < kHq; ++q) l[q] = -c.Kd * irc2[q] * l[q];
     st4<VEC>(f.Hrho + idx, nv, l);
   }
   {
     double hx[kHq], hy[kHq], hz[kHq];
-    lap4<VEC>(f.Xvx, nb, lch, L, lev0, nv, idx, hx);
-    lap4<VEC>(f.Xvy, nb, lch, L, lev0, nv, idx, hy);
-    lap4<VEC>(f.Xvz, nb, lch, L, lev0, nv, idx, hz);
+    lap4<VEC>(f.Xvx, nb, lch, c.S, lev0, nv, idx, hx);
+    lap4<VEC>(f.Xvy, nb, lch, c.S, lev0, nv, idx, hy);
+    lap4<VEC>(f.Xvz, nb, lch, c.S, lev0, nv, idx, hz);
     const H *rh = f.rhat + (size_t)col * 3;
     const double rx = rh[0], ry = rh[1], rz = rh[2];
     H fx[kHq], fy[kHq], fz[kHq];
@@ -1237,7 +1235,7 @@ __device__ __forceinline__ void large2_cells(const Fields<H> &f, const Consts &c
   }
   {
     double l[kHq], fw[kHq];
-    lap4<VEC>(f.Xw, nb, lch, L, lev0, nv, idx, l);
+    lap4<VEC>(f.Xw, nb, lch, c.S, lev0, nv, idx, l);
     ld4<VEC>(f.FW + idx, nv, fw);
 #pragma unroll
     for (int q = 0; q < kHq; ++q) {
@@ -1249,7 +1247,7 @@ __device__ __forceinline__ void large2_cells(const Fields<H> &f, const Consts &c
   }
   {
     double l[kHq], rth[kHq], p[kHq];
-    lap4<VEC>(f.XT, nb, lch, L, lev0, nv, idx, l);
+    lap4<VEC>(f.XT, nb, lch, c.S, lev0, nv, idx, l);
     ld4<VEC>(f.rth_t + idx, nv, rth);
     ld4<VEC>(f.p_t + idx, nv, p);
 #pragma unroll
@@ -1261,21 +1259,18 @@ __device__ __forceinline__ void large2_cells(const Fields<H> &f, const Consts &c
 #define THOR_HBODY(NAME)                                                                       \
   template <typename H>                                                                      \
   __device__ __forceinline__ void b_##NAME(const Fields<H> &f, const Consts &c, const HLane &ln) { \
-    if ((c.L % kHq) == 0)                                                                    \
-      NAME##_cells<H, true>(f, c, ln);                                                       \
-    else                                                                                     \
-      NAME##_cells<H, false>(f, c, ln);                                                      \
+    NAME##_cells<H, true>(f, c, ln);   /* rows of stride S: whole groups of kHq */            \
   }
 THOR_HBODY(large0)
 THOR_HBODY(large1)
 THOR_HBODY(large2)
 #undef THOR_HBODY
 
-// Diagnostic field into f.diag (FP64, canonical layout).
+// Diagnostic field into f.diag (FP64, canonical layout [col][lev]).
 template <typename H>
 __device__ __forceinline__ void b_diag(const Fields<H> &f, const Consts &c, const Lane &ln, int field) {
   const int L = c.L, lev = ln.lev, col = ln.col;
-  const size_t idx = (size_t)col * L + lev;
+  const size_t idx = (size_t)col * c.S + lev;
   const int lp = ln.lane < 63 ? ln.lane + 1 : 63;
   const double W = lev == 0 ? 0.0 : f.W_t[idx];
   double W1 = shfl(W, lp);
@@ -1309,7 +1304,7 @@ __device__ __forceinline__ void b_diag(const Fields<H> &f, const Consts &c, cons
   } else {
     out = W;
   }
-  f.diag[idx] = out;
+  f.diag[(size_t)col * L + lev] = out;
 }
 
 // Mass partial sums and a non-finite count per block (fixed reduction order).
@@ -1317,8 +1312,8 @@ template <typename H>
 __global__ __launch_bounds__(256) void k_mass(Fields<H> f, Consts c) {
   __shared__ double sm[4][2];
   const Lane ln = map_lane(c, xcd_block());
-  const int L = c.L, lev = ln.lev, col = ln.col;
-  const size_t idx = (size_t)col * L + lev;
+  const int lev = ln.lev, col = ln.col;
+  const size_t idx = (size_t)col * c.S + lev;
   double m = 0.0, bad = 0.0;
   if (ln.store) {
     const double rC = radius_c(c, lev);
@@ -1360,7 +1355,7 @@ __global__ __launch_bounds__(256) void k_energy(Fields<H> f, Consts c, int which
   __shared__ double sm[4][2];
   const Lane ln = map_lane(c, xcd_block());
   const int L = c.L, lev = ln.lev, col = ln.col;
-  const size_t idx = (size_t)col * L + lev;
+  const size_t idx = (size_t)col * c.S + lev;
   const double *rho_a = which ? f.rho : f.rho_t;
   const double *rth_a = which ? f.rth : f.rth_t;
   const double *W_a = which ? f.W : f.W_t;
@@ -1433,7 +1428,7 @@ __global__ __launch_bounds__(256) void k_efix(const double *pa, const double *pb
 template <typename H>
 __global__ __launch_bounds__(256) void k_fixphys(Fields<H> f, Consts c, const double *dT) {
   const Lane ln = map_lane(c, xcd_block());
-  const size_t idx = (size_t)ln.col * c.L + ln.lev;
+  const size_t idx = (size_t)ln.col * c.S + ln.lev;
   const double rho = f.rho[idx];
   const double p0 = c.p_ref * pow(c.Rd * f.rth[idx] / c.p_ref, c.gamma);
   double p = rho * c.Rd * (p0 / (rho * c.Rd) + *dT);
@@ -1446,18 +1441,20 @@ __global__ __launch_bounds__(256) void k_fixphys(Fields<H> f, Consts c, const do
   if (c.forcing == THOR_FORCING_HELD_SUAREZ) f.D[idx] = (H)sigma;
 }
 
-// Prognostic fields from a staged FP64 blob (checkpoint import).
+// Prognostic fields from a staged FP64 blob (checkpoint import; canonical
+// [col][lev] layout).
 template <typename H>
 __device__ __forceinline__ void b_import(const Fields<H> &f, const Consts &c, const Lane &ln, const double *blob) {
   if (!ln.store) return;
   const size_t NL = (size_t)c.N * c.L;
-  const size_t idx = (size_t)ln.col * c.L + ln.lev;
-  f.rho_t[idx] = blob[idx];
-  f.Mx_t[idx] = (H)blob[NL + idx];
-  f.My_t[idx] = (H)blob[2 * NL + idx];
-  f.Mz_t[idx] = (H)blob[3 * NL + idx];
-  f.rth_t[idx] = blob[4 * NL + idx];
-  f.W_t[idx] = ln.lev == 0 ? 0.0 : blob[5 * NL + idx];
+  const size_t bi = (size_t)ln.col * c.L + ln.lev;
+  const size_t idx = (size_t)ln.col * c.S + ln.lev;
+  f.rho_t[idx] = blob[bi];
+  f.Mx_t[idx] = (H)blob[NL + bi];
+  f.My_t[idx] = (H)blob[2 * NL + bi];
+  f.Mz_t[idx] = (H)blob[3 * NL + bi];
+  f.rth_t[idx] = blob[4 * NL + bi];
+  f.W_t[idx] = ln.lev == 0 ? 0.0 : blob[5 * NL + bi];
 }
 
 // OCC: minimum wavefronts per SIMD the register allocation must allow
@@ -1491,12 +1488,14 @@ THOR_KERNEL(diag, 8, map_lane, COMMA int field, COMMA field)
 THOR_KERNEL(import, 8, map_lane, COMMA const double *blob, COMMA blob)
 THOR_KERNEL(friction, 8, map_lane, , )
 template <typename H>
-__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? HMOM_OCC_D : HMOM_OCC_F)))
+__global__ __launch_bounds__(kMaxBlock)
+__attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? HMOM_OCC_D : HMOM_OCC_F, sizeof(H) == 8 ? HMOM_OCC_D : HMOM_OCC_F)))
 void k_hmom(Fields<H> f, Consts c, int div, int first) {
   b_hmom(f, c, map_hlane(c, xcd_block()), c.dt / div, first);
 }
 template <typename H>
-__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? HMOM_OCC_D : HMOM_OCC_F)))
+__global__ __launch_bounds__(kMaxBlock)
+__attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? HMOM_OCC_D : HMOM_OCC_F, sizeof(H) == 8 ? HMOM_OCC_D : HMOM_OCC_F)))
 void kb_hmom(const Planet<H> *P, const int2 *tiles, int parity, int div, int first) {
   const int2 t = tiles[xcd_block()];
   if (t.x < 0) return;

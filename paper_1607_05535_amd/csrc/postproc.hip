@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void k_zinterp(Fields<H> f, Consts c, const do
   int col = wave * cpw + cw;
   const bool store = real && col < c.N;
   if (col >= c.N) col = c.N - 1;
-  const size_t idx = (size_t)col * L + lev;
+  const size_t idx = (size_t)col * c.S + lev;   // state row stride
   const double rho = f.rho_t[idx], rth = f.rth_t[idx];
   const double p = c.p_ref * pow(c.Rd * rth / c.p_ref, c.gamma);
   const H *rh = f.rhat + (size_t)col * 3;

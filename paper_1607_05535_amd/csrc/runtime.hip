@@ -47,9 +47,15 @@ struct Carver {
   }
 };
 
+// Per-cell state arrays use the row stride S = L rounded up to a multiple of
+// kHq, so that every row starts 16-byte aligned and the gather kernels load
+// whole groups of kHq levels; the staging/diagnostic area keeps the
+// canonical [col][lev] layout.
+inline size_t row_stride(size_t L) { return (L + kHq - 1) / kHq * kHq; }
+
 template <typename H>
 void carve(Carver &cv, Fields<H> &f, size_t N, size_t L) {
-  const size_t NL = N * L;
+  const size_t NL = N * row_stride(L), NLc = N * L;
   f.nbr = cv.take<int32_t>(N * 6);
   f.dc = cv.take<H>(N * 21);
   f.lc = cv.take<H>(N * 6);
@@ -98,7 +104,7 @@ void carve(Carver &cv, Fields<H> &f, size_t N, size_t L) {
   f.Xw = cv.take<double>(NL);
   f.XT = cv.take<double>(NL);
   // the staging/diagnostic area doubles as checkpoint staging (6 fields)
-  f.diag = cv.take<double>(6 * NL);
+  f.diag = cv.take<double>(6 * NLc);
   f.partial = cv.take<double>(2 * ((N + 3) / 4 + 16));
   f.epart = cv.take<double>(4 * ((N + 3) / 4 + 16) + 8);
 }
@@ -202,8 +208,10 @@ template <typename H>
 int upload(thor_state *s, const Grid &G, const thor_planet *pl, const thor_vertical *v,
            const thor_forcing *fo, const thor_init *in, char *base, Fields<H> *fp) {
   Carver cv{base};
-  const size_t N = G.n, L = v->n_lev, NL = N * L;
+  const size_t N = G.n, L = v->n_lev, S = row_stride(L), NL = N * S;
   carve(cv, fp[0], N, L);
+  // every array starts at zero (padding levels included)
+  if (!hip_ok(hipMemsetAsync(base, 0, cv.off, s->stream), "clear state")) return THOR_EHIP;
   fp[1] = swapped(fp[0]);
   const Fields<H> &f = fp[0];
   const Consts &c = s->c;
@@ -242,8 +250,14 @@ int upload(thor_state *s, const Grid &G, const thor_planet *pl, const thor_verti
       double u = (double)(z >> 11) * 0x1.0p-53;
       double T = in->T0 + in->noise_amp * (2.0 * u - 1.0);
       double p = pcol[k];
-      rho[i * L + k] = p / (pl->Rd * T);
-      rth[i * L + k] = pl->p_ref / pl->Rd * std::pow(p / pl->p_ref, 1.0 / c.gamma);
+      rho[i * S + k] = p / (pl->Rd * T);
+      rth[i * S + k] = pl->p_ref / pl->Rd * std::pow(p / pl->p_ref, 1.0 / c.gamma);
+    }
+  // padding levels repeat the top level (finite, positive density)
+  for (size_t i = 0; i < N; ++i)
+    for (size_t k = L; k < S; ++k) {
+      rho[i * S + k] = rho[i * S + L - 1];
+      rth[i * S + k] = rth[i * S + L - 1];
     }
   hipStream_t st = s->stream;
   bool ok = hip_ok(hipMemcpyAsync((void *)f.nbr, G.nbr.data(), N * 6 * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy nbr") &&
@@ -486,6 +500,7 @@ int thor_state_init(const thor_grid *g, const thor_planet *pl, const thor_vertic
   Consts &c = s->c;
   c.N = (int)g->g.n;
   c.L = v->n_lev;
+  c.S = (int)row_stride(v->n_lev);
   c.cpw = 64 / v->n_lev;
   c.hlpc = (v->n_lev + kHq - 1) / kHq;
   c.hcpw = 64 / c.hlpc;
