@@ -357,9 +357,20 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--physics-only", action="store_true",
+                    help="only the hot-Jupiter and Held-Suarez benchmark setups (g5 L37)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.physics_only:
+        import workloads
+        print(json.dumps({"hot_jupiter": run_physics_case(
+                              workloads.hot_jupiter(glevel=5, n_lev=37), "hot-Jupiter benchmark g5 L37",
+                              args.steps, args.warmup),
+                          "held_suarez": run_physics_case(
+                              workloads.held_suarez(glevel=5, n_lev=37), "Held-Suarez benchmark g5 L37",
+                              args.steps, args.warmup)}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
