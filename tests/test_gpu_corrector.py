@@ -10,12 +10,14 @@ from tests.gpu_util import say
 pytestmark = pytest.mark.gpu
 
 
-def test_restriction_of_a_uniform_rest_state():
+@pytest.mark.parametrize("n_lev", [32, 13])
+def test_restriction_of_a_uniform_rest_state(n_lev):
     """Every fine column of a resting isothermal state is the same column:
-    the restriction reproduces it on the coarse grid, whatever was there."""
+    the restriction reproduces it on the coarse grid, whatever was there
+    (also with a level count whose state rows are padded)."""
     import torch
     from paper_1607_05535_amd import thor
-    fw, cw = workloads.corrector_pair(4, 2, dt_coarse=2400.0)
+    fw, cw = workloads.corrector_pair(4, 2, n_lev=n_lev, dt_coarse=2400.0)
     fw.noise_amp = 0.0
     cw.T0 = 900.0                       # a different state to overwrite
     fg, cg = thor.Grid(4), thor.Grid(2)
@@ -29,6 +31,25 @@ def test_restriction_of_a_uniform_rest_state():
         assert np.abs(got / v[None, :] - 1).max() < 1e-12, k
     for k in ("u", "v", "w"):
         assert np.abs(coarse.field(k)[0]).max() < 1e-12
+
+
+def test_fp32_fields_equal_the_diagnostics_with_padded_rows():
+    """thor_state_fields32 (the network's input fields, [5][col][lev]) at 13
+    levels (state rows of 16) against the FP64 diagnostics after two steps."""
+    import torch
+    from paper_1607_05535_amd import thor
+    from tests.gpu_util import lib_state, small_earth
+    w = small_earth(glevel=3, n_lev=13, n_large=2, noise=1.0)
+    st = lib_state(w)
+    st.step(2, w.n_acoustic)
+    out = torch.empty((5, st.n_col, st.n_lev), dtype=torch.float32, device="cuda:0")
+    thor.thor_state_fields32(st, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for i, k in enumerate(("T", "u", "v", "w", "p")):
+        ref = st.field(k)[0]
+        scale = max(np.abs(ref).max(), 1e-30)
+        assert np.abs(got[i] - ref).max() <= 2e-7 * scale, k
 
 
 def _pipeline():
