@@ -41,7 +41,7 @@ struct Fields {
   // large-step forcing (frozen over the step)
   H *FMx, *FMy, *FMz;     // proj_h(-grad p[t]) + hyperdiffusion of momentum
   double *FW;             // [t] vertical imbalance + hyperdiffusion of W
-  double *Hrho, *Hrth;    // hyperdiffusion of rho and rho theta
+  H *Hrho, *Hrth;         // hyperdiffusion of rho and rho theta (horizontal stencils)
   // stage forcing
   H *SMx, *SMy, *SMz;
   double *SW;

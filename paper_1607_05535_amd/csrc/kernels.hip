@@ -428,8 +428,8 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
   const double gam = (double)f.Gam[idx];
   const double thC = (double)f.thL[idx];
   const double Drho = (double)drho, Dth = (double)dth;
-  const double Hrth = f.Hrth[idx];
-  const double rho_hat = rho0 + dtau * (-Drho + f.Hrho[idx]);
+  const double Hrth = (double)f.Hrth[idx];
+  const double rho_hat = rho0 + dtau * (-Drho + (double)f.Hrho[idx]);
   const double rth_hat = rth0 + dtau * (-Dth + Hrth);
   const double phs = ps_in + dtau * gam * (-Dth + Hrth);   // p-hat minus p[t]
   const double rhs = rho_hat - f.rho_t[idx];              // rho-hat minus rho[t]
@@ -616,8 +616,8 @@ __device__ __forceinline__ void b_vert2(const Fields<H> &f, const Consts &c, con
     thC[q] = (double)f.thL[idx];
     Drho[q] = (double)drho;
     const double Dth = (double)dth;
-    const double Hrth = f.Hrth[idx];
-    rho_hat[q] = rho0 + dtau * (-Drho[q] + f.Hrho[idx]);
+    const double Hrth = (double)f.Hrth[idx];
+    rho_hat[q] = rho0 + dtau * (-Drho[q] + (double)f.Hrho[idx]);
     rth_hat[q] = rth0 + dtau * (-Dth + Hrth);
     phs[q] = ps_in + dtau * gam[q] * (-Dth + Hrth);
     rt[q] = f.rho_t[idx];
@@ -1206,9 +1206,10 @@ __device__ __forceinline__ void large2_cells(const Fields<H> &f, const Consts &c
   {
     double l[kHq];
     lap4<VEC>(f.Xrho, nb, lch, c.S, lev0, nv, idx, l);
+    H h[kHq];
 #pragma unroll
-    for (int q = 0; q < kHq; ++q) l[q] = -c.Kd * irc2[q] * l[q];
-    st4<VEC>(f.Hrho + idx, nv, l);
+    for (int q = 0; q < kHq; ++q) h[q] = (H)(-c.Kd * irc2[q] * l[q]);
+    st4<VEC>(f.Hrho + idx, nv, h);
   }
   {
     double hx[kHq], hy[kHq], hz[kHq];
@@ -1250,9 +1251,10 @@ __device__ __forceinline__ void large2_cells(const Fields<H> &f, const Consts &c
     lap4<VEC>(f.XT, nb, lch, c.S, lev0, nv, idx, l);
     ld4<VEC>(f.rth_t + idx, nv, rth);
     ld4<VEC>(f.p_t + idx, nv, p);
+    H h[kHq];
 #pragma unroll
-    for (int q = 0; q < kHq; ++q) l[q] = rth[q] / (c.gamma * p[q]) * (-c.Rd * irc2[q] * l[q]);
-    st4<VEC>(f.Hrth + idx, nv, l);
+    for (int q = 0; q < kHq; ++q) h[q] = (H)(rth[q] / (c.gamma * p[q]) * (-c.Rd * irc2[q] * l[q]));
+    st4<VEC>(f.Hrth + idx, nv, h);
   }
 }
 
@@ -1512,7 +1514,7 @@ void k_slow_var(Fields<H> f, Consts c, int from_t) {
   b_slow<H, SHALLOW, ORD>(f, c, map_hlane(c, xcd_block()), from_t);
 }
 template <typename H, bool LAST>
-__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? 4 : (LAST ? 5 : 6))))
 void k_vert(Fields<H> f, Consts c, int div, int first) {
   b_vert<H, LAST>(f, c, map_lane(c, xcd_block()), c.dt / div, first);
 }

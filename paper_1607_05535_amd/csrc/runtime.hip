@@ -82,8 +82,8 @@ void carve(Carver &cv, Fields<H> &f, size_t N, size_t L) {
   f.FMy = cv.take<H>(NL);
   f.FMz = cv.take<H>(NL);
   f.FW = cv.take<double>(NL);
-  f.Hrho = cv.take<double>(NL);
-  f.Hrth = cv.take<double>(NL);
+  f.Hrho = cv.take<H>(NL);
+  f.Hrth = cv.take<H>(NL);
   f.SMx = cv.take<H>(NL);
   f.SMy = cv.take<H>(NL);
   f.SMz = cv.take<H>(NL);
