@@ -227,7 +227,7 @@ __device__ __forceinline__ void st4(float *p, int nv, const float v[kHq]) {
 template <typename H, bool VEC>
 __device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, const HLane &ln, double dtau,
                                            int first) {
-  const int L = c.L, col = ln.col, nv = ln.nv;
+  const int col = ln.col, nv = ln.nv;
   const size_t idx = (size_t)col * c.S + ln.lev0;
   int nb[6];
   load_nbr(f.nbr, col, nb);
@@ -1009,7 +1009,7 @@ __device__ __forceinline__ void interface_rho(const Consts &c, const double rho[
 
 template <typename H, bool VEC>
 __device__ __forceinline__ void large0_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
-  const int L = c.L, lev0 = ln.lev0, nv = ln.nv;
+  const int lev0 = ln.lev0, nv = ln.nv;
   const size_t idx = (size_t)ln.col * c.S + lev0;
   const int lane = threadIdx.x & 63;
   const int lm = lane > 0 ? lane - 1 : 0;
@@ -1192,7 +1192,7 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
 template <typename H, bool VEC>
 __device__ __forceinline__ void large2_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
   if (!ln.store) return;
-  const int L = c.L, lev0 = ln.lev0, nv = ln.nv, col = ln.col;
+  const int lev0 = ln.lev0, nv = ln.nv, col = ln.col;
   const size_t idx = (size_t)col * c.S + lev0;
   int nb[6];
   load_nbr(f.nbr, col, nb);
