@@ -35,7 +35,7 @@ def vert_bytes_per_cell(L, mixed):
     field words read and written once, plus the per-column stencil geometry
     (neighbour ids and 7 coefficient vectors) once per column."""
     h = 4 if mixed else 8
-    reads = 3 * h + h + h + 8 + 8 + 8 + h + 8 + 8 + 8 + 8 + 8   # M, thL, Gam, rho, rth, W, p*, S_W, H_rho, H_rth, rho_t, p_t
+    reads = 3 * h + h + h + 8 + 8 + 8 + h + 8 + h + h + 8 + 8   # M, thL, Gam, rho, rth, W, p*, S_W, H_rho, H_rth, rho_t, p_t
     writes = 8 + 8 + 8 + h + h                                  # rho, rth, W, p*, D
     geom = 6 * 4 + 21 * h
     return reads + writes + geom / L
