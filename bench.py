@@ -136,11 +136,14 @@ def mixed_one_day():
 
 
 def run_physics_case(w, label, steps, warmup):
-    """One of the paper's two benchmark setups at its own size, FP64,
-    autotuned: cell-updates/s and kernel times."""
+    """One of the paper's two benchmark setups at its own size, FP64 and
+    mixed, autotuned: cell-updates/s and kernel times."""
     T, kt, sc, tuned = run_gpu(w, 0, steps, warmup)
+    T32, _, _, _ = run_gpu(w, 1, steps, warmup)
     return {"workload": label, "value": w.cells * w.substeps_per_large * steps / T, "unit": "cell-updates/s",
             "ms_per_step": T / steps * 1e3, "max_speed": sc["max_speed"],
+            "mixed": {"value": w.cells * w.substeps_per_large * steps / T32, "ms_per_step": T32 / steps * 1e3,
+                      "speedup_vs_fp64": T / T32},
             "kernel_ms": {k: v[0] for k, v in kt.items()}}
 
 
