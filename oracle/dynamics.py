@@ -599,6 +599,18 @@ def total_energy(model, st):
     return float(np.sum(e * model.G.Ac[:, None] * model.rC[None, :] ** 2) * model.dz)
 
 
+def axial_angular_momentum(model, st):
+    """Absolute angular momentum about the rotation axis: per cell the
+    relative part (R x rho v)_z with R = r_C rhat (the radial momentum adds
+    nothing about the axis) plus the planetary part rho Omega r_C^2 cos^2(lat),
+    summed over the cells with the volumes of ``mass``."""
+    P = model.rhat
+    rC = model.rC[None, :]
+    rel = rC * (P[:, None, 0] * st.M[..., 1] - P[:, None, 1] * st.M[..., 0])
+    plan = st.rho * model.planet.omega * rC ** 2 * (P[:, None, 0] ** 2 + P[:, None, 1] ** 2)
+    return float(np.sum((rel + plan) * model.G.Ac[:, None] * model.rC[None, :] ** 2) * model.dz)
+
+
 def fix_energy(model, st, E_target):
     """Energy fixer in the manner of Williamson (2009), which the paper
     implements (Sec. 3, discussion of the thermodynamic equation): one

@@ -122,3 +122,32 @@ def test_a_large_step_with_the_fixer_conserves_total_energy(fixer):
         assert rel < 1e-13
     else:
         assert rel > 1e-10
+
+
+def test_axial_angular_momentum_of_solid_body_rotation():
+    """Uniform rho0, u = U cos(lat): the relative part is
+    rho0 U (8 pi / 3) int r^3 dr and the planetary part
+    rho0 Omega (8 pi / 3) int r^4 dr.  The cells integrate cos^2(lat) over
+    the sphere exactly (the icosahedral symmetry); the midpoint rule in r
+    leaves a relative error of about dz^2 / (2 A^2) for r^4 and
+    dz^2 / (4 A^2) for r^3.  A purely meridional wind adds nothing."""
+    rho0, p0, U = 0.3, 2.0e4, 40.0
+    for g in (3, 4):
+        model = _model(glevel=g)
+        A, H, Om = model.planet.radius, model.vert.z_top, model.planet.omega
+        dz = model.dz
+        st = _uniform_state(model, rho0, p0)
+        lam, phi = dy.lon_lat(model.rhat)
+        east = np.stack([-np.sin(lam), np.cos(lam), np.zeros_like(lam)], axis=-1)
+        north = np.stack([-np.sin(phi) * np.cos(lam), -np.sin(phi) * np.sin(lam), np.cos(phi)], axis=-1)
+        L = model.vert.n_lev
+        planetary = dy.axial_angular_momentum(model, st)
+        ref_p = rho0 * Om * (8 * math.pi / 3) * ((A + H) ** 5 - A ** 5) / 5
+        assert abs(planetary / ref_p - 1) < dz * dz / A ** 2
+        M = (rho0 * U * np.cos(phi))[:, None, None] * east[:, None, :] * np.ones((1, L, 1))
+        rel = dy.axial_angular_momentum(model, dy.State(st.rho, M, st.rth, st.W)) - planetary
+        ref_r = rho0 * U * (8 * math.pi / 3) * ((A + H) ** 4 - A ** 4) / 4
+        assert abs(rel / ref_r - 1) < dz * dz / (2 * A ** 2)
+        Mn = (rho0 * 7.0 * np.cos(phi) ** 2)[:, None, None] * north[:, None, :] * np.ones((1, L, 1))
+        mer = dy.axial_angular_momentum(model, dy.State(st.rho, Mn, st.rth, st.W)) - planetary
+        assert abs(mer) < 1e-12 * abs(ref_r)
