@@ -262,10 +262,16 @@ enum {
   THOR_DIAG_FIELD = 2,         /* n_col * n_lev doubles of field `field` */
   THOR_DIAG_STATE_EXPORT = 3,  /* checkpoint blob of thor_state_blob_bytes */
   THOR_DIAG_SCALARS = 4,       /* thor_scalars */
-  THOR_DIAG_ENERGY = 5         /* 1 double: total energy [J] = sum over cells of
+  THOR_DIAG_ENERGY = 5,        /* 1 double: total energy [J] = sum over cells of
                                   (Cv p / Rd + (|rho v_h|^2 + (rho v_r)^2) / (2 rho)
                                   + rho g z) A_c r_k^2 dz, rho v_r at the layer
                                   centre (mean of its interfaces) */
+  THOR_DIAG_ANGULAR_MOMENTUM = 6 /* 1 double: absolute angular momentum about
+                                  the rotation axis [kg m^2/s] = sum over cells
+                                  of ((R x rho v_h)_z + rho Omega r_k^2
+                                  cos^2(lat)) A_c r_k^2 dz, R = r_k rhat (a
+                                  conserved quantity of the equations that the
+                                  scheme does not enforce; Sec. 3) */
 };
 enum {
   THOR_F_T = 0, THOR_F_U, THOR_F_V, THOR_F_W, THOR_F_P, THOR_F_RHO,

@@ -129,6 +129,10 @@ void launch_to_state(const Fields<H> &f, const Consts &c, const double *blob, hi
 // the small-step state (which = 1) into out[2 b], out[2 b + 1].
 template <typename H>
 void launch_energy(const Fields<H> &f, const Consts &c, int which, double *out, hipStream_t s, int *nblocks_out);
+// Partial sums (one per workgroup) of the absolute axial angular momentum of
+// the state Phi[t] (postproc.hip).
+template <typename H>
+void launch_angmom(const Fields<H> &f, const Consts &c, double *out, hipStream_t s, int *nblocks_out);
 // The energy fixer after the dynamics of a large step (the start's partial
 // sums already in f.epart), followed by the physics: replaces the physics of
 // the last phase V, which then runs with last = false.

@@ -196,7 +196,46 @@ __global__ void k_zzero(double *S, size_t n) {
 
 size_t a256z(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Partial sums per workgroup (4 wavefronts, lanes = levels) of the absolute
+// angular momentum about the rotation axis of the state between large steps:
+// per cell (R x rho v)_z with R = r_C rhat, plus rho Omega r_C^2 cos^2(lat),
+// times the volume A_c r_C^2 dz; fixed reduction order.
+template <typename H>
+__global__ __launch_bounds__(256) void k_angmom(Fields<H> f, Consts c, double *out) {
+  __shared__ double sm[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int L = c.L, cpw = 64 / L;
+  const int cw = lane / L, lev = lane - cw * L;
+  const int col = wave * cpw + cw;
+  double v = 0.0;
+  if (cw < cpw && col < c.N) {
+    const size_t idx = (size_t)col * c.S + lev;
+    const double rC = c.radius + (lev + 0.5) * c.rdz;
+    const H *rh = f.rhat + (size_t)col * 3;
+    const double x = rh[0], y = rh[1];
+    const double rel = rC * (x * (double)f.My_t[idx] - y * (double)f.Mx_t[idx]);
+    const double plan = f.rho_t[idx] * c.omega * rC * rC * (x * x + y * y);
+    v = (rel + plan) * f.area[col] * rC * rC * c.dz;
+  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if (lane == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = ((sm[0] + sm[1]) + sm[2]) + sm[3];
+}
+
 }  // namespace
+
+template <typename H>
+void launch_angmom(const Fields<H> &f, const Consts &c, double *out, hipStream_t s, int *nblocks_out) {
+  const long waves = (c.N + 64 / c.L - 1) / (64 / c.L);
+  const int nb = (int)((waves + 3) / 4);
+  *nblocks_out = nb;
+  hipLaunchKernelGGL(k_angmom<H>, dim3(nb), dim3(256), 0, s, f, c, out);
+}
+template void launch_angmom<double>(const Fields<double> &, const Consts &, double *, hipStream_t, int *);
+template void launch_angmom<float>(const Fields<float> &, const Consts &, double *, hipStream_t, int *);
+
 }  // namespace thor
 
 using namespace thor;

@@ -384,7 +384,7 @@ int diag_impl(thor_state *s, const Fields<H> &f, int kind, int field, void *host
     if (out_bytes < sizeof(double)) { set_error("thor_diag: out_bytes too small"); return THOR_EINVAL; }
   } else if (kind == THOR_DIAG_SCALARS) {
     if (out_bytes < sizeof(thor_scalars)) { set_error("thor_diag: out_bytes too small"); return THOR_EINVAL; }
-  } else if (kind == THOR_DIAG_ENERGY) {
+  } else if (kind == THOR_DIAG_ENERGY || kind == THOR_DIAG_ANGULAR_MOMENTUM) {
     if (out_bytes < sizeof(double)) { set_error("thor_diag: out_bytes too small"); return THOR_EINVAL; }
   } else if (kind == THOR_DIAG_STATE_EXPORT) {
     if (out_bytes < thor_state_blob_bytes(s)) { set_error("thor_diag: out_bytes too small"); return THOR_EINVAL; }
@@ -421,6 +421,16 @@ int diag_impl(thor_state *s, const Fields<H> &f, int kind, int field, void *host
     double e = 0.0;
     for (int i = 0; i < ne; ++i) e += ep[2 * i];
     *(double *)host_out = e;
+  } else if (kind == THOR_DIAG_ANGULAR_MOMENTUM) {
+    int na = 0;
+    launch_angmom(f, c, f.partial, st, &na);
+    std::vector<double> ap((size_t)na);
+    if (!hip_ok(hipMemcpyAsync(ap.data(), f.partial, ap.size() * sizeof(double), hipMemcpyDeviceToHost, st), "copy angular momentum") ||
+        !hip_ok(hipStreamSynchronize(st), "diag synchronize"))
+      return THOR_EHIP;
+    double a = 0.0;
+    for (int i = 0; i < na; ++i) a += ap[i];
+    *(double *)host_out = a;
   } else if (kind == THOR_DIAG_FIELD) {
     if (!field_to_host(field, (double *)host_out)) return THOR_EHIP;
   } else if (kind == THOR_DIAG_SCALARS) {

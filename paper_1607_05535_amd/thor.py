@@ -17,6 +17,7 @@ THOR_OK, THOR_EINVAL, THOR_ENOMEM, THOR_EHIP, THOR_ENONFINITE, THOR_ENOTCONV = 0
 THOR_FP64, THOR_MIXED = 0, 1
 THOR_FORCING_NONE, THOR_FORCING_NEWTONIAN, THOR_FORCING_HOT_JUPITER, THOR_FORCING_HELD_SUAREZ = 0, 1, 2, 3
 THOR_DIAG_MASS, THOR_DIAG_FIELD, THOR_DIAG_STATE_EXPORT, THOR_DIAG_SCALARS, THOR_DIAG_ENERGY = 1, 2, 3, 4, 5
+THOR_DIAG_ANGULAR_MOMENTUM = 6
 FIELDS = {"T": 0, "u": 1, "v": 2, "w": 3, "p": 4, "rho": 5, "rhotheta": 6,
           "Mx": 7, "My": 8, "Mz": 9, "W": 10}
 
@@ -403,6 +404,11 @@ class State:
         rc = thor_diag(self.handle, THOR_DIAG_ENERGY, 0, out)
         return float(out[0]), rc
 
+    def angular_momentum(self):
+        out = np.empty(1)
+        rc = thor_diag(self.handle, THOR_DIAG_ANGULAR_MOMENTUM, 0, out)
+        return float(out[0]), rc
+
     def scalars(self):
         s = Scalars()
         arr = np.frombuffer(s, dtype=np.float64)
@@ -437,6 +443,7 @@ class Member:
     field = State.field
     mass = State.mass
     energy = State.energy
+    angular_momentum = State.angular_momentum
     scalars = State.scalars
     export = State.export
 

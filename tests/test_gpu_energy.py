@@ -90,3 +90,21 @@ def test_ensembles_reject_the_fixer():
     g = thor.Grid(w.glevel)
     with pytest.raises(thor.ThorError, match="energy fixer"):
         thor.Batch([g], [thor.structs_from_workload(w)])
+
+
+@pytest.mark.parametrize("shallow", [False, True])
+def test_axial_angular_momentum_matches_the_oracle(shallow):
+    """The absolute axial angular momentum through the C ABI, at rest and
+    after two large steps of the day/night forcing have set up winds (deep
+    and shallow forms)."""
+    w = workloads.small_gas_giant(glevel=3, n_lev=13, n_large=2)
+    w.shallow = shallow
+    model, ost = odyn.model_from_workload(w, oracle_grid(w.glevel))
+    st = lib_state(w)
+    for k in range(2):
+        a, rc = st.angular_momentum()
+        ref = odyn.axial_angular_momentum(model, ost)
+        say(f"[angmom] shallow={shallow} after {2 * k} steps: rel {abs(a / ref - 1):.2e}")
+        assert rc == 0 and abs(a / ref - 1) < 1e-12
+        st.step(2, w.n_acoustic)
+        ost = odyn.run(model, ost, 2, w.n_acoustic)
