@@ -165,7 +165,7 @@ typedef struct {
                       0: the paper's deep atmosphere.  Not available in
                       ensembles. */
   int lagrange_order; /* order k of the vertical Lagrange interpolation
-                      (Sec. 2.2) used for interface values of centre fields
+                      (Sec. 2.1) used for interface values of centre fields
                       (theta of the vertical solve, the advected velocity,
                       the slow forcing of rho v_r, rho in its hyperdiffusion)
                       and centre values of rho v_r (the advected momentum):
@@ -188,7 +188,7 @@ typedef struct {
  *                carried down to z = 0 hydrostatically at that cell's
  *                temperature.  No boundary-layer friction.
  *   HELD_SUAREZ: the Earth benchmark (Eqs. im_eq_v, im_eq_fv and the T_eq,
- *                K_T of Sec. 5): boundary-layer friction of the horizontal
+ *                K_T of Sec. 7.1): boundary-layer friction of the horizontal
  *                momentum, (rho v_h) / (1 + K_v dt) with K_v = k_f max(0,
  *                (sigma - sigma_b) / (1 - sigma_b)), and relaxation with
  *                K_T = k_a + (k_s - k_a) max(0, (sigma - sigma_b) /
@@ -475,7 +475,7 @@ void thor_corrector_free(thor_corrector *c);
 
 /* ---------------------------------------------------------------------------
  * Post-processing on pressure levels (the paper shows its results on
- * pressure levels, interpolated linearly from the model levels; Sec. 6).
+ * pressure levels, interpolated linearly from the model levels; Sec. 7).
  *
  * Each thor_zonal_accumulate call takes the state as it stands (between
  * large steps): every column's u, v, T and theta = rho theta / rho are
@@ -490,7 +490,7 @@ void thor_corrector_free(thor_corrector *c);
  *   Psi = 2 pi radius cos(lat_b) / gravity * int_0^p [v] dp
  * (trapezoid rule over plev, [v](0) = [v](plev[0])).  Beside them, each
  * snapshot adds to the grid-imprinting map of the Held-Suarez results
- * (Sec. 6): per column, w* = w - {w} in the first model layer (w at the
+ * (Sec. 7.1): per column, w* = w - {w} in the first model layer (w at the
  * layer centre; {w} the area-weighted mean over the column's band), whose
  * time mean [w*] thor_zonal_imprint returns.  Results are reproducible:
  * every sum runs in a fixed order.

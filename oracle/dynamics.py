@@ -67,7 +67,7 @@ class Numerics:
     energy_fixer: bool = False   # Sec. 3: globally uniform internal-energy fixer
     hydrostatic: bool = False    # Sec. 3: hydrostatic approximation
     shallow: bool = False        # Sec. 3: shallow atmosphere, traditional approximation
-    lagrange_order: int = 1      # Sec. 2.2: order k of the vertical interpolation
+    lagrange_order: int = 1      # Sec. 2.1: order k of the vertical interpolation
 
 
 @dataclass
@@ -81,7 +81,7 @@ class Forcing:
     z_strat: float = 2.0e6       # kind 2: z_stra (m)
     dT_strat: float = 10.0       # kind 2: Delta T_stra (K)
     sigma_strat: float = 0.12    # kind 2: sigma_stra
-    # kind 3, Held-Suarez (Eqs. im_eq_v, im_eq_fv, Sec. 5 T_eq and K_T)
+    # kind 3, Held-Suarez (Eqs. im_eq_v, im_eq_fv, Sec. 7.1 T_eq and K_T)
     k_f: float = 1.0 / 86400.0
     k_a: float = 1.0 / (40.0 * 86400.0)
     k_s: float = 1.0 / (4.0 * 86400.0)
@@ -206,7 +206,7 @@ def to_centres(W):
 
 def lagrange_weights(nodes, target):
     """Weights L_j(target) of the Lagrange polynomial through `nodes`
-    (Sec. 2.2): prod over i != j of (target - z_i) / (z_j - z_i)."""
+    (Sec. 2.1): prod over i != j of (target - z_i) / (z_j - z_i)."""
     w = np.ones(len(nodes))
     for j, zj in enumerate(nodes):
         for i, zi in enumerate(nodes):
@@ -522,7 +522,7 @@ def hot_jupiter_teq(model, p, T):
 
 
 def held_suarez_rates(model, p, T):
-    """Sec. 5, Earth benchmark: boundary-layer friction rate K_v(sigma)
+    """Sec. 7.1, Earth benchmark: boundary-layer friction rate K_v(sigma)
     (Eq. im_eq_fv), the relaxation rate K_T(sigma, lat) and T_eq(p, lat), with
     sigma = p / p_s of the dynamics output (p_s as for the hot Jupiter)."""
     f, pl = model.forcing, model.planet

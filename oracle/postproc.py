@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
 The paper's results are shown on pressure levels: fields are interpolated
-linearly in pressure from the model levels (Sec. 6, opening of the results),
+linearly in pressure from the model levels (Sec. 7, opening of the results),
 averaged zonally and in time; eddies are deviations from the zonal average
 (phi' = phi - [phi]) and the mass streamfunction is
 Psi = 2 pi A cos(lat) / g * integral_0^p [v] dp.
@@ -20,7 +20,7 @@ grid, nor what happens outside a column's pressure range):
     value in a snapshot contributes nothing to that snapshot's average;
   * Psi integrates with the trapezoid rule over the pressure levels and
     takes [v] at p = 0 equal to its value at the first (smallest) level;
-  * the grid-imprinting map [w*] (Sec. 6, Held-Suarez results) uses the
+  * the grid-imprinting map [w*] (Sec. 7.1, Held-Suarez results) uses the
     deviation of w from its zonal (band) mean, w* = w - {w}, on the first
     model layer, and then averages it in time: with the bracket read as a
     time mean alone, w - [w] would average to zero identically.
@@ -127,7 +127,7 @@ def first_layer_w(model, st):
 def imprint_snapshot(model, st, n_bands):
     """w* of one state in the first layer: w minus the area-weighted mean of
     w over the column's latitude band (the grid-imprinting diagnostic of
-    Sec. 6 before its time average)."""
+    Sec. 7.1 before its time average)."""
     w = first_layer_w(model, st)
     _, lat = lon_lat(model.rhat)
     band = band_of(lat, n_bands)

@@ -77,7 +77,7 @@ struct Consts {
   double tau;
   // hot-Jupiter benchmark forcing (Eqs. teq-hj, btrop, tvert)
   double hj_Tsurf, hj_dTep, hj_lapse, hj_zstrat, hj_dTstrat, hj_sstrat;
-  // Held-Suarez forcing (Eqs. im_eq_v, im_eq_fv; Sec. 5 T_eq, K_T)
+  // Held-Suarez forcing (Eqs. im_eq_v, im_eq_fv; Sec. 7.1 T_eq, K_T)
   double hs_kf, hs_ka, hs_ks, hs_sb, hs_dTy, hs_dthz, hs_pstar, hs_Ttop, hs_Tmin;
 };
 

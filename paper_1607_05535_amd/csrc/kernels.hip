@@ -146,7 +146,7 @@ __device__ __forceinline__ void ld4(const float *p, int nv, float v[kHq]) {
   }
 }
 // ---------------------------------------------------------------------------
-// Cubic vertical interpolation (the Lagrange interpolation of Sec. 2.2 with
+// Cubic vertical interpolation (the Lagrange interpolation of Sec. 2.1 with
 // k = 3 on the equally spaced levels).  Centre values to interface j from
 // the centres j-2..j+1, weights (-1, 9, 9, -1)/16; at the first interior
 // interface (j = 1) from centres 0..3, (5, 15, -5, 1)/16; at the last
@@ -342,7 +342,7 @@ __device__ __forceinline__ void b_hmom(const Fields<H> &f, const Consts &c, cons
 //   NEWTONIAN:   K_T = 1 / tau toward the day/night T_eq;
 //   HOT_JUPITER: K_T = 1 / tau toward Eqs. teq-hj, btrop, tvert, sigma from
 //                the surface pressure the lowest cell implies at constant T;
-//   HELD_SUAREZ: K_T and T_eq of Sec. 5 with the same sigma.
+//   HELD_SUAREZ: K_T and T_eq of Sec. 7.1 with the same sigma.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double physics_p(const Consts &c, const double *teq, int col, int lev, double rho,
                                             double p, double p0, double T0, double &sigma) {

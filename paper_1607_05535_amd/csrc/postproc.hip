@@ -1,4 +1,4 @@
-// Post-processing on pressure levels (the results of Sec. 6 are shown on
+// Post-processing on pressure levels (the results of Sec. 7 are shown on
 // pressure levels): per snapshot, every column's u, v, T and theta are
 // interpolated linearly in pressure to the requested levels; latitude-band
 // zonal means (area-weighted over the columns that have a value), the eddy

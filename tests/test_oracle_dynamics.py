@@ -294,7 +294,7 @@ def test_kd_matches_table1_damping_times():
 
 
 # ---------------------------------------------------------------------------
-# Hot-Jupiter benchmark forcing (Sec. 5, Eqs. teq-hj, btrop, tvert)
+# Hot-Jupiter benchmark forcing (Sec. 7.2, Eqs. teq-hj, btrop, tvert)
 # ---------------------------------------------------------------------------
 
 def test_hot_jupiter_vertical_profile_closed_forms():
@@ -368,7 +368,7 @@ def test_hot_jupiter_relaxation_is_backward_euler():
 
 
 # ---------------------------------------------------------------------------
-# Held-Suarez forcing (Sec. 5 Earth benchmark, Eqs. im_eq_v, im_eq_fv)
+# Held-Suarez forcing (Sec. 7.1 Earth benchmark, Eqs. im_eq_v, im_eq_fv)
 # ---------------------------------------------------------------------------
 
 def _hs_pressures(w, model, sig, T=250.0):

@@ -157,7 +157,7 @@ def test_shallow_and_deep_agree_for_a_thin_atmosphere():
 
 
 # ---------------------------------------------------------------------------
-# Vertical Lagrange interpolation of order k (Sec. 2.2)
+# Vertical Lagrange interpolation of order k (Sec. 2.1)
 # ---------------------------------------------------------------------------
 def test_lagrange_weights_reproduce_polynomials_up_to_their_degree():
     rs = np.random.default_rng(2)

@@ -153,7 +153,7 @@ def ensemble(n=64, seed=4, glevels=(4, 5, 6), levels=(20, 32, 48), n_acoustic=8)
 
 
 def hot_jupiter(glevel=5, n_lev=37, n_large=1, dt=600.0, n_acoustic=8, noise_amp=0.0, seed=5):
-    """The hot-Jupiter benchmark of Sec. 5 (Eqs. teq-hj, btrop, tvert): Table 1
+    """The hot-Jupiter benchmark of Sec. 7.2 (Eqs. teq-hj, btrop, tvert): Table 1
     planet (radius 1e8 m, rotation 2.1e-5 1/s, gravity 8, cp 13226.5,
     Rd 3779), 37 layers to 4875 km, isothermal 1600 K at rest, Newtonian
     relaxation with timescale 1.5e5 s toward T_vert + beta_trop 300 K
@@ -168,7 +168,7 @@ def hot_jupiter(glevel=5, n_lev=37, n_large=1, dt=600.0, n_acoustic=8, noise_amp
 
 
 def held_suarez(glevel=5, n_lev=37, n_large=1, dt=1000.0, n_acoustic=8, noise_amp=0.1, seed=6, T0=300.0):
-    """The Earth benchmark of Sec. 5 (Held-Suarez forcing): Table 1 Earth
+    """The Earth benchmark of Sec. 7.1 (Held-Suarez forcing): Table 1 Earth
     (radius 6.371e6 m, rotation 7.292e-5 1/s, gravity 9.8, cp 1004.6,
     Rd 287.04), 37 layers to 32 km, large step 1000 s, diffusion timescale
     6.46e3 s; friction k_f = 1/day above sigma_b = 0.7, relaxation k_a =
