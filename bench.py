@@ -376,7 +376,7 @@ def main():
                               args.steps, args.warmup)}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+        print("bench.py: the library runs on one GPU (there is no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     import workloads
