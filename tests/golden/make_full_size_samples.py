@@ -1,11 +1,13 @@
-"""Write the oracle's fields after one large step of the g6 L32 gas-giant
-benchmark workload at seeded sample cells.
+"""Write the oracle's fields after one large step of a full-size gas-giant
+workload at seeded sample cells.
 
-    python tests/golden/make_gas_giant_g6l32_samples.py
+    python tests/golden/make_full_size_samples.py g6l32   # 40962 columns x 32 levels
+    python tests/golden/make_full_size_samples.py g7l48   # 163842 columns x 48 levels
 
-Calls only `oracle/` (FP64 CPU, a few minutes): the stored values are the
-oracle's, never the library's.  Output: gas_giant_g6l32_one_step.txt, one
-line per sample "col lev T u v w p rho", then a line "mass0 mass1".
+Calls only `oracle/` (FP64 CPU; minutes for g6, longer for g7): the stored
+values are the oracle's, never the library's.  Output:
+gas_giant_<case>_one_step.txt, one line per sample "col lev T u v w p rho",
+then a line "mass mass0 mass1".
 """
 import os
 import sys
@@ -20,12 +22,16 @@ N_SAMPLES = 600
 SAMPLE_SEED = 20161  # fixes which cells are sampled
 
 
-def main():
+def _workload(case):
     import workloads
+    return {"g6l32": workloads.gas_giant_c2, "g7l48": workloads.gas_giant_c3}[case]()
+
+
+def main(case):
     from oracle import dynamics as odyn
     from oracle import grid as ogrid
 
-    w = workloads.gas_giant_c2()
+    w = _workload(case)
     G = ogrid.Grid(w.glevel, k=100.0)
     model, st = odyn.model_from_workload(w, G)
     m0 = odyn.mass(model, st)
@@ -39,10 +45,11 @@ def main():
     pent = int(np.flatnonzero(np.asarray(G.deg) == 5)[0])
     cols[:4] = [w.n_col - 2, w.n_col - 1, pent, pent]
     levs[:4] = [0, w.n_lev - 1, 0, w.n_lev - 1]
-    path = os.path.join(HERE, "gas_giant_g6l32_one_step.txt")
+    path = os.path.join(HERE, f"gas_giant_{case}_one_step.txt")
     with open(path, "w") as fh:
-        fh.write("# oracle fields after 1 large step of the g6 L32 gas giant (dt 300 s, n = 8),\n")
-        fh.write("# written by make_gas_giant_g6l32_samples.py; col lev T u v w p rho\n")
+        fh.write(f"# oracle fields after 1 large step of the g{w.glevel} L{w.n_lev} gas giant "
+                 f"(dt {w.dt:g} s, n = {w.n_acoustic}),\n")
+        fh.write(f"# written by make_full_size_samples.py {case}; col lev T u v w p rho\n")
         for c, k in zip(cols, levs):
             vals = [f[name][c, k] for name in ("T", "u", "v", "w", "p", "rho")]
             fh.write(f"{c} {k} " + " ".join(repr(float(v)) for v in vals) + "\n")
@@ -51,4 +58,6 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) != 2 or sys.argv[1] not in ("g6l32", "g7l48"):
+        sys.exit("usage: make_full_size_samples.py g6l32|g7l48")
+    main(sys.argv[1])

@@ -32,8 +32,15 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(thor.EXPORTED)
 
 
-@pytest.mark.parametrize("g,smooth", [(0, True), (2, True), (3, False), (4, True)])
+@pytest.mark.parametrize("g,smooth", [(0, True), (2, True), (3, False), (4, True), (5, True)])
 def test_host_grid_matches_oracle(g, smooth):
+    """Same topology and spring iteration count; positions and areas agree
+    to the last bits of the two atan2 implementations (NumPy's vectorised
+    one and the C library's differ by one unit in the last place for some
+    arguments), which the spring relaxation amplifies over its iterations:
+    measured largest relative area differences 5.3e-12 at g5, 4.7e-11 at
+    g6 and 3.9e-10 at g7 (the last two too slow to build here).  The next
+    test removes that one difference."""
     thor = _thor()
     G = thor.Grid(g, smooth=smooth)
     O = oracle_grid(g, smooth=smooth)
@@ -43,6 +50,24 @@ def test_host_grid_matches_oracle(g, smooth):
     assert G.spring_iters == O.spring_iters
     assert np.abs(xyz - O.P).max() < 1e-12
     assert np.abs(area / O.Ac - 1).max() < 1e-11
+
+
+def test_host_grid_equals_oracle_bitwise_with_the_same_atan2(monkeypatch):
+    """With the C library's atan2 in place of NumPy's vectorised one, the
+    oracle's spring relaxation, centroids and areas equal the host grid
+    builder's bit for bit (g4: 2562 points, 822 spring iterations)."""
+    import math
+    from oracle import grid as ogrid
+    thor = _thor()
+    G = thor.Grid(4)
+    nbr, xyz, area = G.export()
+    scalar = np.frompyfunc(math.atan2, 2, 1)
+    monkeypatch.setattr(np, "arctan2", lambda y, x: scalar(y, x).astype(np.float64))
+    O = ogrid.Grid(4, k=100.0)
+    assert G.spring_iters == O.spring_iters
+    assert np.array_equal(nbr, O.nbr.astype(np.int32))
+    assert np.array_equal(xyz, O.P)
+    assert np.array_equal(area, O.Ac)
 
 
 @pytest.mark.parametrize("g,smooth", [(3, True), (4, True), (4, False)])
