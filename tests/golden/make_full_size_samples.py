@@ -1,13 +1,14 @@
-"""Write the oracle's fields after one large step of a full-size gas-giant
-workload at seeded sample cells.
+"""Write the oracle's fields after one large step (two for the hot Jupiter)
+of a full-size workload at seeded sample cells.
 
     python tests/golden/make_full_size_samples.py g6l32   # 40962 columns x 32 levels
     python tests/golden/make_full_size_samples.py g7l48   # 163842 columns x 48 levels
+    python tests/golden/make_full_size_samples.py hs_g5l37   # Held-Suarez, 10242 x 37
+    python tests/golden/make_full_size_samples.py hj_g5l37   # hot Jupiter, 10242 x 37
 
 Calls only `oracle/` (FP64 CPU; minutes for g6, longer for g7): the stored
-values are the oracle's, never the library's.  Output:
-gas_giant_<case>_one_step.txt, one line per sample "col lev T u v w p rho",
-then a line "mass mass0 mass1".
+values are the oracle's, never the library's.  Output (named by out_name):
+one line per sample "col lev T u v w p rho", then a line "mass mass0 mass1".
 """
 import os
 import sys
@@ -24,7 +25,22 @@ SAMPLE_SEED = 20161  # fixes which cells are sampled
 
 def _workload(case):
     import workloads
-    return {"g6l32": workloads.gas_giant_c2, "g7l48": workloads.gas_giant_c3}[case]()
+    return {"g6l32": workloads.gas_giant_c2, "g7l48": workloads.gas_giant_c3,
+            "hs_g5l37": lambda: workloads.held_suarez(glevel=5, n_lev=37),
+            "hj_g5l37": lambda: workloads.hot_jupiter(glevel=5, n_lev=37)}[case]()
+
+
+CASES = ("g6l32", "g7l48", "hs_g5l37", "hj_g5l37")
+# the hot Jupiter starts at rest with no noise: its winds appear in the
+# second step, once the first step's relaxation has set up the day/night
+# contrast
+N_STEPS = {"hj_g5l37": 2}
+
+
+def out_name(case):
+    if case in ("g6l32", "g7l48"):
+        return f"gas_giant_{case}_one_step.txt"
+    return f"{case}_two_steps.txt" if N_STEPS.get(case, 1) == 2 else f"{case}_one_step.txt"
 
 
 def main(case):
@@ -35,7 +51,8 @@ def main(case):
     G = ogrid.Grid(w.glevel, k=100.0)
     model, st = odyn.model_from_workload(w, G)
     m0 = odyn.mass(model, st)
-    st = odyn.run(model, st, 1, w.n_acoustic)
+    n_steps = N_STEPS.get(case, 1)
+    st = odyn.run(model, st, n_steps, w.n_acoustic)
     f = odyn.fields(model, st)
     m1 = odyn.mass(model, st)
     rs = np.random.default_rng(SAMPLE_SEED)
@@ -45,9 +62,9 @@ def main(case):
     pent = int(np.flatnonzero(np.asarray(G.deg) == 5)[0])
     cols[:4] = [w.n_col - 2, w.n_col - 1, pent, pent]
     levs[:4] = [0, w.n_lev - 1, 0, w.n_lev - 1]
-    path = os.path.join(HERE, f"gas_giant_{case}_one_step.txt")
+    path = os.path.join(HERE, out_name(case))
     with open(path, "w") as fh:
-        fh.write(f"# oracle fields after 1 large step of the g{w.glevel} L{w.n_lev} gas giant "
+        fh.write(f"# oracle fields after {n_steps} large step(s) of {w.name} "
                  f"(dt {w.dt:g} s, n = {w.n_acoustic}),\n")
         fh.write(f"# written by make_full_size_samples.py {case}; col lev T u v w p rho\n")
         for c, k in zip(cols, levs):
@@ -58,6 +75,6 @@ def main(case):
 
 
 if __name__ == "__main__":
-    if len(sys.argv) != 2 or sys.argv[1] not in ("g6l32", "g7l48"):
-        sys.exit("usage: make_full_size_samples.py g6l32|g7l48")
+    if len(sys.argv) != 2 or sys.argv[1] not in CASES:
+        sys.exit("usage: make_full_size_samples.py " + "|".join(CASES))
     main(sys.argv[1])

@@ -59,15 +59,15 @@ def test_rest_state_stays_at_rest_on_gpu():
         assert np.abs(v).max() < 1e-8, k
 
 
-def _full_size_samples(case, w, precision, tol_thermo, tol_wind):
+def _full_size_samples(fname, w, precision, tol_thermo, tol_wind, n_steps=1):
     """Full-size workload in the benchmark's launch configuration
-    (autotuned workgroup sizes, graph replay of thor_step): after one large
-    step the sampled cells are compared with the oracle's stored values
-    (tests/golden/gas_giant_<case>_one_step.txt, written by
-    make_full_size_samples.py beside it from the oracle alone)."""
+    (autotuned workgroup sizes, graph replay of thor_step): after n_steps
+    large steps the sampled cells are compared with the oracle's stored
+    values (tests/golden/<fname>, written by make_full_size_samples.py
+    beside it from the oracle alone)."""
     import os
     from paper_1607_05535_amd import thor
-    path = os.path.join(os.path.dirname(__file__), "golden", f"gas_giant_{case}_one_step.txt")
+    path = os.path.join(os.path.dirname(__file__), "golden", fname)
     rows, mass = [], None
     for line in open(path):
         if line.startswith("#"):
@@ -79,14 +79,14 @@ def _full_size_samples(case, w, precision, tol_thermo, tol_wind):
             rows.append([float(x) for x in parts])
     S = np.array(rows)
     cols, levs = S[:, 0].astype(int), S[:, 1].astype(int)
-    say(f"[parity] full size {w.name} precision={precision}: autotune, 1 graph-replayed large step, "
+    say(f"[parity] full size {w.name} precision={precision}: autotune, {n_steps} graph-replayed large step(s), "
         f"{len(S)} samples")
     st = lib_state(w, precision)
     tuned = thor.thor_autotune(st.handle, w.n_acoustic)
     say(f"         tuned {tuned}")
     m0, rc = st.mass()
     assert rc == 0 and abs(m0 / mass[0] - 1) < 1e-13
-    st.step(1, w.n_acoustic)
+    st.step(n_steps, w.n_acoustic)
     got = {}
     for name in ("T", "u", "v", "w", "p", "rho"):
         f, rc = st.field(name)
@@ -110,7 +110,7 @@ def _full_size_samples(case, w, precision, tol_thermo, tol_wind):
 
 def test_gas_giant_g6_l32_full_size_samples_after_one_step():
     """The benchmark workload at full size (40962 columns x 32 levels)."""
-    _full_size_samples("g6l32", workloads.gas_giant_c2(), 0, TOL, TOL)
+    _full_size_samples("gas_giant_g6l32_one_step.txt", workloads.gas_giant_c2(), 0, TOL, TOL)
 
 
 # The oracle's grid and the host grid builder differ only through NumPy's
@@ -129,9 +129,22 @@ def test_gas_giant_g7_l48_full_size_samples_after_one_step(precision):
     leave relative errors of order 1e-7 in T, p and rho after a step
     (bounded as in the mixed-form tests)."""
     if precision == 0:
-        _full_size_samples("g7l48", workloads.gas_giant_c3(), 0, TOL, 10 * G7_AREA_DIFF)
+        _full_size_samples("gas_giant_g7l48_one_step.txt", workloads.gas_giant_c3(), 0, TOL, 10 * G7_AREA_DIFF)
     else:
-        _full_size_samples("g7l48", workloads.gas_giant_c3(), 1, 1e-6, 1e-2)
+        _full_size_samples("gas_giant_g7l48_one_step.txt", workloads.gas_giant_c3(), 1, 1e-6, 1e-2)
+
+
+def test_held_suarez_g5_l37_full_size_samples_after_one_step():
+    """The paper's Earth benchmark setup at its own size (10242 columns x 37
+    levels), autotuned (phase V may take the two-levels-per-lane mapping)."""
+    _full_size_samples("hs_g5l37_one_step.txt", workloads.held_suarez(glevel=5, n_lev=37), 0, TOL, TOL)
+
+
+def test_hot_jupiter_g5_l37_full_size_samples_after_two_steps():
+    """The paper's hot-Jupiter setup at its own size; it starts at rest, so
+    the winds compared are those of the second step."""
+    _full_size_samples("hj_g5l37_two_steps.txt", workloads.hot_jupiter(glevel=5, n_lev=37), 0, TOL, TOL,
+                       n_steps=2)
 
 
 def test_hot_jupiter_benchmark_forcing():
