@@ -5,6 +5,8 @@ of a full-size workload at seeded sample cells.
     python tests/golden/make_full_size_samples.py g7l48   # 163842 columns x 48 levels
     python tests/golden/make_full_size_samples.py hs_g5l37   # Held-Suarez, 10242 x 37
     python tests/golden/make_full_size_samples.py hj_g5l37   # hot Jupiter, 10242 x 37
+    python tests/golden/make_full_size_samples.py g6l32_fixer   # also _hydrostatic, _shallow,
+                                                                # _cubic: g6 L32 with a switch on
 
 Calls only `oracle/` (FP64 CPU; minutes for g6, longer for g7): the stored
 values are the oracle's, never the library's.  Output (named by out_name):
@@ -27,10 +29,23 @@ def _workload(case):
     import workloads
     return {"g6l32": workloads.gas_giant_c2, "g7l48": workloads.gas_giant_c3,
             "hs_g5l37": lambda: workloads.held_suarez(glevel=5, n_lev=37),
-            "hj_g5l37": lambda: workloads.hot_jupiter(glevel=5, n_lev=37)}[case]()
+            "hj_g5l37": lambda: workloads.hot_jupiter(glevel=5, n_lev=37),
+            "g6l32_fixer": lambda: _switched("energy_fixer", True),
+            "g6l32_hydrostatic": lambda: _switched("hydrostatic", True),
+            "g6l32_shallow": lambda: _switched("shallow", True),
+            "g6l32_cubic": lambda: _switched("lagrange_order", 3)}[case]()
 
 
-CASES = ("g6l32", "g7l48", "hs_g5l37", "hj_g5l37")
+def _switched(attr, value):
+    """The g6 L32 gas giant with one of its switches set."""
+    import workloads
+    w = workloads.gas_giant_c2()
+    setattr(w, attr, value)
+    return w
+
+
+CASES = ("g6l32", "g7l48", "hs_g5l37", "hj_g5l37",
+         "g6l32_fixer", "g6l32_hydrostatic", "g6l32_shallow", "g6l32_cubic")
 # the hot Jupiter starts at rest with no noise: its winds appear in the
 # second step, once the first step's relaxation has set up the day/night
 # contrast
@@ -38,7 +53,7 @@ N_STEPS = {"hj_g5l37": 2}
 
 
 def out_name(case):
-    if case in ("g6l32", "g7l48"):
+    if case.startswith(("g6l32", "g7l48")):
         return f"gas_giant_{case}_one_step.txt"
     return f"{case}_two_steps.txt" if N_STEPS.get(case, 1) == 2 else f"{case}_one_step.txt"
 

@@ -134,6 +134,24 @@ def test_gas_giant_g7_l48_full_size_samples_after_one_step(precision):
         _full_size_samples("gas_giant_g7l48_one_step.txt", workloads.gas_giant_c3(), 1, 1e-6, 1e-2)
 
 
+# g6 counterpart of G7_AREA_DIFF: the largest relative cell-area difference
+# between the oracle's grid and the host grid at g6
+G6_AREA_DIFF = 4.7e-11
+
+
+@pytest.mark.parametrize("attr,value", [("energy_fixer", True), ("hydrostatic", True), ("shallow", True),
+                                        ("lagrange_order", 3)])
+def test_gas_giant_g6_l32_switches_full_size_samples_after_one_step(attr, value):
+    """The benchmark workload with each of the switches the benchmark times
+    (energy fixer, hydrostatic, shallow, cubic vertical interpolation); the
+    wind bar is ten times the g6 grid difference, as at g7."""
+    w = workloads.gas_giant_c2()
+    setattr(w, attr, value)
+    name = {"energy_fixer": "fixer", "hydrostatic": "hydrostatic", "shallow": "shallow",
+            "lagrange_order": "cubic"}[attr]
+    _full_size_samples(f"gas_giant_g6l32_{name}_one_step.txt", w, 0, TOL, 10 * G6_AREA_DIFF)
+
+
 def test_held_suarez_g5_l37_full_size_samples_after_one_step():
     """The paper's Earth benchmark setup at its own size (10242 columns x 37
     levels), autotuned (phase V may take the two-levels-per-lane mapping)."""
