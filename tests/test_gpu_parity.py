@@ -108,9 +108,17 @@ def _full_size_samples(fname, w, precision, tol_thermo, tol_wind, n_steps=1):
     assert rc == 0 and abs(m1 / mass[1] - 1) < 1e-12
 
 
-def test_gas_giant_g6_l32_full_size_samples_after_one_step():
-    """The benchmark workload at full size (40962 columns x 32 levels)."""
-    _full_size_samples("gas_giant_g6l32_one_step.txt", workloads.gas_giant_c2(), 0, TOL, TOL)
+# the mixed form's bars, as in the mixed-form tests: FP32 horizontal
+# stencils leave relative errors of order 1e-7 in T, p and rho
+MIXED_THERMO, MIXED_WIND = 1e-6, 1e-2
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gas_giant_g6_l32_full_size_samples_after_one_step(precision):
+    """The benchmark workload at full size (40962 columns x 32 levels), FP64
+    and mixed."""
+    tol = (TOL, TOL) if precision == 0 else (MIXED_THERMO, MIXED_WIND)
+    _full_size_samples("gas_giant_g6l32_one_step.txt", workloads.gas_giant_c2(), precision, *tol)
 
 
 # The oracle's grid and the host grid builder differ only through NumPy's
@@ -131,7 +139,7 @@ def test_gas_giant_g7_l48_full_size_samples_after_one_step(precision):
     if precision == 0:
         _full_size_samples("gas_giant_g7l48_one_step.txt", workloads.gas_giant_c3(), 0, TOL, 10 * G7_AREA_DIFF)
     else:
-        _full_size_samples("gas_giant_g7l48_one_step.txt", workloads.gas_giant_c3(), 1, 1e-6, 1e-2)
+        _full_size_samples("gas_giant_g7l48_one_step.txt", workloads.gas_giant_c3(), 1, MIXED_THERMO, MIXED_WIND)
 
 
 # g6 counterpart of G7_AREA_DIFF: the largest relative cell-area difference
@@ -152,16 +160,21 @@ def test_gas_giant_g6_l32_switches_full_size_samples_after_one_step(attr, value)
     _full_size_samples(f"gas_giant_g6l32_{name}_one_step.txt", w, 0, TOL, 10 * G6_AREA_DIFF)
 
 
-def test_held_suarez_g5_l37_full_size_samples_after_one_step():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_held_suarez_g5_l37_full_size_samples_after_one_step(precision):
     """The paper's Earth benchmark setup at its own size (10242 columns x 37
-    levels), autotuned (phase V may take the two-levels-per-lane mapping)."""
-    _full_size_samples("hs_g5l37_one_step.txt", workloads.held_suarez(glevel=5, n_lev=37), 0, TOL, TOL)
+    levels), autotuned (phase V may take the two-levels-per-lane mapping),
+    FP64 and mixed."""
+    tol = (TOL, TOL) if precision == 0 else (MIXED_THERMO, MIXED_WIND)
+    _full_size_samples("hs_g5l37_one_step.txt", workloads.held_suarez(glevel=5, n_lev=37), precision, *tol)
 
 
-def test_hot_jupiter_g5_l37_full_size_samples_after_two_steps():
-    """The paper's hot-Jupiter setup at its own size; it starts at rest, so
-    the winds compared are those of the second step."""
-    _full_size_samples("hj_g5l37_two_steps.txt", workloads.hot_jupiter(glevel=5, n_lev=37), 0, TOL, TOL,
+@pytest.mark.parametrize("precision", [0, 1])
+def test_hot_jupiter_g5_l37_full_size_samples_after_two_steps(precision):
+    """The paper's hot-Jupiter setup at its own size, FP64 and mixed; it
+    starts at rest, so the winds compared are those of the second step."""
+    tol = (TOL, TOL) if precision == 0 else (MIXED_THERMO, MIXED_WIND)
+    _full_size_samples("hj_g5l37_two_steps.txt", workloads.hot_jupiter(glevel=5, n_lev=37), precision, *tol,
                        n_steps=2)
 
 
