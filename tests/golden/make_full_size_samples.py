@@ -7,6 +7,8 @@ of a full-size workload at seeded sample cells.
     python tests/golden/make_full_size_samples.py hj_g5l37   # hot Jupiter, 10242 x 37
     python tests/golden/make_full_size_samples.py g6l32_fixer   # also _hydrostatic, _shallow,
                                                                 # _cubic: g6 L32 with a switch on
+    python tests/golden/make_full_size_samples.py ensemble_member0_g6l48   # first planet of the
+                                                                           # 64-planet ensemble
 
 Calls only `oracle/` (FP64 CPU; minutes for g6, longer for g7): the stored
 values are the oracle's, never the library's.  Output (named by out_name):
@@ -33,7 +35,8 @@ def _workload(case):
             "g6l32_fixer": lambda: _switched("energy_fixer", True),
             "g6l32_hydrostatic": lambda: _switched("hydrostatic", True),
             "g6l32_shallow": lambda: _switched("shallow", True),
-            "g6l32_cubic": lambda: _switched("lagrange_order", 3)}[case]()
+            "g6l32_cubic": lambda: _switched("lagrange_order", 3),
+            "ensemble_member0_g6l48": lambda: workloads.ensemble()[0]}[case]()
 
 
 def _switched(attr, value):
@@ -45,7 +48,7 @@ def _switched(attr, value):
 
 
 CASES = ("g6l32", "g7l48", "hs_g5l37", "hj_g5l37",
-         "g6l32_fixer", "g6l32_hydrostatic", "g6l32_shallow", "g6l32_cubic")
+         "g6l32_fixer", "g6l32_hydrostatic", "g6l32_shallow", "g6l32_cubic", "ensemble_member0_g6l48")
 # the hot Jupiter starts at rest with no noise: its winds appear in the
 # second step, once the first step's relaxation has set up the day/night
 # contrast

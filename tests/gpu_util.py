@@ -62,3 +62,39 @@ def small_earth(glevel=3, n_lev=20, n_large=3, noise=0.1, seed=1):
     w.glevel, w.n_lev, w.n_large, w.noise_amp, w.seed = glevel, n_lev, n_large, noise, seed
     w.z_top = 36.0e3 * n_lev / 20
     return w
+
+
+def read_samples(fname):
+    """Stored oracle samples (tests/golden/<fname>, written by
+    make_full_size_samples.py): cols, levs, {field: values}, (mass0, mass1)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", fname)
+    rows, mass = [], None
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        parts = line.split()
+        if parts[0] == "mass":
+            mass = (float(parts[1]), float(parts[2]))
+        else:
+            rows.append([float(x) for x in parts])
+    S = np.array(rows)
+    ref = dict(zip(("T", "u", "v", "w", "p", "rho"), S[:, 2:].T))
+    return S[:, 0].astype(int), S[:, 1].astype(int), ref, mass
+
+
+def sample_errors(st, cols, levs, ref):
+    """Largest relative error of T, p, rho and largest wind error over the
+    samples' RMS speed, from a state's (or ensemble member's) fields."""
+    got = {}
+    for name in ("T", "u", "v", "w", "p", "rho"):
+        f, rc = st.field(name)
+        assert rc == 0, name
+        got[name] = f[cols, levs]
+    speed = np.sqrt(np.mean(ref["u"] ** 2 + ref["v"] ** 2 + ref["w"] ** 2))
+    errs = {}
+    for name in ("T", "p", "rho"):
+        errs[name] = float(np.max(np.abs(got[name] / ref[name] - 1)))
+    for name in ("u", "v", "w"):
+        errs[name] = float(np.max(np.abs(got[name] - ref[name])) / speed)
+    return errs

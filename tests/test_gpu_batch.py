@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import workloads
-from tests.gpu_util import say
+from tests.gpu_util import read_samples, sample_errors, say
 
 pytestmark = pytest.mark.gpu
 
@@ -91,3 +91,35 @@ def test_sixty_four_planet_ensemble():
         mass, rc = m.mass()
         assert rc == 0, ws[i].name
         assert abs(mass / m0[i] - 1) < 1e-13, ws[i].name
+
+
+def test_ensemble_member_at_full_size_matches_stored_oracle_samples():
+    """The 64-planet ensemble in the benchmark's launch configuration
+    (autotuned, one graph-replayed large step for all planets): its first
+    planet (g6, 40962 columns x 48 levels) against the oracle's stored
+    samples (tests/golden/ensemble_member0_g6l48_one_step.txt).  The wind
+    bar is ten times the largest relative cell-area difference between the
+    oracle's g6 grid and the host grid (4.7e-11), which the winds carry."""
+    from paper_1607_05535_amd import thor
+    ws = workloads.ensemble()
+    cols, levs, ref, mass = read_samples("ensemble_member0_g6l48_one_step.txt")
+    grids = _grids(ws)
+    members = []
+    for i, w in enumerate(ws):
+        pl, v, num, fo, ini = thor.structs_from_workload(w)
+        ini.planet_index = i
+        members.append((pl, v, num, fo, ini))
+    b = thor.Batch(grids, members)
+    tuned = b.autotune(8)
+    say(f"[batch] 64 planets, tuned {tuned}; member 0 {ws[0].name}")
+    m0, rc = b.members[0].mass()
+    assert rc == 0 and abs(m0 / mass[0] - 1) < 1e-13
+    b.step(1, 8)
+    errs = sample_errors(b.members[0], cols, levs, ref)
+    say(f"        max errors {errs}")
+    for k in ("T", "p", "rho"):
+        assert errs[k] < 1e-10, (k, errs[k])
+    for k in ("u", "v", "w"):
+        assert errs[k] < 10 * 4.7e-11, (k, errs[k])
+    m1, rc = b.members[0].mass()
+    assert rc == 0 and abs(m1 / mass[1] - 1) < 1e-12

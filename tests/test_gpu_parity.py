@@ -3,7 +3,8 @@ import numpy as np
 import pytest
 
 import workloads
-from tests.gpu_util import lib_fields, lib_state, oracle_fields, rel_errors, say, small_earth
+from tests.gpu_util import (lib_fields, lib_state, oracle_fields, read_samples, rel_errors, sample_errors, say,
+                             small_earth)
 
 pytestmark = pytest.mark.gpu
 
@@ -65,40 +66,17 @@ def _full_size_samples(fname, w, precision, tol_thermo, tol_wind, n_steps=1):
     large steps the sampled cells are compared with the oracle's stored
     values (tests/golden/<fname>, written by make_full_size_samples.py
     beside it from the oracle alone)."""
-    import os
     from paper_1607_05535_amd import thor
-    path = os.path.join(os.path.dirname(__file__), "golden", fname)
-    rows, mass = [], None
-    for line in open(path):
-        if line.startswith("#"):
-            continue
-        parts = line.split()
-        if parts[0] == "mass":
-            mass = (float(parts[1]), float(parts[2]))
-        else:
-            rows.append([float(x) for x in parts])
-    S = np.array(rows)
-    cols, levs = S[:, 0].astype(int), S[:, 1].astype(int)
+    cols, levs, ref, mass = read_samples(fname)
     say(f"[parity] full size {w.name} precision={precision}: autotune, {n_steps} graph-replayed large step(s), "
-        f"{len(S)} samples")
+        f"{len(cols)} samples")
     st = lib_state(w, precision)
     tuned = thor.thor_autotune(st.handle, w.n_acoustic)
     say(f"         tuned {tuned}")
     m0, rc = st.mass()
     assert rc == 0 and abs(m0 / mass[0] - 1) < 1e-13
     st.step(n_steps, w.n_acoustic)
-    got = {}
-    for name in ("T", "u", "v", "w", "p", "rho"):
-        f, rc = st.field(name)
-        assert rc == 0
-        got[name] = f[cols, levs]
-    ref = dict(zip(("T", "u", "v", "w", "p", "rho"), S[:, 2:].T))
-    speed = np.sqrt(np.mean(ref["u"] ** 2 + ref["v"] ** 2 + ref["w"] ** 2))
-    errs = {}
-    for name in ("T", "p", "rho"):
-        errs[name] = float(np.max(np.abs(got[name] / ref[name] - 1)))
-    for name in ("u", "v", "w"):
-        errs[name] = float(np.max(np.abs(got[name] - ref[name])) / speed)
+    errs = sample_errors(st, cols, levs, ref)
     say(f"         max errors {errs}")
     for k in ("T", "p", "rho"):
         assert errs[k] < tol_thermo, (k, errs[k])
