@@ -22,6 +22,8 @@ design notes are used:
     pentagons pad slot 6 with -1;
   * spring dynamics: tangent unit vectors, symplectic Euler, synchronous
     update of the hexagon points, stop when every point moved < tol;
+  * spring constant k = 100 (the paper gives none; with k = 1 the stopping
+    rule holds after the first step and nothing is relaxed);
   * centroid of a spherical polygon: nrm(sum_i nhat_i * theta_i) with theta_i
     the arc angle of edge i (the paper's printed arctangent is the
     complementary angle; the 1/(2 pi) factor vanishes in the normalisation);
@@ -205,7 +207,7 @@ def arc(a, b):
     return np.arctan2(np.sqrt(np.sum(c * c, axis=-1)), np.sum(a * b, axis=-1))
 
 
-def spring_dynamics(P, nbr, deg, g, k=1.0, beta=1.15, alpha=1.0, dt=0.01,
+def spring_dynamics(P, nbr, deg, g, k=100.0, beta=1.15, alpha=1.0, dt=0.01,
                     tol=1e-5, max_iter=100000):
     """Relax the hexagon points with damped springs; pentagons stay fixed.
 
@@ -271,7 +273,7 @@ class Grid:
       corner_tri[n,6]  index of the triangle at corner k of each cell
     """
 
-    def __init__(self, g, smooth=True, k=1.0, beta=1.15, alpha=1.0, dt=0.01,
+    def __init__(self, g, smooth=True, k=100.0, beta=1.15, alpha=1.0, dt=0.01,
                  tol=1e-5, max_iter=100000):
         self.g = g
         self.n = n_vertices(g)
