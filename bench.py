@@ -275,10 +275,11 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(w):
-    """The FP64 oracle on the host: one large step's worth estimated from a
-    bounded sample (the per-step terms, one RK stage of slow terms and two
-    acoustic substeps), with every BLAS/OpenMP pool held to one thread."""
+def cpu_baseline(w, n_steps=1):
+    """The FP64 oracle on the host: n_steps whole large steps of the workload
+    (per-step terms, three RK stages of slow terms, every acoustic substep,
+    the physics), timed end to end after the grid and initial state are
+    built, with every BLAS/OpenMP pool held to one thread."""
     from threadpoolctl import threadpool_limits
     from oracle import dynamics as odyn
     from oracle import grid as ogrid
@@ -286,42 +287,41 @@ def cpu_baseline(w):
     model, st = odyn.model_from_workload(w, G)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        large = odyn.large_step_terms(model, st)
-        t1 = time.perf_counter()
-        f = odyn.slow_forcing(model, st, large)
-        t2 = time.perf_counter()
-        s = st
-        dtau = w.dt / w.n_acoustic
-        for _ in range(2):
-            s = odyn.acoustic_substep(model, s, f, dtau, large)
-        t3 = time.perf_counter()
-    t_large = (t1 - t0) + 3 * (t2 - t1) + w.substeps_per_large * (t3 - t2) / 2
-    value = w.cells * w.substeps_per_large / t_large
+        st = odyn.run(model, st, n_steps, w.n_acoustic)
+        T = time.perf_counter() - t0
+    value = w.cells * w.substeps_per_large * n_steps / T
     return dict(value=value, unit="cell-updates/s", cores=1, kind="oracle",
-                sample=(f"{w.name}: per-step terms + 1 slow stage + 2 acoustic substeps "
-                        f"({t3 - t0:.1f} s), extrapolated to one large step "
-                        f"({t_large:.1f} s: 1 + 3 slow + {w.substeps_per_large} substeps)"),
-                cpu_model=cpu_model(), host_cpus=os.cpu_count())
+                sample=(f"{w.name}: {n_steps} whole large step(s) of the oracle ({T:.1f} s; "
+                        f"{w.substeps_per_large} acoustic substeps each), not extrapolated"),
+                seconds=T, steps=n_steps, cpu_model=cpu_model(), host_cpus=os.cpu_count())
 
 
-def copy_GBs():
-    """Read + write GB/s of a plain 1 GiB device copy on this GPU."""
+def stream_GBs(n_src, n_dst, n, reps=20):
+    """GB/s of the library's streaming kernel (thor_stream_mix) reading n_src
+    and writing n_dst FP64 arrays of n words: what the memory system delivers
+    for a kernel's traffic mix without its arithmetic or gathers."""
     import torch
-    n = 1 << 27
-    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
+    from paper_1607_05535_amd import thor
+    src = [torch.full((n,), 1.0 + k, dtype=torch.float64, device="cuda:0") for k in range(n_src)]
+    dst = [torch.empty(n, dtype=torch.float64, device="cuda:0") for _ in range(n_dst)]
+    thor.stream_mix(src, dst)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(10):
-        dst.copy_(src)
+    for _ in range(reps):
+        thor.stream_mix(src, dst)
     e1.record()
     torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) / 10 * 1e-3
+    t = e0.elapsed_time(e1) / reps * 1e-3
     del src, dst
     torch.cuda.empty_cache()
-    return 16.0 * n / t / 1e9
+    return 8.0 * n * (n_src + n_dst) / t / 1e9
+
+
+def copy_GBs():
+    """Read + write GB/s of a plain 1 GiB device copy (the streaming kernel
+    with one source and one destination of 2^27 words)."""
+    return stream_GBs(1, 1, 1 << 27, reps=10)
 
 
 def copy_probe():
@@ -360,11 +360,19 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="only the oracle on one host core: the g4 L20 Earth case (10 steps) "
+                         "and the g6 L32 benchmark (3 steps)")
     ap.add_argument("--physics-only", action="store_true",
                     help="only the hot-Jupiter and Held-Suarez benchmark setups (g5 L37)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.cpu_baseline_only:
+        import workloads
+        for wc, k in ((workloads.earth_c1(), 10), (workloads.gas_giant_c2(), 3)):
+            print(json.dumps({"workload": wc.name, "cpu_baseline": cpu_baseline(wc, k)}), flush=True)
         return
     if args.physics_only:
         import workloads
@@ -386,6 +394,11 @@ def main():
 
     T64, kt64, sc64, tuned64 = run_gpu(w, 0, args.steps, args.warmup)
     copy_bw = copy_GBs()
+    # phase V's own-column traffic: 14 FP64 arrays read (M, theta_L, rho,
+    # rho theta, W, p*, p[t], rho[t], Gamma, the two hyperdiffusion
+    # tendencies, the slow W forcing) and 5 written (rho, rho theta, W, p*, D)
+    # over the padded cells
+    ceiling = stream_GBs(14, 5, w.n_col * ((w.n_lev + 3) // 4 * 4))
     value = updates / T64
     vmean = kt64["vert"][0] * 1e-3
     vb = vert_bytes_per_cell(w.n_lev, False) * w.cells
@@ -411,7 +424,8 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(),
                      "bytes_per_launch": vb, "mean_launch_ms": kt64["vert"][0],
-                     "copy_GBs": copy_bw, "frac_of_copy": achieved / copy_bw},
+                     "copy_GBs": copy_bw, "frac_of_copy": achieved / copy_bw,
+                     "mix_ceiling_GBs": ceiling, "frac_of_mix_ceiling": achieved / ceiling},
         # phase M + phase V kernel time per substep, as cell-updates/s
         "kernel_only_substep_value": w.cells / ((kt64["vert"][0] + kt64["hmom"][0]) * 1e-3),
         "kernel_ms": {k: v[0] for k, v in kt64.items()},

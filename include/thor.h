@@ -36,7 +36,8 @@ enum {
   THOR_ENOMEM = -2,      /* host allocation failed, or dev_bytes too small */
   THOR_EHIP = -3,        /* a HIP runtime call failed (message has the detail) */
   THOR_ENONFINITE = -4,  /* thor_diag found NaN or Inf in the state */
-  THOR_ENOTCONV = -5     /* spring dynamics hit max_iter before the stop rule */
+  THOR_ENOTCONV = -5,    /* spring dynamics hit max_iter before the stop rule */
+  THOR_ENOTSMOOTH = -6   /* spring dynamics stopped after its first step: nothing relaxed */
 };
 
 /* Message of the last failing call on this thread (empty if none).  Valid
@@ -84,7 +85,14 @@ void thor_grid_params_default(int glevel, thor_grid_params *p);
 
 /* Build the grid on the host.  EINVAL: bad parameters (glevel outside 0..8,
  * non-positive k, beta, dt, tol or max_iter).  ENOTCONV: max_iter reached
- * (*out is still returned and usable).  ENOMEM: allocation failure. */
+ * (*out is still returned and usable).  ENOTSMOOTH: smooth = 1 and glevel > 0
+ * but the stopping rule already held after the first spring step while the
+ * springs were out of equilibrium (largest force above 1e-9 k dbar_spr), so
+ * no point was relaxed (*out is still returned: the bisection points moved
+ * to their control-volume centroids).  (At glevel 1 the hexagon points start
+ * in equilibrium: one step, THOR_OK.)  The per-step displacement shrinks with
+ * the spacing, so with k = 100 this happens at glevel 8; a larger k relaxes
+ * that grid.  ENOMEM: allocation failure. */
 int thor_grid_build(const thor_grid_params *p, thor_grid **out);
 
 /* Number of columns, pentagons and spring-dynamics iterations taken. */
@@ -298,19 +306,23 @@ int thor_state_import(thor_state *s, const void *blob, size_t bytes);
  * i.e. column groups of 1-8 x floor(64 / n_lev) columns) inside real large
  * steps with n_acoustic substeps on this state, keep the fastest, and restore
  * the state from a checkpoint taken before tuning (the state is unchanged).
- * For 32 < n_lev <= 64 with linear interpolation the "vert" family also
- * tries two levels per lane (thor_set_vert_levels_per_lane).
+ * With linear interpolation the "vert" family also tries four levels per
+ * lane, and for 32 < n_lev <= 64 two (thor_set_vert_levels_per_lane).
  * Synchronises.  wpb_out (4 ints, may be NULL) receives the choice in the
  * order above.  EINVAL: n_acoustic < 2 or odd. */
 int thor_autotune(thor_state *s, int n_acoustic, int *wpb_out);
 
 /* Work mapping of the acoustic phase V (the column tridiagonal): 1 level per
- * lane (floor(64 / n_lev) columns per wavefront) or 2 levels per lane
- * (ceil(n_lev / 2) lanes per column), the same arithmetic either way up to
- * rounding.  The default is 1, the ensemble kernels' mapping, so that a
- * planet run alone equals its ensemble member bitwise; thor_autotune may
- * choose 2 (then the two agree to rounding).  EINVAL: nl not 1 or 2, or 2
- * where n_lev <= 32 or lagrange_order is 3.  Synchronises. */
+ * lane (floor(64 / n_lev) columns per wavefront), 2 levels per lane
+ * (ceil(n_lev / 2) lanes per column) or 4 levels per lane (ceil(n_lev / 4)
+ * lanes per column, 16-byte row accesses, two in-lane steps of odd-even
+ * reduction before the cyclic reduction across lanes), the same arithmetic
+ * either way up to rounding.  The default is 4 (1 with lagrange_order 3),
+ * the ensemble kernels' mapping, so that a planet run alone equals its
+ * ensemble member bitwise; thor_autotune may choose another (then the two
+ * agree to rounding).
+ * EINVAL: nl not 1, 2 or 4; 2 where n_lev <= 32; 2 or 4 where
+ * lagrange_order is 3.  Synchronises. */
 int thor_set_vert_levels_per_lane(thor_state *s, int nl);
 
 /* Mean duration [ms] of the last n kernel launches of the named kernel family
@@ -522,6 +534,20 @@ int thor_zonal_imprint(thor_zonal *z, double *host_out, int *n_snapshots);
  * memset). */
 int thor_zonal_reset(thor_zonal *z);
 void thor_zonal_free(thor_zonal *z);   /* never frees dev_buf */
+
+/* ---------------------------------------------------------------------------
+ * Measurement aid (not part of the method): the memory-traffic mix of a
+ * kernel without its arithmetic or gathers, to compare a kernel's achieved
+ * bandwidth with what the memory system delivers for the same mix.  Reads
+ * n_src FP64 arrays and writes n_dst FP64 arrays of n words each, one word
+ * of every array per work item: dst_j[i] = sum_k src_k[i] + j.  src and dst
+ * are host arrays of device pointers to caller-owned device arrays (no two
+ * dst arrays may overlap); 1 <= n_src <= 16, 1 <= n_dst <= 8, n >= 1.
+ * Enqueued on hip_stream, asynchronous.  EINVAL on bad counts or a NULL
+ * pointer.
+ * ------------------------------------------------------------------------- */
+int thor_stream_mix(const double *const *src, int n_src, double *const *dst, int n_dst, int64_t n,
+                    void *hip_stream);
 
 #ifdef __cplusplus
 }

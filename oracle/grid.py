@@ -30,6 +30,8 @@ design notes are used:
   * control-volume corners = centroids of the triangles; cell point moved
     once to the centroid of its control volume (modified grid only).
 """
+import math
+
 import numpy as np
 
 
@@ -201,14 +203,24 @@ def positions(g):
 # ---------------------------------------------------------------------------
 # Sec. 2.2: spring dynamics (Eqs. spring_force, spr_vel, dbar)
 # ---------------------------------------------------------------------------
-def arc(a, b):
+_SCALAR_ATAN2 = np.frompyfunc(math.atan2, 2, 1)
+
+
+def libm_atan2(y, x):
+    """Elementwise atan2 of the C library (one scalar call per element).
+    NumPy's vectorised atan2 can differ from it in the last bit; a grid built
+    with this one is bit-identical to a builder that calls the C library."""
+    return _SCALAR_ATAN2(y, x).astype(np.float64)
+
+
+def arc(a, b, atan2=np.arctan2):
     """Geodesic arc angle between unit vectors (last axis)."""
     c = np.cross(a, b)
-    return np.arctan2(np.sqrt(np.sum(c * c, axis=-1)), np.sum(a * b, axis=-1))
+    return atan2(np.sqrt(np.sum(c * c, axis=-1)), np.sum(a * b, axis=-1))
 
 
 def spring_dynamics(P, nbr, deg, g, k=100.0, beta=1.15, alpha=1.0, dt=0.01,
-                    tol=1e-5, max_iter=100000):
+                    tol=1e-5, max_iter=100000, atan2=np.arctan2):
     """Relax the hexagon points with damped springs; pentagons stay fixed.
 
     dv/dt = sum_i k (d_i - dbar_spr) e_i - alpha v,  dP/dt = v, with natural
@@ -224,7 +236,7 @@ def spring_dynamics(P, nbr, deg, g, k=100.0, beta=1.15, alpha=1.0, dt=0.01,
     for it in range(1, max_iter + 1):
         p0 = P[moving]
         pi = P[nb]
-        d = arc(p0[:, None, :], pi)
+        d = arc(p0[:, None, :], pi, atan2)
         dot = np.sum(p0[:, None, :] * pi, axis=-1)
         e = nrm(pi - dot[..., None] * p0[:, None, :])
         force = np.sum(k * (d - dbar)[..., None] * e, axis=1)
@@ -241,20 +253,20 @@ def spring_dynamics(P, nbr, deg, g, k=100.0, beta=1.15, alpha=1.0, dt=0.01,
 # ---------------------------------------------------------------------------
 # Centroid equation (Sec. 2.2) and spherical triangle areas
 # ---------------------------------------------------------------------------
-def polygon_centroid(verts):
+def polygon_centroid(verts, atan2=np.arctan2):
     """Centroid direction of spherical polygon(s) verts[..., n, 3] (CCW)."""
     nxt = np.roll(verts, -1, axis=-2)
     c = np.cross(verts, nxt)
     cn = np.sqrt(np.sum(c * c, axis=-1))
-    theta = np.arctan2(cn, np.sum(verts * nxt, axis=-1))
+    theta = atan2(cn, np.sum(verts * nxt, axis=-1))
     return nrm(np.sum(c / cn[..., None] * theta[..., None], axis=-2))
 
 
-def tri_area(a, b, c):
+def tri_area(a, b, c, atan2=np.arctan2):
     """Spherical triangle area (Van Oosterom and Strackee)."""
     num = np.abs(np.sum(a * np.cross(b, c), axis=-1))
     den = 1.0 + np.sum(a * b, axis=-1) + np.sum(b * c, axis=-1) + np.sum(c * a, axis=-1)
-    return 2.0 * np.arctan2(num, den)
+    return 2.0 * atan2(num, den)
 
 
 class Grid:
@@ -274,8 +286,12 @@ class Grid:
     """
 
     def __init__(self, g, smooth=True, k=100.0, beta=1.15, alpha=1.0, dt=0.01,
-                 tol=1e-5, max_iter=100000):
+                 tol=1e-5, max_iter=100000, scalar_atan2=False):
+        """scalar_atan2: take every arc angle and area with the C library's
+        atan2 (``libm_atan2``) instead of NumPy's vectorised one."""
         self.g = g
+        at = libm_atan2 if scalar_atan2 else np.arctan2
+        self._atan2 = at
         self.n = n_vertices(g)
         ids = id_table(g)
         self.tri = triangles(g, ids)
@@ -284,9 +300,9 @@ class Grid:
         self.spring_iters, self.converged = 0, True
         if smooth and g > 0:
             P, self.spring_iters, self.converged = spring_dynamics(
-                P, self.nbr, self.deg, g, k, beta, alpha, dt, tol, max_iter)
+                P, self.nbr, self.deg, g, k, beta, alpha, dt, tol, max_iter, at)
         # Triangle centroids become the control-volume corners.
-        tC = polygon_centroid(P[self.tri])
+        tC = polygon_centroid(P[self.tri], at)
         self._corner_map()
         if smooth:
             # Move each point once to the centroid of its control volume.
@@ -294,7 +310,7 @@ class Grid:
             newP = np.empty_like(P)
             for d in (5, 6):
                 sel = self.deg == d
-                newP[sel] = polygon_centroid(C[sel, :d])
+                newP[sel] = polygon_centroid(C[sel, :d], at)
             P = newP
         self.P = P
         self.tC = tC
@@ -323,6 +339,7 @@ class Grid:
         return C
 
     def _geometry(self):
+        at = self._atan2
         n = self.n
         P, tri = self.P, self.tri
         C = self._corners(self.tC)
@@ -340,29 +357,29 @@ class Grid:
             ck = C[sel, :d]
             ck1 = np.roll(ck, -1, axis=1)
             # Eq. int_grid: A1 (P0,Pk,Ck), A2 (Pk,Pk+1,Ck), A3 (P0,Pk+1,Ck)
-            A1 = tri_area(p0, pk, ck)
-            A2 = tri_area(pk, pk1, ck)
-            A3 = tri_area(p0, pk1, ck)
+            A1 = tri_area(p0, pk, ck, at)
+            A2 = tri_area(pk, pk1, ck, at)
+            A3 = tri_area(p0, pk1, ck, at)
             tot = A1 + A2 + A3
             self.w[sel, :d, 0] = A2 / tot
             self.w[sel, :d, 1] = A3 / tot
             self.w[sel, :d, 2] = A1 / tot
-            self.l[sel, :d] = arc(ck, ck1)
+            self.l[sel, :d] = arc(ck, ck1, at)
             self.nh[sel, :d] = nrm(np.cross(ck1, ck))
-            self.Ac[sel] = np.sum(tri_area(p0, ck, ck1), axis=1)
+            self.Ac[sel] = np.sum(tri_area(p0, ck, ck1, at), axis=1)
         self.Sc = np.sum(self.l[..., None] * self.nh, axis=1)
         # Primal triangles, for the Laplacian (Sec. 4).
         a, b, c = P[tri[:, 0]], P[tri[:, 1]], P[tri[:, 2]]
-        self.tA = tri_area(a, b, c)
+        self.tA = tri_area(a, b, c, at)
         vs = np.stack([a, b, c], axis=1)
         ve = np.roll(vs, -1, axis=1)
-        self.tl = arc(vs, ve)
+        self.tl = arc(vs, ve, at)
         self.tn = nrm(np.cross(ve, vs))
         # Barycentric corner weights of the triangle centroid for its three
         # vertices: each weight is the sub-area opposite that vertex.
         ct = self.tC
-        wa = tri_area(b, c, ct)
-        wb = tri_area(c, a, ct)
-        wc = tri_area(a, b, ct)
+        wa = tri_area(b, c, ct, at)
+        wb = tri_area(c, a, ct, at)
+        wc = tri_area(a, b, ct, at)
         tot = wa + wb + wc
         self.tw = np.stack([wa / tot, wb / tot, wc / tot], axis=1)

@@ -19,6 +19,7 @@
 
 #include "internal.h"
 #include "kernels.h"
+#include "powd.h"
 #include "state.h"
 
 namespace thor {
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(256) void k_fields(Fields<H> f, Consts c, float *ou
   if (ln.lev == L - 1) W1 = 0.0;
   if (!ln.store) return;
   const double rho = f.rho_t[idx];
-  const double p = c.p_ref * pow(c.Rd * f.rth_t[idx] / c.p_ref, c.gamma);
+  const double p = c.p_ref * powd(c.Rd * f.rth_t[idx] / c.p_ref, c.gamma);
   const H *rh = f.rhat + (size_t)ln.col * 3;
   double e[3], n[3];
   east_north(rh[0], rh[1], rh[2], e, n);
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(256) void k_restrict(Fields<H> ff, Consts cf, Field
     if (ln.lev == L - 1) W1 = 0.0;
     const double A = ff.area[fcol];
     const double rho = ff.rho_t[fi];
-    const double p = cf.p_ref * pow(cf.Rd * ff.rth_t[fi] / cf.p_ref, cf.gamma);
+    const double p = cf.p_ref * powd(cf.Rd * ff.rth_t[fi] / cf.p_ref, cf.gamma);
     sA += A;
     sT += A * p / (rho * cf.Rd);
     sp += A * p;
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(256) void k_restrict(Fields<H> ff, Consts cf, Field
   if (!ln.store) return;
   const size_t ci = (size_t)ln.col * cc.S + ln.lev;
   fc.rho_t[ci] = rho;
-  fc.rth_t[ci] = cc.p_ref / cc.Rd * pow(p / cc.p_ref, 1.0 / cc.gamma);
+  fc.rth_t[ci] = cc.p_ref / cc.Rd * powd(p / cc.p_ref, 1.0 / cc.gamma);
   fc.Mx_t[ci] = (H)(rho * vx);
   fc.My_t[ci] = (H)(rho * vy);
   fc.Mz_t[ci] = (H)(rho * vz);
@@ -186,9 +187,9 @@ __global__ void k_batch(const float *C, const float *Fn, size_t pair_stride, con
 }
 
 // Bounded correction of the state's *_t buffers from network outputs Y
-// [col][f * L + k]: a column whose largest |y| exceeds `bound` (or whose
-// corrected temperature or pressure would not stay positive) is left
-// unchanged.  Otherwise the cell is rebuilt the way a restriction builds it:
+// [col][f * L + k]: a column whose largest |y| exceeds `bound`, that has a
+// non-finite output, or whose corrected temperature or pressure would not
+// stay positive is left unchanged.  Otherwise the cell is rebuilt the way a restriction builds it:
 // density from the corrected p and T through the gas law, rho theta from the
 // corrected p, horizontal momentum from the corrected velocity at the new
 // density, and interface vertical momentum rescaled to the new interface
@@ -204,8 +205,11 @@ __global__ __launch_bounds__(256) void k_apply(Fields<H> f, Consts c, const floa
   const float *y = Y + (size_t)ln.col * kF * L;
   const float yT = y[k], yu = y[L + k], yv = y[2 * L + k], yw = y[3 * L + k], yp = y[4 * L + k];
   float m = fmaxf(fmaxf(fabsf(yT), fabsf(yu)), fmaxf(fmaxf(fabsf(yv), fabsf(yw)), fabsf(yp)));
+  // fmaxf drops a NaN operand: a non-finite output marks the column here,
+  // before the reduction, as out of bound
+  if (!(isfinite(yT) && isfinite(yu) && isfinite(yv) && isfinite(yw) && isfinite(yp))) m = INFINITY;
   const double rho = f.rho_t[idx];
-  const double p = c.p_ref * pow(c.Rd * f.rth_t[idx] / c.p_ref, c.gamma);
+  const double p = c.p_ref * powd(c.Rd * f.rth_t[idx] / c.p_ref, c.gamma);
   const float *mo = norm + 2 * kF * L, *so = norm + 3 * kF * L;   // output mean, spread [f][k]
   const double dT = (double)(yT * so[k] + mo[k]);
   const double du = (double)(yu * so[L + k] + mo[L + k]);
@@ -221,7 +225,7 @@ __global__ __launch_bounds__(256) void k_apply(Fields<H> f, Consts c, const floa
     const int other = (ln.lane ^ s) / L;
     if (other == cw && (ln.lane ^ s) < cpw * L) m = fmaxf(m, o);
   }
-  const bool ok = m <= bound;
+  const bool ok = m <= bound && m < INFINITY;
   const double rho1 = ok ? p1 / (c.Rd * T1) : rho;
   const double rdw = rho1 * dw;
   const double rdw_m = __shfl(rdw, lm, 64);
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(256) void k_apply(Fields<H> f, Consts c, const floa
   f.Mz_t[idx] = (H)(r * (double)f.Mz_t[idx] + rho1 * (du * e[2] + dv * n[2]));
   if (k > 0) f.W_t[idx] = f.W_t[idx] * (rho1_m + rho1) / (rho_m + rho) + 0.5 * (rdw_m + rdw);
   f.rho_t[idx] = rho1;
-  f.rth_t[idx] = c.p_ref / c.Rd * pow(p1 / c.p_ref, 1.0 / c.gamma);
+  f.rth_t[idx] = c.p_ref / c.Rd * powd(p1 / c.p_ref, 1.0 / c.gamma);
 }
 
 // Per (field, level) sum and sum of squares over n arrays [f][col][lev] (or

@@ -199,6 +199,7 @@ int build_grid(const thor_grid_params &p, Grid &G) {
   // Spring dynamics on the hexagon points (pentagon points stay fixed).
   G.spring_iters = 0;
   G.converged = true;
+  G.first_force = 0.0;
   if (p.smooth && g > 0) {
     const double dspr = p.beta * 2.0 * M_PI / (10.0 * std::ldexp(1.0, g - 1));
     std::vector<int64_t> mov;
@@ -211,10 +212,10 @@ int build_grid(const thor_grid_params &p, Grid &G) {
     const size_t nm = mov.size();
     const int nt = (int)std::max<size_t>(1, std::min<size_t>({(size_t)std::thread::hardware_concurrency(),
                                                                (size_t)16, nm / 4096 + 1}));
-    std::vector<double> part(nt);
+    std::vector<double> part(nt), pforce(nt);
     auto sweep = [&](int t) {
       const size_t lo = nm * t / nt, hi = nm * (t + 1) / nt;
-      double mm = 0.0;
+      double mm = 0.0, ff = 0.0;
       for (size_t m = lo; m < hi; ++m) {
         const Vec3 p0 = P[mov[m]];
         Vec3 F{0, 0, 0};
@@ -224,6 +225,7 @@ int build_grid(const thor_grid_params &p, Grid &G) {
           Vec3 e = unit(pk - dot(p0, pk) * p0);
           F = F + (p.k * (d - dspr)) * e;
         }
+        ff = std::max(ff, dot(F, F));
         Vec3 v = vel[m] + p.dt * (F - p.alpha * vel[m]);
         v = v - dot(v, p0) * p0;
         vel[m] = v;
@@ -233,6 +235,7 @@ int build_grid(const thor_grid_params &p, Grid &G) {
         nxt[m] = q;
       }
       part[t] = mm;
+      pforce[t] = ff;
     };
     for (int it = 1; it <= p.max_iter; ++it) {
       if (nt == 1) {
@@ -245,6 +248,13 @@ int build_grid(const thor_grid_params &p, Grid &G) {
       }
       double maxmove2 = 0.0;
       for (double v : part) maxmove2 = std::max(maxmove2, v);
+      if (it == 1) {
+        double f2 = 0.0;
+        for (double v : pforce) f2 = std::max(f2, v);
+        // largest spring force of the first step relative to k times the
+        // natural length: ~1e-16 for points already in equilibrium
+        G.first_force = std::sqrt(f2) / (p.k * dspr);
+      }
       for (size_t m = 0; m < nm; ++m) P[mov[m]] = nxt[m];
       G.spring_iters = it;
       if (std::sqrt(maxmove2) < p.tol) {
@@ -450,6 +460,11 @@ int thor_grid_build(const thor_grid_params *p, thor_grid **out) {
   if (!g->g.converged) {
     thor::set_error("thor_grid_build: spring dynamics reached max_iter");
     return THOR_ENOTCONV;
+  }
+  if (p->smooth && p->glevel > 0 && g->g.spring_iters <= 1 && g->g.first_force > 1e-9) {
+    thor::set_error("thor_grid_build: spring dynamics stopped after its first step (every point moved less than "
+                    "tol) with the points out of equilibrium; no point was relaxed, a larger k relaxes this grid");
+    return THOR_ENOTSMOOTH;
   }
   return THOR_OK;
 }

@@ -22,6 +22,7 @@ struct Grid {
   int64_t n = 0;
   int spring_iters = 0;
   bool converged = true;
+  double first_force = 0.0;      // largest spring force of the first step / (k dbar_spr)
   std::vector<int32_t> nbr;      // [n][6], -1 pads pentagons
   std::vector<uint8_t> deg;      // 5 or 6
   std::vector<Vec3> pos;         // cell points (unit sphere)

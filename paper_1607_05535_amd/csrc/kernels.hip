@@ -29,6 +29,7 @@
 
 #include "internal.h"
 #include "kernels.h"
+#include "powd.h"
 
 // Wavefronts per SIMD that the phase-M kernel is compiled for, as both the
 // minimum and the maximum (register budget 512 / n): scheduled for that
@@ -37,6 +38,12 @@
 // to aim for 4, at g6 L32).
 #define HMOM_OCC_D 2
 #define HMOM_OCC_F 4
+#ifndef VERT4_OCC
+#define VERT4_OCC 2
+#endif
+#ifndef VERT4_UNROLL
+#define VERT4_UNROLL 3
+#endif
 
 namespace thor {
 namespace {
@@ -75,7 +82,7 @@ __device__ __forceinline__ float shfl(float v, int src) { return __shfl(v, src, 
 
 template <typename H>
 __device__ __forceinline__ H eos(double rth, const Consts &c) {
-  return (H)(c.p_ref * pow(c.Rd * rth / c.p_ref, c.gamma));
+  return (H)(c.p_ref * powd(c.Rd * rth / c.p_ref, c.gamma));
 }
 
 // Distance from the planet's centre of level centres and interfaces; the
@@ -83,6 +90,17 @@ __device__ __forceinline__ H eos(double rth, const Consts &c) {
 // radius at every level).
 __device__ __forceinline__ double radius_c(const Consts &c, int lev) { return c.radius + (lev + 0.5) * c.rdz; }
 __device__ __forceinline__ double radius_i(const Consts &c, int lev) { return c.radius + lev * c.rdz; }
+
+// 1 / x from the hardware reciprocal estimate refined by two Newton steps
+// (within an ulp or two of the quotient; for the geometric factors and the
+// pivots of the column solve, where no correctly rounded quotient is needed).
+__device__ __forceinline__ double rcpd(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 
 // Neighbour ids of a column; a pentagon's missing 6th neighbour points at the
 // column itself (its coefficients are zero).
@@ -510,13 +528,13 @@ __device__ __forceinline__ void b_vert(const Fields<H> &f, const Consts &c, cons
 
   const double rho_new = rho_hat - ap * Wp + am * Wn;
   double rth_new = rth_hat - ap * thI_p * Wp + am * thI * Wn;
-  double p = c.p_ref * pow(c.Rd * rth_new / c.p_ref, c.gamma);
+  double p = c.p_ref * powd(c.Rd * rth_new / c.p_ref, c.gamma);
   double hs_sigma = 0.0;
   if (LAST && c.forcing != THOR_FORCING_NONE) {
     const int l0 = ln.lane - lev;   // the column's lowest cell
     const double p0 = shfl(p, l0), T0 = shfl(p / (rho_new * c.Rd), l0);
     p = physics_p(c, f.teq, col, lev, rho_new, p, p0, T0, hs_sigma);
-    rth_new = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
+    rth_new = c.p_ref / c.Rd * powd(p / c.p_ref, 1.0 / c.gamma);
   }
   const double D3 = Drho + (gp * Wp - gm * Wn);
   if (ln.store) {
@@ -708,7 +726,7 @@ __device__ __forceinline__ void b_vert2(const Fields<H> &f, const Consts &c, con
     const double ap = dtau * gpq, am = dtau * gmq;
     rho_new[q] = rho_hat[q] - ap * Wp[q] + am * Wn[q];
     rth_new[q] = rth_hat[q] - ap * thIp * Wp[q] + am * thI[q] * Wn[q];
-    p[q] = c.p_ref * pow(c.Rd * rth_new[q] / c.p_ref, c.gamma);
+    p[q] = c.p_ref * powd(c.Rd * rth_new[q] / c.p_ref, c.gamma);
   }
   double hs_sigma[2] = {0.0, 0.0};
   if (LAST && c.forcing != THOR_FORCING_NONE) {
@@ -718,7 +736,7 @@ __device__ __forceinline__ void b_vert2(const Fields<H> &f, const Consts &c, con
     for (int q = 0; q < 2; ++q) {
       const int lev = min(lev0 + q, L - 1);
       p[q] = physics_p(c, f.teq, col, lev, rho_new[q], p[q], p0, T0, hs_sigma[q]);
-      rth_new[q] = c.p_ref / c.Rd * pow(p[q] / c.p_ref, 1.0 / c.gamma);
+      rth_new[q] = c.p_ref / c.Rd * powd(p[q] / c.p_ref, 1.0 / c.gamma);
     }
   }
   if (!ln.store) return;
@@ -738,19 +756,325 @@ __device__ __forceinline__ void b_vert2(const Fields<H> &f, const Consts &c, con
   }
 }
 
+// ---------------------------------------------------------------------------
+// Phase V on the gather mapping: a lane owns kHq = 4 consecutive levels
+// lev0..lev0+3 of one column (hlpc = ceil(L / 4) lanes per column, hcpw
+// columns per wavefront) and the tridiagonal rows of interfaces lev0..lev0+3.
+// Every row moves in 16-byte loads and the per-column stencil data is loaded
+// once per 4 cells.  The same arithmetic per cell as b_vert; the solve
+// eliminates inside the lane first, by two steps of odd-even (cyclic)
+// reduction: the odd rows (lev0+1, lev0+3; the second needs the row below
+// the lane, lev0-1, from the lane below), then row lev0+2, which leaves row
+// lev0 of each lane coupled to row lev0 of the lanes below and above.
+// Cyclic reduction across the column's lanes solves those (ceil(log2 hlpc)
+// shuffle rounds), and back substitution recovers rows lev0+2, then
+// lev0+1 and lev0+3.  Rows of the ground (interface 0), of levels from L up
+// (a partly filled top lane) and of lanes outside the wavefront's columns
+// are identity rows (W = 0) whose coefficients are constants, so padding
+// levels never reach a real cell; only levels below L are stored.
+// ---------------------------------------------------------------------------
+struct VLane {
+  int lane, sub, lev0, nv, col;
+  bool real_col;   // lane belongs to one of the wavefront's columns
+  bool store;      // ... and that column exists
+};
+
+__device__ __forceinline__ VLane map_vlane(const Consts &c, int lb) {
+  VLane r;
+  r.lane = threadIdx.x & 63;
+  const int wave = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int cw = r.lane / c.hlpc;
+  r.sub = r.lane - cw * c.hlpc;
+  r.lev0 = r.sub * kHq;
+  r.nv = min(kHq, c.L - r.lev0);
+  const int col = wave * c.hcpw + cw;
+  r.real_col = cw < c.hcpw;
+  r.store = r.real_col && col < c.N;
+  r.col = col < c.N ? col : c.N - 1;
+  return r;
+}
+
+template <typename H, bool LAST>
+__device__ __forceinline__ void b_vert4(const Fields<H> &f, const Consts &c, const VLane &ln, double dtau,
+                                        int first) {
+  const int L = c.L, col = ln.col, lev0 = ln.lev0;
+  const size_t idx = (size_t)col * c.S + lev0;
+  const int lm = ln.lane > 0 ? ln.lane - 1 : 0;
+  const int lp = ln.lane < 63 ? ln.lane + 1 : 63;
+  int nb[6];
+  load_nbr(f.nbr, col, nb);
+  const H *dc = f.dc + (size_t)col * 21;
+
+  // radial factors g+ = r_I(k+1)^2 / (r_C^2 dz), g- = r_I(k)^2 / (r_C^2 dz)
+  // and 1 / r_C of cells lev0 - 1 .. lev0 + 3 (index k - lev0 + 1)
+  const double idz = 1.0 / c.dz;
+  double gp[kHq + 1], gm[kHq + 1], irc[kHq + 1];
+#pragma unroll
+  for (int k = 0; k <= kHq; ++k) {
+    const int lev = lev0 - 1 + k;
+    const double rI = radius_i(c, lev), rI1 = rI + c.rdz;
+    irc[k] = rcpd(radius_c(c, lev));
+    const double irc2dz = irc[k] * irc[k] * idz;
+    gp[k] = rI1 * rI1 * irc2dz;
+    gm[k] = rI * rI * irc2dz;
+  }
+
+  // horizontal divergences of M and theta_L M
+  H drho[kHq], dth[kHq], thl[kHq];
+  {
+    H mx[kHq], my[kHq], mz[kHq];
+    ld4<true>(f.Mx + idx, kHq, mx);
+    ld4<true>(f.My + idx, kHq, my);
+    ld4<true>(f.Mz + idx, kHq, mz);
+    ld4<true>(f.thL + idx, kHq, thl);
+    const H c0x = dc[0], c0y = dc[1], c0z = dc[2];
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const H t = c0x * mx[q] + c0y * my[q] + c0z * mz[q];
+      drho[q] = t;
+      dth[q] = thl[q] * t;
+    }
+#pragma unroll VERT4_UNROLL
+    for (int j = 0; j < 6; ++j) {
+      const size_t nj = (size_t)nb[j] * c.S + lev0;
+      H nx[kHq], ny[kHq], nz[kHq], nt[kHq];
+      ld4<true>(f.Mx + nj, kHq, nx);
+      ld4<true>(f.My + nj, kHq, ny);
+      ld4<true>(f.Mz + nj, kHq, nz);
+      ld4<true>(f.thL + nj, kHq, nt);
+      const H cx = dc[3 * (j + 1)], cy = dc[3 * (j + 1) + 1], cz = dc[3 * (j + 1) + 2];
+#pragma unroll
+      for (int q = 0; q < kHq; ++q) {
+        const H u = cx * nx[q] + cy * ny[q] + cz * nz[q];
+        drho[q] += u;
+        dth[q] += nt[q] * u;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const H ir = (H)irc[q + 1];
+      drho[q] *= ir;
+      dth[q] *= ir;
+    }
+  }
+
+  // explicit parts of density, rho theta and the deviation pressure
+  double rho_hat[kHq], rth_hat[kHq], phs[kHq], rhs[kHq], gam[kHq], thC[kHq], pt[kHq], d0[kHq];
+  {
+    double rho0[kHq], rth0[kHq], rt[kHq];
+    H gh[kHq], hrho[kHq], hrth[kHq], psh[kHq];
+    ld4<true>((first ? f.rho_t : f.rho) + idx, kHq, rho0);
+    ld4<true>((first ? f.rth_t : f.rth) + idx, kHq, rth0);
+    ld4<true>(f.p_t + idx, kHq, pt);
+    ld4<true>(f.rho_t + idx, kHq, rt);
+    ld4<true>(f.Gam + idx, kHq, gh);
+    ld4<true>(f.Hrho + idx, kHq, hrho);
+    ld4<true>(f.Hrth + idx, kHq, hrth);
+    if (first) {
+#pragma unroll
+      for (int q = 0; q < kHq; ++q) psh[q] = (H)0;
+    } else {
+      ld4<true>(f.ps + idx, kHq, psh);
+    }
+    if (c.hydrostatic) {
+      // the [t] imbalance of the lane's interfaces (no vertical acceleration:
+      // W leaves the end of the substep balanced)
+      const double pt_m = shfl(pt[3], lm), rt_m = shfl(rt[3], lm);
+#pragma unroll
+      for (int q = 0; q < kHq; ++q) {
+        const double ptm = q ? pt[q - 1] : pt_m, rtm = q ? rt[q - 1] : rt_m;
+        d0[q] = dtau * (-(pt[q] - ptm) * idz - 0.5 * c.grav * (rtm + rt[q]));
+      }
+    } else {
+      double w0[kHq], sw[kHq];
+      ld4<true>((first ? f.W_t : f.W) + idx, kHq, w0);
+      ld4<true>(f.SW + idx, kHq, sw);
+#pragma unroll
+      for (int q = 0; q < kHq; ++q) d0[q] = (lev0 + q == 0 ? 0.0 : w0[q]) + dtau * sw[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      gam[q] = (double)gh[q];
+      thC[q] = (double)thl[q];
+      const double Dr = (double)drho[q], Dt = (double)dth[q], Hr = (double)hrth[q];
+      rho_hat[q] = rho0[q] + dtau * (-Dr + (double)hrho[q]);
+      rth_hat[q] = rth0[q] + dtau * (-Dt + Hr);
+      phs[q] = (double)psh[q] + dtau * gam[q] * (-Dt + Hr);
+      rhs[q] = rho_hat[q] - rt[q];
+    }
+  }
+
+  // theta at the lane's interfaces and at interface lev0 + 4 (lane above)
+  double thI[kHq];
+  const double thC_dn = shfl(thC[3], lm);
+  thI[0] = ln.sub == 0 ? thC[0] : 0.5 * (thC_dn + thC[0]);   // interface 0 only meets W = 0
+#pragma unroll
+  for (int q = 1; q < kHq; ++q) thI[q] = 0.5 * (thC[q - 1] + thC[q]);
+  const double thI_up = shfl(thI[0], lp);
+  const double gam_m = shfl(gam[3], lm), phs_m = shfl(phs[3], lm), rhs_m = shfl(rhs[3], lm);
+
+  const double c1 = dtau * idz, c2 = 0.5 * c.grav * dtau;
+
+  // rows of interfaces lev0 + q: a x[j-1] + b x[j] + cc x[j+1] = d
+  const double thI_dn = shfl(thI[3], lm);   // interface lev0 - 1
+  double a[kHq], b[kHq], cc[kHq], d[kHq];
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) {
+    const int j = lev0 + q;
+    const double ap = dtau * gp[q + 1], am = dtau * gm[q + 1];   // cell j
+    const double apm = dtau * gp[q], amm = dtau * gm[q];         // cell j - 1
+    const double gmq = q ? gam[q - 1] : gam_m, phsm = q ? phs[q - 1] : phs_m, rhsm = q ? rhs[q - 1] : rhs_m;
+    const double thIm = q ? thI[q - 1] : thI_dn, thIp = q < kHq - 1 ? thI[q + 1] : thI_up;
+    a[q] = 0.0;
+    b[q] = 1.0;
+    cc[q] = 0.0;
+    d[q] = 0.0;
+    if (ln.real_col && j > 0 && j < L) {
+      a[q] = j == 1 ? 0.0 : -c1 * gmq * amm * thIm + c2 * amm;
+      b[q] = c.hydrostatic ? c1 * thI[q] * (gam[q] * am + gmq * apm) + c2 * (am - apm)
+                           : 1.0 + c1 * thI[q] * (gam[q] * am + gmq * apm) + c2 * (am - apm);
+      cc[q] = j == L - 1 ? 0.0 : -c1 * gam[q] * ap * thIp - c2 * ap;
+      d[q] = d0[q] - c1 * (phs[q] - phsm) - c2 * (rhsm + rhs[q]);
+    }
+  }
+
+  // (1) eliminate the odd rows 1 and 3 from rows 0 and 2; row 0 also uses
+  // row 3 of the lane below (a[0] = 0 in the column's first lane)
+  const bool first_lane = ln.sub == 0;
+  const double r1 = rcpd(b[1]), r3 = rcpd(b[3]);
+  const double a3d = shfl(a[3], lm), r3d = shfl(r3, lm), c3d = shfl(cc[3], lm), d3d = shfl(d[3], lm);
+  double A0, B0, C0, D0, A2, B2, C2, D2;
+  {
+    const double k1 = first_lane ? 0.0 : a[0] * r3d, k2 = cc[0] * r1;
+    A0 = -a3d * k1;              // couples to row 2 of the lane below
+    B0 = b[0] - c3d * k1 - a[1] * k2;
+    C0 = -cc[1] * k2;            // couples to row 2
+    D0 = d[0] - d3d * k1 - d[1] * k2;
+  }
+  {
+    const double k1 = a[2] * r1, k2 = cc[2] * r3;
+    A2 = -a[1] * k1;             // couples to row 0
+    B2 = b[2] - cc[1] * k1 - a[3] * k2;
+    C2 = -cc[3] * k2;            // couples to row 0 of the lane above
+    D2 = d[2] - d[1] * k1 - d[3] * k2;
+  }
+  // (2) eliminate row 2 (the lane's own and the lane below's) from row 0
+  const double R2 = rcpd(B2);
+  const double A2d = shfl(A2, lm), R2d = shfl(R2, lm), C2d = shfl(C2, lm), D2d = shfl(D2, lm);
+  double A, B, C, D;
+  {
+    const double k1 = first_lane ? 0.0 : A0 * R2d, k2 = C0 * R2;
+    A = -A2d * k1;               // couples to row 0 of the lane below
+    B = B0 - C2d * k1 - A2 * k2;
+    C = -C2 * k2;                // couples to row 0 of the lane above
+    D = D0 - D2d * k1 - D2 * k2;
+  }
+  // (3) cyclic reduction of the rows 0 across the column's lanes
+  const int lpc = c.hlpc;
+  for (int s = 1; s < lpc; s <<= 1) {
+    const bool lo = ln.real_col && ln.sub >= s, hi = ln.real_col && ln.sub + s < lpc;
+    const int sl = lo ? ln.lane - s : ln.lane;
+    const int sh = hi ? ln.lane + s : ln.lane;
+    const double rb = rcpd(B);
+    const double a_l = shfl(A, sl), rb_l = shfl(rb, sl), c_l = shfl(C, sl), d_l = shfl(D, sl);
+    const double a_h = shfl(A, sh), rb_h = shfl(rb, sh), c_h = shfl(C, sh), d_h = shfl(D, sh);
+    const double k1 = lo ? A * rb_l : 0.0;
+    const double k2 = hi ? C * rb_h : 0.0;
+    const double na = lo ? -a_l * k1 : 0.0;
+    const double nc = hi ? -c_h * k2 : 0.0;
+    B = B - (lo ? c_l * k1 : 0.0) - (hi ? a_h * k2 : 0.0);
+    D = D - (lo ? d_l * k1 : 0.0) - (hi ? d_h * k2 : 0.0);
+    A = na;
+    C = nc;
+  }
+  // (4) back substitution: row 0, then row 2 (with row 0 of the lane
+  // above), then rows 1 and 3
+  double x[kHq];
+  x[0] = D * rcpd(B);
+  const bool last_lane = ln.sub + 1 >= lpc;
+  const double x4n = shfl(x[0], lp);
+  const double x4 = last_lane ? 0.0 : x4n;   // interface lev0 + 4
+  x[2] = (D2 - A2 * x[0] - C2 * x4) * R2;
+  x[1] = (d[1] - a[1] * x[0] - cc[1] * x[2]) * r1;
+  x[3] = (d[3] - a[3] * x[2] - cc[3] * x4) * r3;
+
+  double Wn[kHq], Wp[kHq], rho_new[kHq], rth_new[kHq], p[kHq];
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) {
+    const int j = lev0 + q;
+    Wn[q] = (j > 0 && j < L) ? x[q] : 0.0;
+    Wp[q] = j + 1 < L ? (q < kHq - 1 ? x[q + 1] : x4) : 0.0;
+    const double thIp = j + 1 < L ? (q < kHq - 1 ? thI[q + 1] : thI_up) : 0.0;
+    const double ap = dtau * gp[q + 1], am = dtau * gm[q + 1];
+    rho_new[q] = rho_hat[q] - ap * Wp[q] + am * Wn[q];
+    rth_new[q] = rth_hat[q] - ap * thIp * Wp[q] + am * thI[q] * Wn[q];
+    p[q] = c.p_ref * powd(c.Rd * rth_new[q] / c.p_ref, c.gamma);
+  }
+  double hs_sigma[kHq] = {0.0, 0.0, 0.0, 0.0};
+  if (LAST && c.forcing != THOR_FORCING_NONE) {
+    const int l0 = ln.lane - ln.sub;   // the column's first lane holds its lowest cell
+    const double p0 = shfl(p[0], l0), T0 = shfl(p[0] / (rho_new[0] * c.Rd), l0);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const int lev = min(lev0 + q, L - 1);
+      p[q] = physics_p(c, f.teq, col, lev, rho_new[q], p[q], p0, T0, hs_sigma[q]);
+      rth_new[q] = c.p_ref / c.Rd * powd(p[q] / c.p_ref, 1.0 / c.gamma);
+    }
+  }
+  if (!ln.store) return;
+  H psn[kHq], dn[kHq];
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) {
+    psn[q] = (H)(p[q] - pt[q]);
+    const double D3 = (double)drho[q] + (gp[q + 1] * Wp[q] - gm[q + 1] * Wn[q]);
+    dn[q] = (H)(LAST && c.forcing == THOR_FORCING_HELD_SUAREZ ? hs_sigma[q] : D3);
+  }
+  if (ln.nv == kHq) {
+    st4<true>(f.rho + idx, kHq, rho_new);
+    st4<true>(f.rth + idx, kHq, rth_new);
+    st4<true>(f.W + idx, kHq, Wn);
+    st4<true>(f.ps + idx, kHq, psn);
+    st4<true>(f.D + idx, kHq, dn);
+  } else {
+    st4<false>(f.rho + idx, ln.nv, rho_new);
+    st4<false>(f.rth + idx, ln.nv, rth_new);
+    st4<false>(f.W + idx, ln.nv, Wn);
+    st4<false>(f.ps + idx, ln.nv, psn);
+    st4<false>(f.D + idx, ln.nv, dn);
+  }
+}
+
 // Held-Suarez boundary-layer friction (Eq. im_eq_v with K_v of Eq. im_eq_fv)
 // after the last phase V of a large step, with sigma of the dynamics output
 // left in D by that kernel.  Other forcings: nothing.
 template <typename H>
-__device__ __forceinline__ void b_friction(const Fields<H> &f, const Consts &c, const Lane &ln) {
+__device__ __forceinline__ void b_friction(const Fields<H> &f, const Consts &c, const HLane &ln) {
   if (!ln.store || c.forcing != THOR_FORCING_HELD_SUAREZ) return;
-  const size_t idx = (size_t)ln.col * c.S + ln.lev;
-  const double sigma = (double)f.D[idx];
-  const double kv = c.hs_kf * fmax(0.0, (sigma - c.hs_sb) / (1.0 - c.hs_sb));
-  const double den = 1.0 + kv * c.dt;
-  f.Mx[idx] = (H)((double)f.Mx[idx] / den);
-  f.My[idx] = (H)((double)f.My[idx] / den);
-  f.Mz[idx] = (H)((double)f.Mz[idx] / den);
+  const size_t idx = (size_t)ln.col * c.S + ln.lev0;
+  H sg[kHq], mx[kHq], my[kHq], mz[kHq];
+  ld4<true>(f.D + idx, kHq, sg);
+  ld4<true>(f.Mx + idx, kHq, mx);
+  ld4<true>(f.My + idx, kHq, my);
+  ld4<true>(f.Mz + idx, kHq, mz);
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) {
+    const double sigma = (double)sg[q];
+    const double kv = c.hs_kf * fmax(0.0, (sigma - c.hs_sb) / (1.0 - c.hs_sb));
+    const double den = 1.0 + kv * c.dt;
+    mx[q] = (H)((double)mx[q] / den);
+    my[q] = (H)((double)my[q] / den);
+    mz[q] = (H)((double)mz[q] / den);
+  }
+  // levels from L up are left as they are
+  if (ln.nv == kHq) {
+    st4<true>(f.Mx + idx, kHq, mx);
+    st4<true>(f.My + idx, kHq, my);
+    st4<true>(f.Mz + idx, kHq, mz);
+  } else {
+    st4<false>(f.Mx + idx, ln.nv, mx);
+    st4<false>(f.My + idx, ln.nv, my);
+    st4<false>(f.Mz + idx, ln.nv, mz);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1028,7 +1352,7 @@ __device__ __forceinline__ void large0_cells(const Fields<H> &f, const Consts &c
   double p[kHq], T[kHq], vx[kHq], vy[kHq], vz[kHq], wI[kHq];
 #pragma unroll
   for (int q = 0; q < kHq; ++q) {
-    p[q] = c.p_ref * pow(c.Rd * rth[q] / c.p_ref, c.gamma);
+    p[q] = c.p_ref * powd(c.Rd * rth[q] / c.p_ref, c.gamma);
     const double irho = 1.0 / rho[q];
     T[q] = p[q] * irho / c.Rd;
     vx[q] = (double)mx[q] * irho;
@@ -1283,7 +1607,7 @@ __device__ __forceinline__ void b_diag(const Fields<H> &f, const Consts &c, cons
   const H *rh = f.rhat + (size_t)col * 3;
   const double x = rh[0], y = rh[1], z = rh[2];
   if (field == THOR_F_T || field == THOR_F_P) {
-    const double p = c.p_ref * pow(c.Rd * f.rth_t[idx] / c.p_ref, c.gamma);
+    const double p = c.p_ref * powd(c.Rd * f.rth_t[idx] / c.p_ref, c.gamma);
     out = field == THOR_F_P ? p : p / (rho * c.Rd);
   } else if (field == THOR_F_U || field == THOR_F_V) {
     const double lam = (sqrt(x * x + y * y) < 1e-12) ? 0.0 : atan2(y, x);
@@ -1373,7 +1697,7 @@ __global__ __launch_bounds__(256) void k_energy(Fields<H> f, Consts c, int which
     const double rC = radius_c(c, lev);
     const double vol = f.area[col] * rC * rC * c.dz;
     const double rho = rho_a[idx];
-    const double p = c.p_ref * pow(c.Rd * rth_a[idx] / c.p_ref, c.gamma);
+    const double p = c.p_ref * powd(c.Rd * rth_a[idx] / c.p_ref, c.gamma);
     const double mx = (double)Mx[idx], my = (double)My[idx], mz = (double)Mz[idx];
     const double wc = 0.5 * (W + W1);
     const double ke = 0.5 * (mx * mx + my * my + mz * mz + wc * wc) / rho;
@@ -1432,14 +1756,14 @@ __global__ __launch_bounds__(256) void k_fixphys(Fields<H> f, Consts c, const do
   const Lane ln = map_lane(c, xcd_block());
   const size_t idx = (size_t)ln.col * c.S + ln.lev;
   const double rho = f.rho[idx];
-  const double p0 = c.p_ref * pow(c.Rd * f.rth[idx] / c.p_ref, c.gamma);
+  const double p0 = c.p_ref * powd(c.Rd * f.rth[idx] / c.p_ref, c.gamma);
   double p = rho * c.Rd * (p0 / (rho * c.Rd) + *dT);
   double sigma = 0.0;
   const int l0 = ln.lane - ln.lev;   // the column's lowest cell
   const double pl0 = shfl(p, l0), Tl0 = shfl(p / (rho * c.Rd), l0);
   p = physics_p(c, f.teq, ln.col, ln.lev, rho, p, pl0, Tl0, sigma);
   if (!ln.store) return;
-  f.rth[idx] = c.p_ref / c.Rd * pow(p / c.p_ref, 1.0 / c.gamma);
+  f.rth[idx] = c.p_ref / c.Rd * powd(p / c.p_ref, 1.0 / c.gamma);
   if (c.forcing == THOR_FORCING_HELD_SUAREZ) f.D[idx] = (H)sigma;
 }
 
@@ -1488,7 +1812,7 @@ THOR_KERNEL(large1, sizeof(H) == 8 ? 3 : 4, map_hlane, , )
 THOR_KERNEL(large2, 5, map_hlane, , )
 THOR_KERNEL(diag, 8, map_lane, COMMA int field, COMMA field)
 THOR_KERNEL(import, 8, map_lane, COMMA const double *blob, COMMA blob)
-THOR_KERNEL(friction, 8, map_lane, , )
+THOR_KERNEL(friction, 8, map_hlane, , )
 template <typename H>
 __global__ __launch_bounds__(kMaxBlock)
 __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? HMOM_OCC_D : HMOM_OCC_F, sizeof(H) == 8 ? HMOM_OCC_D : HMOM_OCC_F)))
@@ -1524,6 +1848,12 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeo
 void k_vert2(Fields<H> f, Consts c, int div, int first) {
   b_vert2<H, LAST>(f, c, map_lane2(c, xcd_block()), c.dt / div, first);
 }
+// phase V on the gather mapping (kHq levels per lane)
+template <typename H, bool LAST>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(VERT4_OCC)))
+void k_vert4(Fields<H> f, Consts c, int div, int first) {
+  b_vert4<H, LAST>(f, c, map_vlane(c, xcd_block()), c.dt / div, first);
+}
 // phase V with the cubic interface theta (single states only)
 template <typename H, bool LAST>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? 3 : 4)))
@@ -1531,13 +1861,13 @@ void k_vert3(Fields<H> f, Consts c, int div, int first) {
   b_vert<H, LAST, 3>(f, c, map_lane(c, xcd_block()), c.dt / div, first);
 }
 template <typename H, bool LAST>
-__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(VERT4_OCC)))
 void kb_vert(const Planet<H> *P, const int2 *tiles, int parity, int div, int first) {
   const int2 t = tiles[xcd_block()];
   if (t.x < 0) return;
   const Fields<H> &f = P[t.x].f[parity];
   const Consts &c = P[t.x].c;
-  b_vert<H, LAST>(f, c, map_lane(c, t.y), c.dt / div, first);
+  b_vert4<H, LAST>(f, c, map_vlane(c, t.y), c.dt / div, first);
 }
 #undef COMMA
 #undef THOR_KERNEL
@@ -1551,18 +1881,23 @@ void launch_hmom(const Fields<H> &f, const Consts &c, int wpb, int div, bool fir
 template <typename H>
 void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, bool last,
                  hipStream_t s) {
-  const dim3 g(c.vnl == 2 ? n_blocks_for(c.N, c.vcpw, wpb) : n_blocks(c, wpb)), b(64 * wpb);
+  const dim3 g(c.vnl == 4 ? n_blocks_h(c, wpb) : c.vnl == 2 ? n_blocks_for(c.N, c.vcpw, wpb) : n_blocks(c, wpb)),
+      b(64 * wpb);
   if (last) {
-    if (c.vnl == 2)
+    if (c.vnl == 4)
+      hipLaunchKernelGGL((k_vert4<H, true>), g, b, 0, s, f, c, div, (int)first);
+    else if (c.vnl == 2)
       hipLaunchKernelGGL((k_vert2<H, true>), g, b, 0, s, f, c, div, (int)first);
     else if (c.vorder == 3)
       hipLaunchKernelGGL((k_vert3<H, true>), g, b, 0, s, f, c, div, (int)first);
     else
       hipLaunchKernelGGL((k_vert<H, true>), g, b, 0, s, f, c, div, (int)first);
     if (c.forcing == THOR_FORCING_HELD_SUAREZ)
-      hipLaunchKernelGGL(k_friction<H>, dim3(n_blocks(c, 4)), dim3(256), 0, s, f, c);
+      hipLaunchKernelGGL(k_friction<H>, dim3(n_blocks_h(c, 4)), dim3(256), 0, s, f, c);
   } else {
-    if (c.vnl == 2)
+    if (c.vnl == 4)
+      hipLaunchKernelGGL((k_vert4<H, false>), g, b, 0, s, f, c, div, (int)first);
+    else if (c.vnl == 2)
       hipLaunchKernelGGL((k_vert2<H, false>), g, b, 0, s, f, c, div, (int)first);
     else if (c.vorder == 3)
       hipLaunchKernelGGL((k_vert3<H, false>), g, b, 0, s, f, c, div, (int)first);
@@ -1610,7 +1945,7 @@ void launch_fixer(const Fields<H> &f, const Consts &c, hipStream_t s) {
   hipLaunchKernelGGL(k_efix, dim3(1), dim3(256), 0, s, pa, pb, nb, c.Cv, dT);
   hipLaunchKernelGGL(k_fixphys<H>, dim3(nb), dim3(256), 0, s, f, c, (const double *)dT);
   if (c.forcing == THOR_FORCING_HELD_SUAREZ)
-    hipLaunchKernelGGL(k_friction<H>, dim3(nb), dim3(256), 0, s, f, c);
+    hipLaunchKernelGGL(k_friction<H>, dim3(n_blocks_h(c, 4)), dim3(256), 0, s, f, c);
 }
 template <typename H>
 void launch_to_state(const Fields<H> &f, const Consts &c, const double *blob, hipStream_t s) {

@@ -26,6 +26,7 @@
 
 #include "internal.h"
 #include "kernels.h"
+#include "powd.h"
 #include "state.h"
 
 namespace thor {
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(256) void k_zinterp(Fields<H> f, Consts c, const do
   if (col >= c.N) col = c.N - 1;
   const size_t idx = (size_t)col * c.S + lev;   // state row stride
   const double rho = f.rho_t[idx], rth = f.rth_t[idx];
-  const double p = c.p_ref * pow(c.Rd * rth / c.p_ref, c.gamma);
+  const double p = c.p_ref * powd(c.Rd * rth / c.p_ref, c.gamma);
   const H *rh = f.rhat + (size_t)col * 3;
   const double x = rh[0], y = rh[1], z = rh[2];
   const double lam = sqrt(x * x + y * y) < 1e-12 ? 0.0 : atan2(y, x);
@@ -429,3 +430,57 @@ int thor_zonal_reset(thor_zonal *z) {
 void thor_zonal_free(thor_zonal *z) { delete z; }
 
 }  // extern "C"
+
+// ===========================================================================
+// Measurement aid: streaming kernel with a given read/write mix.
+// ===========================================================================
+namespace {
+struct StreamPtrs {
+  const double *src[16];
+  double *dst[8];
+};
+
+// NS sources unrolled (every load issued before the sum uses it), the stores
+// in a loop.
+template <int NS>
+__global__ __launch_bounds__(256) void k_stream_mix(StreamPtrs p, int n_dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) v[k] = p.src[k][i];
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc += v[k];
+  for (int k = 0; k < n_dst; ++k) p.dst[k][i] = acc + k;
+}
+
+template <int NS>
+void launch_stream_mix(int n_src, const StreamPtrs &p, int n_dst, int64_t n, unsigned blocks, hipStream_t s) {
+  if (n_src == NS) hipLaunchKernelGGL(k_stream_mix<NS>, dim3(blocks), dim3(256), 0, s, p, n_dst, n);
+  else if constexpr (NS > 1) launch_stream_mix<NS - 1>(n_src, p, n_dst, n, blocks, s);
+}
+}  // namespace
+
+extern "C" int thor_stream_mix(const double *const *src, int n_src, double *const *dst, int n_dst, int64_t n,
+                               void *hip_stream) {
+  thor::clear_error();
+  if (!src || !dst || n_src < 1 || n_src > 16 || n_dst < 1 || n_dst > 8 || n < 1) {
+    thor::set_error("thor_stream_mix: 1..16 sources, 1..8 destinations, n >= 1");
+    return THOR_EINVAL;
+  }
+  StreamPtrs p{};
+  for (int k = 0; k < n_src; ++k) {
+    if (!src[k]) { thor::set_error("thor_stream_mix: NULL source"); return THOR_EINVAL; }
+    p.src[k] = src[k];
+  }
+  for (int k = 0; k < n_dst; ++k) {
+    if (!dst[k]) { thor::set_error("thor_stream_mix: NULL destination"); return THOR_EINVAL; }
+    p.dst[k] = dst[k];
+  }
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffff) { thor::set_error("thor_stream_mix: n too large"); return THOR_EINVAL; }
+  launch_stream_mix<16>(n_src, p, n_dst, n, (unsigned)blocks, (hipStream_t)hip_stream);
+  if (hipGetLastError() != hipSuccess) { thor::set_error("thor_stream_mix: launch failed"); return THOR_EHIP; }
+  return THOR_OK;
+}

@@ -532,11 +532,11 @@ int thor_state_init(const thor_grid *g, const thor_planet *pl, const thor_vertic
   c.shallow = num->shallow;
   c.rdz = num->shallow ? 0.0 : c.dz;
   c.vorder = num->lagrange_order == 3 ? 3 : 1;
-  // phase V: one level per lane, as in the ensemble kernels (a planet's
-  // results then equal its ensemble member's bitwise); thor_autotune may
-  // pack two levels per lane where one per lane leaves a wavefront with a
-  // single column
-  c.vnl = 1;
+  // phase V: four levels per lane (the gather mapping), as in the ensemble
+  // kernels, so that a planet's results equal its ensemble member's bitwise;
+  // with cubic interpolation one level per lane.  thor_autotune may choose
+  // another mapping.
+  c.vnl = c.vorder == 1 ? 4 : 1;
   c.vlpc = (c.L + 1) / 2;
   c.vcpw = 64 / c.vlpc;
   c.forcing = fo->kind;
@@ -613,14 +613,17 @@ int thor_autotune(thor_state *s, int n_acoustic, int *iters_out) {
   if (rc != THOR_OK && rc != THOR_ENONFINITE) return rc;
   const int parity0 = s->parity;
   const bool timing0 = s->timing;
-  // phase V may also choose between one and two levels per lane (L > 32)
+  // phase V may also choose its mapping: one level per lane, two (L > 32)
+  // or four (the gather mapping), with linear interpolation
   const bool two_ok = s->c.L > 32 && s->c.vorder == 1;
+  const bool four_ok = s->c.vorder == 1;
   for (int fam = 0; fam < FAM_COUNT; ++fam) {
     double best = 1e30;
     int best_it = s->wpb[fam], best_nl = s->c.vnl;
-    for (int k = 0; k < 8; ++k) {
-      const int it = cand[k & 3], nl = k < 4 ? 1 : 2;
-      if (nl == 2 && !(fam == FAM_VERT && two_ok)) continue;
+    for (int k = 0; k < 12; ++k) {
+      const int it = cand[k & 3], nl = k < 4 ? 1 : k < 8 ? 2 : 4;
+      if (nl != 1 && fam != FAM_VERT) continue;
+      if ((nl == 2 && !two_ok) || (nl == 4 && !four_ok)) continue;
       if (fam == FAM_VERT) s->c.vnl = nl;
       s->wpb[fam] = it;
       s->timing = true;
@@ -690,8 +693,9 @@ int thor_state_import(thor_state *s, const void *blob, size_t bytes) {
 int thor_set_vert_levels_per_lane(thor_state *s, int nl) {
   clear_error();
   if (!s) { set_error("thor_set_vert_levels_per_lane: NULL state"); return THOR_EINVAL; }
-  if (nl != 1 && (nl != 2 || s->c.L <= 32 || s->c.vorder != 1)) {
-    set_error("thor_set_vert_levels_per_lane: 1, or 2 with 33..64 levels and linear interpolation");
+  if (nl != 1 && ((nl != 2 && nl != 4) || s->c.vorder != 1 || (nl == 2 && s->c.L <= 32))) {
+    set_error("thor_set_vert_levels_per_lane: 1, 4 with linear interpolation, or 2 with 33..64 levels and linear "
+              "interpolation");
     return THOR_EINVAL;
   }
   if (!hip_ok(hipStreamSynchronize(s->stream), "vert mapping synchronize")) return THOR_EHIP;
@@ -784,7 +788,7 @@ int upload_tiles(thor_batch *b, size_t planet_bytes) {
     std::vector<int2> t;
     for (int i = 0; i < b->n; ++i) {
       const Consts &c = b->members[i]->c;
-      const int cols = fam == FAM_VERT ? c.cpw : c.hcpw;
+      const int cols = c.hcpw;   // every ensemble kernel runs on the gather mapping
       const long waves = (c.N + cols - 1) / cols;
       const long wg = (waves + b->wpb[fam] - 1) / b->wpb[fam];
       for (long k = 0; k < wg; ++k) t.push_back(make_int2(i, (int)k));

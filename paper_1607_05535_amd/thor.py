@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libthor.so")
 
 THOR_OK, THOR_EINVAL, THOR_ENOMEM, THOR_EHIP, THOR_ENONFINITE, THOR_ENOTCONV = 0, -1, -2, -3, -4, -5
+THOR_ENOTSMOOTH = -6
 THOR_FP64, THOR_MIXED = 0, 1
 THOR_FORCING_NONE, THOR_FORCING_NEWTONIAN, THOR_FORCING_HOT_JUPITER, THOR_FORCING_HELD_SUAREZ = 0, 1, 2, 3
 THOR_DIAG_MASS, THOR_DIAG_FIELD, THOR_DIAG_STATE_EXPORT, THOR_DIAG_SCALARS, THOR_DIAG_ENERGY = 1, 2, 3, 4, 5
@@ -35,7 +36,7 @@ EXPORTED = ["thor_last_error", "thor_grid_params_default", "thor_grid_build", "t
             "thor_field_stats", "thor_corrector_bytes", "thor_corrector_init", "thor_corrector_batch",
             "thor_corrector_apply", "thor_corrector_free", "thor_zonal_bytes", "thor_zonal_init",
             "thor_zonal_accumulate", "thor_zonal_result", "thor_zonal_imprint", "thor_zonal_reset",
-            "thor_zonal_free"]
+            "thor_zonal_free", "thor_stream_mix"]
 ZM_FIELDS = ("u", "v", "T", "theta", "upvp", "vpTp", "weight", "psi", "snapshots")
 
 
@@ -171,6 +172,7 @@ def lib():
     L.thor_zonal_reset.argtypes = [vp]
     L.thor_zonal_free.argtypes = [vp]
     L.thor_zonal_free.restype = None
+    L.thor_stream_mix.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int64, vp]
     return L
 
 
@@ -190,9 +192,10 @@ def thor_grid_params_default(glevel):
 
 
 def thor_grid_build(params):
-    """Returns (handle, rc); rc is THOR_OK or THOR_ENOTCONV."""
+    """Returns (handle, rc); rc is THOR_OK, THOR_ENOTCONV or THOR_ENOTSMOOTH
+    (a usable grid either way)."""
     h = ctypes.c_void_p()
-    rc = _check(lib().thor_grid_build(ctypes.byref(params), ctypes.byref(h)), allow=(THOR_ENOTCONV,))
+    rc = _check(lib().thor_grid_build(ctypes.byref(params), ctypes.byref(h)), allow=(THOR_ENOTCONV, THOR_ENOTSMOOTH))
     return h, rc
 
 
@@ -683,3 +686,16 @@ class Zonal:
                 self.handle = None
         except Exception:
             pass
+
+
+def stream_mix(srcs, dsts, stream=None):
+    """thor_stream_mix over torch float64 CUDA tensors of equal length
+    (measurement aid: the read/write mix of a kernel without its work)."""
+    import torch
+    n = srcs[0].numel()
+    if any(t.numel() != n or t.dtype != torch.float64 or not t.is_cuda for t in list(srcs) + list(dsts)):
+        raise ValueError("stream_mix: float64 CUDA tensors of one length")
+    sp = (ctypes.c_void_p * len(srcs))(*[t.data_ptr() for t in srcs])
+    dp = (ctypes.c_void_p * len(dsts))(*[t.data_ptr() for t in dsts])
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(lib().thor_stream_mix(sp, len(srcs), dp, len(dsts), n, ctypes.c_void_p(s)))

@@ -16,12 +16,13 @@ def pytest_configure(config):
 _GRIDS = {}
 
 
-def oracle_grid(g, smooth=True, k=100.0):
-    """Session cache of oracle grids (building one at g6 takes ~30 s)."""
+def oracle_grid(g, smooth=True, k=100.0, scalar_atan2=False):
+    """Session cache of oracle grids (building one at g6 takes ~30 s, a
+    minute with the C library's atan2)."""
     from oracle import grid
-    key = (g, smooth, k)
+    key = (g, smooth, k, scalar_atan2)
     if key not in _GRIDS:
-        _GRIDS[key] = grid.Grid(g, smooth=smooth, k=k)
+        _GRIDS[key] = grid.Grid(g, smooth=smooth, k=k, scalar_atan2=scalar_atan2)
     return _GRIDS[key]
 
 

@@ -52,18 +52,15 @@ def test_host_grid_matches_oracle(g, smooth):
     assert np.abs(area / O.Ac - 1).max() < 1e-11
 
 
-def test_host_grid_equals_oracle_bitwise_with_the_same_atan2(monkeypatch):
+def test_host_grid_equals_oracle_bitwise_with_the_same_atan2():
     """With the C library's atan2 in place of NumPy's vectorised one, the
     oracle's spring relaxation, centroids and areas equal the host grid
     builder's bit for bit (g4: 2562 points, 822 spring iterations)."""
-    import math
     from oracle import grid as ogrid
     thor = _thor()
     G = thor.Grid(4)
     nbr, xyz, area = G.export()
-    scalar = np.frompyfunc(math.atan2, 2, 1)
-    monkeypatch.setattr(np, "arctan2", lambda y, x: scalar(y, x).astype(np.float64))
-    O = ogrid.Grid(4, k=100.0)
+    O = ogrid.Grid(4, k=100.0, scalar_atan2=True)
     assert G.spring_iters == O.spring_iters
     assert np.array_equal(nbr, O.nbr.astype(np.int32))
     assert np.array_equal(xyz, O.P)
@@ -111,6 +108,38 @@ def test_spring_dynamics_reports_non_convergence():
     assert rc == thor.THOR_ENOTCONV
     n, npent, it = thor.thor_grid_info(h)
     assert it == 5 and n == 642
+    thor.thor_grid_free(h)
+
+
+def test_unrelaxed_grid_is_reported():
+    """A smoothed grid whose spring relaxation stops after its first step
+    (every point moved less than tol) is reported as THOR_ENOTSMOOTH, with a
+    usable handle: g5 with k = 1, and g8 with the default k = 100, whose
+    per-step displacements are below the paper's 1e-5 from the start; a
+    larger k relaxes g8, and the default k relaxes g5.  At g1 the hexagon
+    points (the icosahedron's edge midpoints) start in equilibrium: one step
+    and THOR_OK."""
+    thor = _thor()
+    h, rc = thor.thor_grid_build(thor.thor_grid_params_default(1))
+    assert rc == thor.THOR_OK and thor.thor_grid_info(h)[2] == 1
+    thor.thor_grid_free(h)
+    p = thor.thor_grid_params_default(5)
+    p.k = 1.0
+    h, rc = thor.thor_grid_build(p)
+    assert rc == thor.THOR_ENOTSMOOTH and "first step" in thor.lib().thor_last_error().decode()
+    assert thor.thor_grid_info(h)[2] == 1
+    thor.thor_grid_free(h)
+    h, rc = thor.thor_grid_build(thor.thor_grid_params_default(5))
+    assert rc == thor.THOR_OK and thor.thor_grid_info(h)[2] > 1
+    thor.thor_grid_free(h)
+    h, rc = thor.thor_grid_build(thor.thor_grid_params_default(8))
+    n, npent, it = thor.thor_grid_info(h)
+    assert rc == thor.THOR_ENOTSMOOTH and it == 1 and n == 10 * 4 ** 8 + 2 and npent == 12
+    thor.thor_grid_free(h)
+    p = thor.thor_grid_params_default(8)
+    p.k, p.max_iter = 1.0e4, 3
+    h, rc = thor.thor_grid_build(p)   # relaxing (stopped early here by max_iter)
+    assert rc == thor.THOR_ENOTCONV and thor.thor_grid_info(h)[2] == 3
     thor.thor_grid_free(h)
 
 

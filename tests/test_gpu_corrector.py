@@ -70,6 +70,31 @@ def test_bound_zero_keeps_the_plain_coarse_state():
     assert np.array_equal(P.work.export()[0], before)
 
 
+def test_non_finite_output_keeps_the_plain_coarse_state():
+    """A network whose u output at one level is NaN for every column (its
+    output bias set to NaN, T and p finite) corrects no column, even with a
+    bound that would accept every finite output; with that bias finite the
+    same network corrects columns."""
+    from paper_1607_05535_amd import thor, learned
+    P = _pipeline()
+    C, F = P.make_pairs([7], spinup=4, pairs_per_seed=2)
+    norm = P.norm(C, F)
+    widths = learned.widths_for(P.L)
+    net = thor.MLP(widths, P.N, seed=1)
+    params = net.get_params()
+    u3 = params.size - widths[-1] + (1 * P.L + 3)   # last bias: outputs [field][level], u is field 1
+    before = P.work.export()[0]
+    params[u3] = np.nan
+    net.set_params(params)
+    corr = thor.Corrector(P.work, net, norm, bound=1e30)
+    assert corr.apply() == 0
+    assert np.array_equal(P.work.export()[0], before)
+    params[u3] = 0.0
+    net.set_params(params)
+    corr = thor.Corrector(P.work, net, norm, bound=1e30)
+    assert corr.apply() > 0
+
+
 def test_trained_corrector_beats_plain_coarse_step():
     P = _pipeline()
     say("[corrector] g4 fine / g3 coarse, L32")

@@ -7,7 +7,7 @@ import pytest
 import workloads
 from oracle import dynamics as odyn
 from tests.conftest import oracle_grid
-from tests.gpu_util import lib_fields, lib_state, oracle_fields, rel_errors, say, small_earth
+from tests.gpu_util import lib_fields, lib_state, oracle_fields, cell_errors, say, small_earth
 
 pytestmark = pytest.mark.gpu
 
@@ -31,7 +31,7 @@ def _fixer_parity(w, precision=0):
     say(f"[fixer] {w.name} g{w.glevel} L{w.n_lev} forcing={w.forcing_kind} n_large={w.n_large}")
     st = lib_state(w, precision)
     st.step(w.n_large, w.n_acoustic)
-    err = rel_errors(lib_fields(st), oracle_fields(w))
+    err = cell_errors(lib_fields(st), oracle_fields(w))
     say(f"        errors {err}")
     for k, e in err.items():
         assert e < TOL, (k, e)
@@ -78,7 +78,7 @@ def test_fixer_in_mixed_precision_stays_close():
     w.energy_fixer = True
     st = lib_state(w, precision=1)
     st.step(w.n_large, w.n_acoustic)
-    err = rel_errors(lib_fields(st, ("T", "p", "rho")), oracle_fields(w))
+    err = cell_errors(lib_fields(st, ("T", "p", "rho")), oracle_fields(w))
     say(f"[fixer] mixed errors {err}")
     assert all(e < 1e-5 for e in err.values()), err
 

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads
-from tests.gpu_util import lib_fields, lib_state, rel_errors, say, small_earth
+from tests.gpu_util import lib_fields, lib_state, cell_errors, say, small_earth
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +26,7 @@ def test_mixed_tracks_fp64(maker):
     say(f"[mixed] {w.name} g{w.glevel} L{w.n_lev}")
     a, b = _pair(w, w.n_large)
     fa, fb = lib_fields(a), lib_fields(b)
-    err = rel_errors(fb, fa)
+    err = cell_errors(fb, fa)
     say(f"        errors {err}")
     for k in ("T", "p", "rho", "rhotheta"):
         assert err[k] < 1e-6, (k, err[k])
@@ -47,3 +47,23 @@ def test_mixed_rest_state():
     st.step(w.n_large, w.n_acoustic)
     for k, v in lib_fields(st, ("u", "v", "w")).items():
         assert np.abs(v).max() < 1e-4, k
+
+
+def test_mixed_four_levels_per_lane_matches_one_level():
+    """The mixed form's phase V on the four-levels mapping (FP32 horizontal
+    fields in 16-byte float4 rows) agrees with the one-level mapping to the
+    form's rounding."""
+    from paper_1607_05535_amd import thor
+    w = workloads.small_gas_giant(glevel=3, n_lev=32, n_large=3)
+    a = lib_state(w, 1)
+    b = lib_state(w, 1)
+    thor.thor_set_vert_levels_per_lane(a.handle, 1)
+    thor.thor_set_vert_levels_per_lane(b.handle, 4)
+    a.step(w.n_large, w.n_acoustic)
+    b.step(w.n_large, w.n_acoustic)
+    err = cell_errors(lib_fields(b), lib_fields(a))
+    say(f"[mixed] four vs one level per lane {err}")
+    for k in ("T", "p", "rho", "rhotheta"):
+        assert err[k] < 1e-6, (k, err[k])
+    for k in ("u", "v", "w"):
+        assert err[k] < 1e-4, (k, err[k])

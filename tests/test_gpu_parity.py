@@ -3,12 +3,15 @@ import numpy as np
 import pytest
 
 import workloads
-from tests.gpu_util import (lib_fields, lib_state, oracle_fields, read_samples, rel_errors, sample_errors, say,
-                             small_earth)
+from tests.gpu_util import (cell_errors, lib_fields, lib_state, oracle_fields, read_samples, rounding_response,
+                             sample_errors, say, small_earth)
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-10   # relative L2 per field after the run (FP64 path)
+# FP64 path: largest cell error after the run (relative for T, p, rho and
+# rho theta; over the RMS speed for the winds); the oracle's grid is
+# bit-identical to the host grid, so every field keeps this bar
+TOL = 1e-10
 
 
 def _compare(w, tol=TOL, precision=0):
@@ -17,7 +20,7 @@ def _compare(w, tol=TOL, precision=0):
     st.step(w.n_large, w.n_acoustic)
     got = lib_fields(st)
     ref = oracle_fields(w)
-    err = rel_errors(got, ref)
+    err = cell_errors(got, ref)
     say(f"         errors {err}")
     for k, e in err.items():
         assert e < tol, (k, e)
@@ -60,7 +63,7 @@ def test_rest_state_stays_at_rest_on_gpu():
         assert np.abs(v).max() < 1e-8, k
 
 
-def _full_size_samples(fname, w, precision, tol_thermo, tol_wind, n_steps=1):
+def _full_size_samples(fname, w, precision, tol_thermo, tol_wind, n_steps=1, tol_w=None):
     """Full-size workload in the benchmark's launch configuration
     (autotuned workgroup sizes, graph replay of thor_step): after n_steps
     large steps the sampled cells are compared with the oracle's stored
@@ -81,7 +84,8 @@ def _full_size_samples(fname, w, precision, tol_thermo, tol_wind, n_steps=1):
     for k in ("T", "p", "rho"):
         assert errs[k] < tol_thermo, (k, errs[k])
     for k in ("u", "v", "w"):
-        assert errs[k] < tol_wind, (k, errs[k])
+        bar = tol_w if (k == "w" and tol_w is not None) else tol_wind
+        assert errs[k] < bar, (k, errs[k], bar)
     m1, rc = st.mass()
     assert rc == 0 and abs(m1 / mass[1] - 1) < 1e-12
 
@@ -99,15 +103,6 @@ def test_gas_giant_g6_l32_full_size_samples_after_one_step(precision):
     _full_size_samples("gas_giant_g6l32_one_step.txt", workloads.gas_giant_c2(), precision, *tol)
 
 
-# The oracle's grid and the host grid builder differ only through NumPy's
-# vectorised atan2 against the C library's (bit-identical otherwise, a CPU
-# test shows); the spring relaxation amplifies that to a largest relative
-# cell-area difference of 3.9e-10 at g7 (4.7e-11 at g6, where the winds
-# then differ by 6e-11 of the speed).  The winds after a step carry it; the
-# g7 wind bar is ten times that area difference.
-G7_AREA_DIFF = 3.9e-10
-
-
 @pytest.mark.parametrize("precision", [0, 1])
 def test_gas_giant_g7_l48_full_size_samples_after_one_step(precision):
     """The largest single-planet workload (163842 columns x 48 levels) in
@@ -115,27 +110,30 @@ def test_gas_giant_g7_l48_full_size_samples_after_one_step(precision):
     leave relative errors of order 1e-7 in T, p and rho after a step
     (bounded as in the mixed-form tests)."""
     if precision == 0:
-        _full_size_samples("gas_giant_g7l48_one_step.txt", workloads.gas_giant_c3(), 0, TOL, 10 * G7_AREA_DIFF)
+        _full_size_samples("gas_giant_g7l48_one_step.txt", workloads.gas_giant_c3(), 0, TOL, TOL)
     else:
         _full_size_samples("gas_giant_g7l48_one_step.txt", workloads.gas_giant_c3(), 1, MIXED_THERMO, MIXED_WIND)
-
-
-# g6 counterpart of G7_AREA_DIFF: the largest relative cell-area difference
-# between the oracle's grid and the host grid at g6
-G6_AREA_DIFF = 4.7e-11
 
 
 @pytest.mark.parametrize("attr,value", [("energy_fixer", True), ("hydrostatic", True), ("shallow", True),
                                         ("lagrange_order", 3)])
 def test_gas_giant_g6_l32_switches_full_size_samples_after_one_step(attr, value):
     """The benchmark workload with each of the switches the benchmark times
-    (energy fixer, hydrostatic, shallow, cubic vertical interpolation); the
-    wind bar is ten times the g6 grid difference, as at g7."""
+    (energy fixer, hydrostatic, shallow, cubic vertical interpolation)."""
     w = workloads.gas_giant_c2()
     setattr(w, attr, value)
     name = {"energy_fixer": "fixer", "hydrostatic": "hydrostatic", "shallow": "shallow",
             "lagrange_order": "cubic"}[attr]
-    _full_size_samples(f"gas_giant_g6l32_{name}_one_step.txt", w, 0, TOL, 10 * G6_AREA_DIFF)
+    tol_w = None
+    if attr == "hydrostatic":
+        # the hydrostatic form diagnoses W from a nearly cancelling balance:
+        # one large step of the oracle itself moves w by 4.7e-10 of the RMS
+        # speed when its initial state is perturbed by one ulp (stored
+        # measurement), so two correct FP64 implementations, whose roundings
+        # differ by a few such perturbations, cannot agree to 1e-10 there;
+        # the w bar is four times that response
+        tol_w = max(TOL, 4.0 * rounding_response("g6l32_hydrostatic")["w"][1])
+    _full_size_samples(f"gas_giant_g6l32_{name}_one_step.txt", w, 0, TOL, TOL, tol_w=tol_w)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -171,12 +169,12 @@ def test_held_suarez_forcing():
     _compare(w)
 
 
-@pytest.mark.parametrize("nl", [1, 2])
+@pytest.mark.parametrize("nl", [1, 2, 4])
 @pytest.mark.parametrize("case", ["held_suarez_37", "earth_48", "earth_33_hydrostatic"])
-def test_both_phase_v_mappings_above_32_levels(nl, case):
-    """One and two levels per lane in phase V (the autotuner chooses between
-    them for 33-64 levels): both match the oracle, with forcing in the last
-    substep and with the hydrostatic rows."""
+def test_phase_v_mappings_above_32_levels(nl, case):
+    """One, two and four levels per lane in phase V (the autotuner chooses
+    among them for 33-64 levels): each matches the oracle, with forcing in
+    the last substep and with the hydrostatic rows."""
     from paper_1607_05535_amd import thor
     if case == "held_suarez_37":
         w = workloads.held_suarez(glevel=3, n_lev=37, n_large=3, dt=3000.0, noise_amp=1.0)
@@ -189,7 +187,50 @@ def test_both_phase_v_mappings_above_32_levels(nl, case):
     st = lib_state(w)
     thor.thor_set_vert_levels_per_lane(st.handle, nl)
     st.step(w.n_large, w.n_acoustic)
-    err = rel_errors(lib_fields(st), oracle_fields(w))
+    err = cell_errors(lib_fields(st), oracle_fields(w))
+    say(f"         errors {err}")
+    for k, e in err.items():
+        assert e < TOL, (k, e)
+
+
+@pytest.mark.parametrize("n_lev", [1, 2, 3, 4, 5, 7, 13, 20, 32, 64])
+def test_phase_v_four_levels_per_lane(n_lev):
+    """Four levels per lane in phase V at every kind of level count: one lane
+    per column with identity rows above the top (1-4), a partly filled top
+    lane (5, 7, 13), 5 lanes x 12 columns (20), 8 x 8 (32), 16 x 4 (64)."""
+    from paper_1607_05535_amd import thor
+    w = small_earth(glevel=2, n_lev=n_lev, n_large=2)
+    say(f"[parity] {w.name} L{n_lev} phase V with 4 levels per lane")
+    st = lib_state(w)
+    thor.thor_set_vert_levels_per_lane(st.handle, 4)
+    st.step(w.n_large, w.n_acoustic)
+    err = cell_errors(lib_fields(st), oracle_fields(w))
+    say(f"         errors {err}")
+    for k, e in err.items():
+        assert e < TOL, (k, e)
+
+
+@pytest.mark.parametrize("case", ["gas_giant_32", "hot_jupiter_37", "hydrostatic_20", "no_damping_12"])
+def test_phase_v_four_levels_per_lane_with_forcing_and_switches(case):
+    """The four-levels mapping with Newtonian and hot-Jupiter relaxation in
+    the last substep, the hydrostatic rows, and without damping/diffusion."""
+    from paper_1607_05535_amd import thor
+    if case == "gas_giant_32":
+        w = workloads.small_gas_giant(glevel=3, n_lev=32, n_large=3)
+    elif case == "hot_jupiter_37":
+        w = workloads.hot_jupiter(glevel=3, n_lev=37, n_large=3, dt=2400.0, noise_amp=0.1)
+    elif case == "hydrostatic_20":
+        w = small_earth(glevel=3, n_lev=20, n_large=2, noise=1.0)
+        w.hydrostatic = True
+    else:
+        w = small_earth(glevel=3, n_lev=12, n_large=2)
+        w.div_damp = False
+        w.diff_D = 0.0
+    say(f"[parity] {w.name} ({case}) phase V with 4 levels per lane")
+    st = lib_state(w)
+    thor.thor_set_vert_levels_per_lane(st.handle, 4)
+    st.step(w.n_large, w.n_acoustic)
+    err = cell_errors(lib_fields(st), oracle_fields(w))
     say(f"         errors {err}")
     for k, e in err.items():
         assert e < TOL, (k, e)
@@ -198,9 +239,15 @@ def test_both_phase_v_mappings_above_32_levels(nl, case):
 def test_vert_mapping_argument_errors():
     from paper_1607_05535_amd import thor
     st = lib_state(small_earth(glevel=2, n_lev=20, n_large=1))
-    for nl in (0, 2, 3):
+    for nl in (0, 2, 3, 8):
         with pytest.raises(thor.ThorError, match="levels_per_lane"):
             thor.thor_set_vert_levels_per_lane(st.handle, nl)
+    w3 = small_earth(glevel=2, n_lev=20, n_large=1)
+    w3.lagrange_order = 3
+    st3 = lib_state(w3)
+    with pytest.raises(thor.ThorError, match="levels_per_lane"):
+        thor.thor_set_vert_levels_per_lane(st3.handle, 4)
+    thor.thor_set_vert_levels_per_lane(st.handle, 4)
     thor.thor_set_vert_levels_per_lane(st.handle, 1)
 
 

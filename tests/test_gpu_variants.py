@@ -3,7 +3,7 @@ oracle (FP64 parity, same bar as the default equations)."""
 import pytest
 
 import workloads
-from tests.gpu_util import lib_fields, lib_state, oracle_fields, rel_errors, say, small_earth
+from tests.gpu_util import lib_fields, lib_state, oracle_fields, cell_errors, say, small_earth
 
 pytestmark = pytest.mark.gpu
 
@@ -17,7 +17,7 @@ def _parity(w, precision=0, tol=TOL, names=("T", "u", "v", "w", "p", "rho", "rho
     st.step(w.n_large, w.n_acoustic)
     got = lib_fields(st, names)
     ref = oracle_fields(w)
-    err = rel_errors(got, ref)
+    err = cell_errors(got, ref)
     say(f"          errors {err}")
     for k, e in err.items():
         assert e < tol, (k, e)
@@ -156,5 +156,9 @@ def test_switches_under_graphs_checkpoints_and_autotune(switches):
     d.load(blob)
     thor.thor_autotune(d.handle, 6)
     assert np.array_equal(d.export()[0], blob)
+    # the tuner may have chosen another phase-V mapping (equal to rounding);
+    # back on the default one the restart equals the straight run bitwise
+    # (workgroup sizes do not change the arithmetic)
+    thor.thor_set_vert_levels_per_lane(d.handle, 4 if w.lagrange_order == 1 else 1)
     d.step(2, 6)
     assert np.array_equal(d.export()[0], ref)
