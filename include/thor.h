@@ -453,6 +453,20 @@ int thor_field_stats(const float *C, const float *Fn, int n_arrays, size_t strid
                      int n_lev, void *dev_scratch, size_t scratch_bytes, void *hip_stream,
                      double *mean_std_host);
 
+/* For callers that cannot allocate memory (serving loops and harnesses that
+ * forbid device allocations): thor_field_stats without the scratch argument
+ * and without any device or host allocation.  The partial sums live in a
+ * library-owned device array of 1 MiB per GPU (set up on the first call on
+ * a device, kept until the process ends); the arrays are reduced in groups
+ * that fit it (12 arrays at n_lev = 32) and summed on the device in
+ * thor_field_stats' order.  Every call on a GPU shares that array: calls
+ * that overlap on one GPU (other host threads, other streams) race.
+ * EINVAL as thor_field_stats; ENOMEM if one array's partial sums
+ * (320 n_lev doubles) do not fit (not for any n_lev that divides 256).
+ * Synchronises. */
+int thor_field_stats_noalloc(const float *C, const float *Fn, int n_arrays, size_t stride, int n_col,
+                             int n_lev, void *hip_stream, double *mean_std_host);
+
 /* A corrector of state s by network net (35 n_lev inputs, 5 n_lev outputs,
  * max_batch >= n_col; n_lev a multiple of 32; EINVAL otherwise; dev_buf
  * 256-byte aligned).  norm_host: 20 n_lev floats

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -283,6 +284,63 @@ bool ok_hip(hipError_t e, const char *what) {
   return false;
 }
 
+// Running sums of the allocation-free statistics: adds a group of arrays'
+// partial sums (k_stats layout, group-local array index) to sums[f][k][2]
+// in the order the host reduction of thor_field_stats uses (array, then
+// chunk), starting from zero for the first group.
+__global__ __launch_bounds__(256) void k_stats_accumulate(const double *partial, int n_group, int chunks, int L,
+                                                          double *sums, int first) {
+  for (int q = threadIdx.x; q < kF * L; q += blockDim.x) {
+    const int f = q / L, k = q % L;
+    double s1 = first ? 0.0 : sums[2 * q], s2 = first ? 0.0 : sums[2 * q + 1];
+    for (int a = 0; a < n_group; ++a)
+      for (int ch = 0; ch < chunks; ++ch) {
+        const size_t o = ((((size_t)a * kF + f) * chunks + ch) * L + k) * 2;
+        s1 += partial[o];
+        s2 += partial[o + 1];
+      }
+    sums[2 * q] = s1;
+    sums[2 * q + 1] = s2;
+  }
+}
+
+// Means and spreads [mean f k][spread f k] from the running sums.
+__global__ __launch_bounds__(256) void k_stats_finish(const double *sums, int L, double n, double *out) {
+  for (int q = threadIdx.x; q < kF * L; q += blockDim.x) {
+    const double mu = sums[2 * q] / n;
+    out[q] = mu;
+    out[kF * L + q] = sqrt(fmax(sums[2 * q + 1] / n - mu * mu, 0.0));
+  }
+}
+
+// Library-owned scratch of the allocation-free statistics: running sums
+// (2 kF 256 doubles), the result (2 kF 256), then the partial sums of as
+// many arrays as fit (320 n_lev doubles each).  One copy per GPU, kept until
+// the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kStatsScratch = 131072;   // doubles: 1 MiB
+constexpr size_t kStatsHead = 2 * 2 * kF * 256;
+static __device__ __align__(256) double stats_scratch[kStatsScratch];
+
+std::mutex g_stats_mu;
+double *g_stats_ptr[64] = {};
+
+// Device address of stats_scratch on the current device (looked up once per
+// device), or nullptr with the error set.
+double *stats_scratch_ptr() {
+  int dev = 0;
+  if (!ok_hip(hipGetDevice(&dev), "thor_field_stats_noalloc: current device")) return nullptr;
+  if (dev < 0 || dev >= 64) { set_error("thor_field_stats_noalloc: device index above 63"); return nullptr; }
+  std::lock_guard<std::mutex> lock(g_stats_mu);
+  if (!g_stats_ptr[dev]) {
+    void *p = nullptr;
+    if (!ok_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(stats_scratch)), "thor_field_stats_noalloc: scratch address"))
+      return nullptr;
+    g_stats_ptr[dev] = static_cast<double *>(p);
+  }
+  return g_stats_ptr[dev];
+}
+
 }  // namespace
 }  // namespace thor
 
@@ -465,6 +523,43 @@ int thor_field_stats(const float *C, const float *Fn, int n_arrays, size_t strid
       mean_std_host[f * L + k] = mu;
       mean_std_host[kF * L + f * L + k] = std::sqrt(std::max(s2 / n - mu * mu, 0.0));
     }
+  return THOR_OK;
+}
+
+int thor_field_stats_noalloc(const float *C, const float *Fn, int n_arrays, size_t stride, int n_col, int n_lev,
+                             void *hip_stream, double *mean_std_host) {
+  clear_error();
+  if (!C || !mean_std_host || n_arrays < 1 || n_col < 1 || n_lev < 1 || 256 % n_lev) {
+    set_error("thor_field_stats_noalloc: bad argument (n_lev must divide 256)");
+    return THOR_EINVAL;
+  }
+  const int chunks = 32;
+  const size_t per_array = (size_t)kF * chunks * n_lev * 2;
+  const size_t cap = (kStatsScratch - kStatsHead) / per_array;   // arrays per group
+  if (cap < 1) {
+    set_error("thor_field_stats_noalloc: one array's partial sums exceed the 1 MiB scratch");
+    return THOR_ENOMEM;
+  }
+  double *scr = stats_scratch_ptr();
+  if (!scr) return THOR_EHIP;
+  double *sums = scr, *result = scr + 2 * kF * 256, *partial = scr + kStatsHead;
+  hipStream_t st = (hipStream_t)hip_stream;
+  for (int a0 = 0; a0 < n_arrays; a0 += (int)cap) {
+    const int ng = (int)std::min<size_t>(cap, (size_t)(n_arrays - a0));
+    const float *Cg = C + (size_t)a0 * stride;
+    const float *Fg = Fn ? Fn + (size_t)a0 * stride : nullptr;
+    hipLaunchKernelGGL(k_stats, dim3(chunks, kF, ng), dim3(256), 0, st, Cg, Fg, stride, n_col, n_lev, partial, chunks);
+    hipLaunchKernelGGL(k_stats_accumulate, dim3(1), dim3(256), 0, st, (const double *)partial, ng, chunks, n_lev, sums,
+                       (int)(a0 == 0));
+  }
+  hipLaunchKernelGGL(k_stats_finish, dim3(1), dim3(256), 0, st, (const double *)sums, n_lev,
+                     (double)n_arrays * n_col, result);
+  if (!ok_hip(hipGetLastError(), "thor_field_stats_noalloc: launch") ||
+      !ok_hip(hipMemcpyAsync(mean_std_host, result, (size_t)2 * kF * n_lev * sizeof(double), hipMemcpyDeviceToHost,
+                             st),
+              "thor_field_stats_noalloc: copy") ||
+      !ok_hip(hipStreamSynchronize(st), "thor_field_stats_noalloc: synchronize"))
+    return THOR_EHIP;
   return THOR_OK;
 }
 

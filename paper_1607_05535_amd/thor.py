@@ -36,7 +36,7 @@ EXPORTED = ["thor_last_error", "thor_grid_params_default", "thor_grid_build", "t
             "thor_field_stats", "thor_corrector_bytes", "thor_corrector_init", "thor_corrector_batch",
             "thor_corrector_apply", "thor_corrector_free", "thor_zonal_bytes", "thor_zonal_init",
             "thor_zonal_accumulate", "thor_zonal_result", "thor_zonal_imprint", "thor_zonal_reset",
-            "thor_zonal_free", "thor_stream_mix"]
+            "thor_zonal_free", "thor_stream_mix", "thor_field_stats_noalloc"]
 ZM_FIELDS = ("u", "v", "T", "theta", "upvp", "vpTp", "weight", "psi", "snapshots")
 
 
@@ -173,6 +173,8 @@ def lib():
     L.thor_zonal_free.argtypes = [vp]
     L.thor_zonal_free.restype = None
     L.thor_stream_mix.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int64, vp]
+    L.thor_field_stats_noalloc.argtypes = [vp, vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, vp,
+                                           ctypes.POINTER(ctypes.c_double)]
     return L
 
 
@@ -608,6 +610,15 @@ def thor_field_stats(C, Fn, n_arrays, stride, n_col, n_lev):
                                   n_col, n_lev, scratch.data_ptr(), scratch.numel() * 8,
                                   torch.cuda.current_stream(C.device).cuda_stream,
                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out.reshape(2, 5, n_lev)
+
+
+def thor_field_stats_noalloc(C, Fn, n_arrays, stride, n_col, n_lev):
+    """thor_field_stats without caller scratch: array [2, 5, n_lev]."""
+    out = np.empty(10 * n_lev)
+    _check(lib().thor_field_stats_noalloc(C.data_ptr(), Fn.data_ptr() if Fn is not None else None, n_arrays,
+                                          stride, n_col, n_lev, torch.cuda.current_stream(C.device).cuda_stream,
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out.reshape(2, 5, n_lev)
 
 
