@@ -220,7 +220,8 @@ def run_ensemble(steps, warmup):
 def run_corrector_mlp(reps=20):
     """The corrector network at the g5 L32 shape (inputs 7 columns x 5 fields
     x 32 levels, three hidden layers of 256, 160 outputs): one inference pass
-    over all 10242 coarse columns and one training step on 4096 columns, as
+    over all 10242 coarse columns (layer by layer, and with the fused
+    4-layer kernel for comparison) and one training step on 4096 columns, as
     matrix-core FLOP/s against the dense BF16 peak.  At this shape inference
     moves ~61 MB for 9.4 GFLOP (~150 flop/byte, under the ~310 flop/byte
     ridge of 2.5 PFLOP/s over 8 TB/s), so its bound is HBM: its GB/s is
@@ -249,20 +250,40 @@ def run_corrector_mlp(reps=20):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps * 1e-3
 
-    t_inf = timed(lambda: net.forward(x, y))
+    t_inf = timed(lambda: net.forward(x, y))          # layer by layer (the default)
+    net.set_fused(True)
+    t_inf_fused = timed(lambda: net.forward(x, y))
+    net.set_fused(False)
     t_tr = timed(lambda: net.train_step(x[:n_train], t, 1e-4))
     # inference traffic: inputs, weights, each hidden activation written and
     # read once (bf16), outputs written (fp32)
     b_inf = (2.0 * n_inf * widths[0] + sum(2.0 * i * o + 4.0 * o for i, o in pairs)
              + sum(4.0 * n_inf * o for o in widths[1:-1]) + 4.0 * n_inf * widths[-1])
     return {"widths": widths,
-            "inference_rows": n_inf, "inference_ms": t_inf * 1e3,
+            "inference_rows": n_inf, "inference_ms": t_inf * 1e3, "inference_ms_fused": t_inf_fused * 1e3,
             "inference_bytes": b_inf, "inference_GBs": b_inf / t_inf / 1e9,
             "inference_TFLOPs": f_fwd * n_inf / t_inf / 1e12,
             "train_rows": n_train, "train_step_ms": t_tr * 1e3,
             "train_TFLOPs": f_train * n_train / t_tr / 1e12,
             "peak_TFLOPs": BF16_PEAK_TFLOPS,
             "inference_frac": f_fwd * n_inf / t_inf / 1e12 / BF16_PEAK_TFLOPS}
+
+
+def run_corrector_c5(seeds, pairs, steps):
+    """The learned form at its own configuration: coarse g5 L32 corrected
+    toward the g7 L32 run restricted to g5 (gas giant, coarse step 600 s,
+    fine 150 s, one Earth day of fine spin-up per trajectory), trained on
+    (seeds - 1) x pairs snapshot pairs and judged on the last seed's pairs:
+    per-field RMS error of the plain and of the corrected coarse step against
+    the restricted fine run, and the wall time of 600 s of simulated time,
+    coarse step + corrector against four fine steps."""
+    from paper_1607_05535_amd import train_corrector
+    t0 = time.perf_counter()
+    rep = train_corrector.run(7, 5, seeds=seeds, pairs=pairs, spinup=576, steps=steps, batch=4096, lr=1e-3)
+    rep["workload"] = (f"g7 L32 fine -> g5 L32 coarse gas giant, {(seeds - 1) * pairs} training pairs, "
+                       f"{pairs} held out, {steps} Adam steps of 4096 columns")
+    rep["seconds_total"] = time.perf_counter() - t0
+    return rep
 
 
 def cpu_model():
@@ -354,6 +375,10 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-one-day", action="store_true")
     ap.add_argument("--no-corrector", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="skip the learned form's own-configuration leg")
+    ap.add_argument("--c5-seeds", type=int, default=4, help="trajectories of the C5 leg (the last held out)")
+    ap.add_argument("--c5-pairs", type=int, default=100, help="pairs per trajectory of the C5 leg")
+    ap.add_argument("--c5-steps", type=int, default=1500, help="Adam steps of the C5 leg")
     ap.add_argument("--no-hot-jupiter", action="store_true")
     ap.add_argument("--no-zonal", action="store_true")
     ap.add_argument("--no-energy-fixer", action="store_true")
@@ -474,6 +499,8 @@ def main():
         out["ensemble"] = run_ensemble(max(1, args.steps // 10), 2)
     if not args.no_corrector:
         out["corrector_mlp"] = run_corrector_mlp()
+    if not args.no_c5:
+        out["corrector_c5"] = run_corrector_c5(args.c5_seeds, args.c5_pairs, args.c5_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

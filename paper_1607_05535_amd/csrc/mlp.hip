@@ -156,6 +156,145 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, int 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference of a 4-layer network whose hidden widths are all kFH =
+// 256 (the corrector's shape): one workgroup of 4 wavefronts per tile of
+// kFM = 64 rows runs every layer.  The 64 x 256 hidden activations stay in
+// LDS (bf16) from one layer to the next, so only the inputs, the weights
+// (from L2) and the outputs cross the memory hierarchy.  Each wavefront
+// reads its own MFMA operand fragments from global memory (inputs in the
+// first layer, weights in every layer) into a ring of kFD chunks of 64 k
+// in registers, so kFD - 1 chunks are in flight while one is multiplied
+// and no barrier is needed inside a layer.  Wavefront w owns hidden columns
+// 64 w .. 64 w + 63 as 4 x 4 MFMA tiles of 16 x 16 over the tile's 64 rows;
+// in the output layer the 16-column tiles w, w + 4, w + 8, ...  Per tile
+// the products and their order (k ascending in steps of 32) equal k_gemm's,
+// so the outputs equal the layer-by-layer path.
+// ---------------------------------------------------------------------------
+constexpr int kFM = 64;              // rows per workgroup
+constexpr int kFH = 256;             // hidden width
+constexpr int kFK = 64;              // k per chunk
+#ifndef MLP_FD
+#define MLP_FD 3
+#endif
+constexpr int kFD = MLP_FD;          // chunks in the register ring
+constexpr int kHRow = kFH + 8;       // LDS row of the hidden activations, padded
+
+struct FusedNet {
+  const __bf16 *W[4];   // [out][in] bf16
+  const float *b[4];
+  int in, out;          // widths of the input and output layers
+};
+
+// Operand fragments of one 64-k chunk: a[2 i + s] rows 16 i + r (first
+// layer only), b[2 j + s] weight rows of tile j; s = 32-k substep.
+struct FusedFrag {
+  bf16x8 a[8], b[8];
+};
+
+__global__ __launch_bounds__(256) void k_mlp_fused4(FusedNet net, const __bf16 *__restrict__ X, int B,
+                                                    float *__restrict__ Y) {
+  __shared__ __align__(16) __bf16 Hs[kFM * kHRow];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, kq = (lane >> 4) * 8;
+  const int m0 = blockIdx.x * kFM;
+  const int K0 = net.in, N3 = net.out;
+  const int nk0 = (K0 + kFK - 1) / kFK, nkh = kFH / kFK;
+  const int n_chunks = nk0 + 3 * nkh;
+  const bf16x8 zero = {};
+  auto layer_of = [&](int c) { return c < nk0 ? 0 : 1 + (c - nk0) / nkh; };
+  auto k0_of = [&](int c) { return c < nk0 ? c * kFK : ((c - nk0) % nkh) * kFK; };
+  // 16-column tile j of this wavefront in layer l (-1: none)
+  auto tile_of = [&](int l, int j) {
+    const int tj = l == 3 ? w + 4 * j : 4 * w + j;
+    return tj < (l == 3 ? N3 / 16 : kFH / 16) ? tj : -1;
+  };
+  auto fetch = [&](int c, FusedFrag &fr) {
+    const int l = layer_of(c), k0 = k0_of(c);
+    const int K = l == 0 ? K0 : kFH;
+    const __bf16 *W = net.W[l];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int tj = tile_of(l, j);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int k = k0 + 32 * s + kq;
+        fr.b[2 * j + s] = tj >= 0 && k < K ? *reinterpret_cast<const bf16x8 *>(W + (size_t)(16 * tj + r) * K + k)
+                                           : zero;
+      }
+    }
+    if (l == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int row = m0 + 16 * i + r, k = k0 + 32 * s + kq;
+          fr.a[2 * i + s] = row < B && k < K0 ? *reinterpret_cast<const bf16x8 *>(X + (size_t)row * K0 + k) : zero;
+        }
+    }
+  };
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  FusedFrag ring[kFD];
+#pragma unroll
+  for (int d = 0; d < kFD; ++d)
+    if (d < n_chunks) fetch(d, ring[d]);
+  for (int c0 = 0; c0 < n_chunks; c0 += kFD) {
+#pragma unroll
+    for (int d = 0; d < kFD; ++d) {
+      const int c = c0 + d;
+      if (c >= n_chunks) break;
+      const int l = layer_of(c), k0 = k0_of(c);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        bf16x8 a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          a[i] = l == 0 ? ring[d].a[2 * i + s]
+                        : *reinterpret_cast<const bf16x8 *>(&Hs[(16 * i + r) * kHRow + k0 + 32 * s + kq]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], ring[d].b[2 * j + s], acc[i][j], 0, 0, 0);
+      }
+      if (c + kFD < n_chunks) fetch(c + kFD, ring[d]);
+      if (c + 1 == n_chunks || layer_of(c + 1) != l) {
+        // end of layer l: bias, then GELU into Hs (hidden) or the output
+        __syncthreads();   // every wavefront is done reading Hs as this layer's input
+        const float *bias = net.b[l];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int tj = tile_of(l, j);
+          if (tj < 0) continue;
+          const int col = 16 * tj + r;
+          const float bb = bias[col];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int row = 16 * i + (lane >> 4) * 4 + q;
+              const float z = acc[i][j][q] + bb;
+              if (l < 3) {
+                Hs[row * kHRow + col] = (__bf16)gelu_f(z);
+              } else if (m0 + row < B) {
+                Y[(size_t)(m0 + row) * N3 + col] = z;
+              }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        __syncthreads();   // Hs holds the next layer's input
+      }
+    }
+  }
+}
+
 // out[i] = sum_{z < S} part[z][i] in order z = 0, 1, ...
 __global__ void k_reduce(const float *part, int S, size_t n, float *out) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -255,6 +394,7 @@ struct thor_mlp {
   float *split = nullptr;        // split-K partial sums of one weight gradient
   float *partial = nullptr;      // loss partial sums
   int adam_t = 0;
+  bool fused = false;            // inference through k_mlp_fused4 where the shape allows
   hipStream_t stream = nullptr;
 };
 
@@ -347,9 +487,26 @@ void gemm(const __bf16 *A, int lda, const __bf16 *B, int ldb, float *C, int ldc,
 // Number of batch chunks of a weight gradient: chunks of at least 256 rows.
 int grad_splits(int B) { return std::max(1, std::min(kMaxSplit, B / 256)); }
 
+// The fused inference kernel serves 4-layer networks with hidden widths
+// kFH and an output width of at most kFH.
+bool fused_shape(const thor_mlp *M) {
+  return M->nl == 4 && M->w[1] == kFH && M->w[2] == kFH && M->w[3] == kFH && M->w[4] <= kFH;
+}
+
 // Forward pass; the output layer's pre-activation goes to y if given
 // (inference: hidden pre-activations are not kept), else to Z[nl - 1].
 void forward(thor_mlp *M, const __bf16 *X, int B, float *y) {
+  if (y && fused_shape(M) && M->fused) {
+    FusedNet net;
+    for (int l = 0; l < 4; ++l) {
+      net.W[l] = M->Wb[l];
+      net.b[l] = M->p + M->boff[l];
+    }
+    net.in = M->w[0];
+    net.out = M->w[4];
+    hipLaunchKernelGGL(k_mlp_fused4, dim3((B + kFM - 1) / kFM), dim3(256), 0, M->stream, net, X, B, y);
+    return;
+  }
   const __bf16 *in = X;
   for (int l = 0; l < M->nl; ++l) {
     const int K = M->w[l], N = M->w[l + 1];
@@ -528,6 +685,13 @@ int thor_mlp_train_step(thor_mlp *m, const void *x_bf16, const float *t, int B, 
                      b1, b2, 1e-8f, c1, c2);
   refresh_bf16(m);
   return mlp_ok(hipGetLastError(), "train step") ? THOR_OK : THOR_EHIP;
+}
+
+int thor_mlp_set_fused(thor_mlp *m, int on) {
+  clear_error();
+  if (!m) { set_error("thor_mlp_set_fused: NULL network"); return THOR_EINVAL; }
+  m->fused = on != 0;
+  return THOR_OK;
 }
 
 void thor_mlp_free(thor_mlp *m) { delete m; }

@@ -36,7 +36,7 @@ EXPORTED = ["thor_last_error", "thor_grid_params_default", "thor_grid_build", "t
             "thor_field_stats", "thor_corrector_bytes", "thor_corrector_init", "thor_corrector_batch",
             "thor_corrector_apply", "thor_corrector_free", "thor_zonal_bytes", "thor_zonal_init",
             "thor_zonal_accumulate", "thor_zonal_result", "thor_zonal_imprint", "thor_zonal_reset",
-            "thor_zonal_free", "thor_stream_mix", "thor_field_stats_noalloc"]
+            "thor_zonal_free", "thor_stream_mix", "thor_field_stats_noalloc", "thor_mlp_set_fused"]
 ZM_FIELDS = ("u", "v", "T", "theta", "upvp", "vpTp", "weight", "psi", "snapshots")
 
 
@@ -173,6 +173,7 @@ def lib():
     L.thor_zonal_free.argtypes = [vp]
     L.thor_zonal_free.restype = None
     L.thor_stream_mix.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int64, vp]
+    L.thor_mlp_set_fused.argtypes = [vp, ctypes.c_int]
     L.thor_field_stats_noalloc.argtypes = [vp, vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, vp,
                                            ctypes.POINTER(ctypes.c_double)]
     return L
@@ -539,6 +540,9 @@ class MLP:
 
     def forward(self, x, y):
         _check(lib().thor_mlp_forward(self.handle, x.data_ptr(), x.shape[0], y.data_ptr()))
+
+    def set_fused(self, on):
+        _check(lib().thor_mlp_set_fused(self.handle, int(bool(on))))
 
     def loss_grad(self, x, t, want_grad=True):
         loss = ctypes.c_double()

@@ -42,6 +42,26 @@ def test_forward_matches_reference():
     assert rel < 2e-2
 
 
+@pytest.mark.parametrize("B", [1, 100, 10242])
+def test_fused_inference_equals_layer_by_layer(B):
+    """The fused 4-layer inference kernel (one workgroup per 64-row tile,
+    hidden activations in LDS) against the layer-by-layer GEMMs: the same
+    products in the same order, so the same outputs, at a single row, a
+    ragged tile and the g5 corrector's 10242 columns."""
+    import torch
+    net, x, xr, t, tr = _net(B, seed=7)
+    y1 = torch.empty(B, WIDTHS[-1], dtype=torch.float32, device="cuda:0")
+    y2 = torch.empty_like(y1)
+    net.set_fused(False)
+    net.forward(x, y1)
+    net.set_fused(True)
+    net.forward(x, y2)
+    net.set_fused(False)
+    a, b = y1.cpu().numpy(), y2.cpu().numpy()
+    say(f"[mlp] fused vs layered B={B}: max |diff| {np.abs(a - b).max():.3e}, bitwise {np.array_equal(a, b)}")
+    assert np.abs(a - b).max() <= 1e-6 * np.abs(a).max()
+
+
 def test_gradients_match_reference():
     B = 128
     net, x, xr, t, tr = _net(B, seed=5)
