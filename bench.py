@@ -211,9 +211,33 @@ def run_ensemble(steps, warmup):
         torch.cuda.synchronize()
         Ts += time.perf_counter() - t0
         del st
+    # the single-planet path on the ensemble's own level counts: the first g6
+    # member of each level count alone (autotuned, graph-replayed), and the
+    # rate the ensemble's cell mix would have if every planet ran at the rate
+    # of the g6 planet with its level count
+    rate_by_L = {}
+    for L in sorted({w.n_lev for w in ws}):
+        cand = [i for i, w in enumerate(ws) if w.n_lev == L and w.glevel == 6]
+        if not cand:
+            continue
+        i = cand[0]
+        st = thor.State(grids[6], *members[i])
+        thor.thor_autotune(st.handle, 8)
+        st.step(warmup, 8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.step(steps, 8)
+        torch.cuda.synchronize()
+        rate_by_L[L] = ws[i].cells * ws[i].substeps_per_large * steps / (time.perf_counter() - t0)
+        del st
+    same_mix = None
+    if all(w.n_lev in rate_by_L for w in ws):
+        same_mix = updates / sum(w.cells * w.substeps_per_large * steps / rate_by_L[w.n_lev] for w in ws)
     return {"value": updates / Tb, "unit": "cell-updates/s", "planets": len(ws),
             "cells": sum(w.cells for w in ws), "ms_per_step": Tb / steps * 1e3,
             "one_by_one_value": updates / Ts, "speedup_vs_one_by_one": Ts / Tb,
+            "single_g6_planet_value_by_levels": rate_by_L, "same_mix_single_planet_value": same_mix,
+            "vs_same_mix_single_planet": (updates / Tb) / same_mix if same_mix else None,
             "autotuned_wavefronts_per_workgroup": wpb}
 
 

@@ -37,7 +37,17 @@
 // (FP64: 33 us at 2 against 36 us at 3 and 43 us when the compiler is left
 // to aim for 4, at g6 L32).
 #define HMOM_OCC_D 2
+#ifndef HMOM_OCC_F
 #define HMOM_OCC_F 4
+#endif
+// Fields of k_large1's velocity/temperature Laplacians in flight together,
+// and its minimum wavefronts per SIMD in FP64.
+#ifndef LARGE1_FU
+#define LARGE1_FU 4
+#endif
+#ifndef LARGE1_OCC_D
+#define LARGE1_OCC_D 3
+#endif
 #ifndef VERT4_OCC
 #define VERT4_OCC 2
 #endif
@@ -1422,7 +1432,7 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
   }
   const double *vsrc[4] = {f.vx, f.vy, f.vz, f.T};
   double *vdst[4] = {f.Xvx, f.Xvy, f.Xvz, f.XT};
-#pragma unroll 1
+#pragma unroll LARGE1_FU
   for (int k = 0; k < 4; ++k) {
     double l[kHq];
     lap4<VEC>(vsrc[k], nb, lch, c.S, lev0, nv, idx, l);
@@ -1808,7 +1818,7 @@ __device__ __forceinline__ void b_import(const Fields<H> &f, const Consts &c, co
 #define COMMA ,
 THOR_KERNEL(slow, sizeof(H) == 8 ? 2 : 4, map_hlane, COMMA int from_t, COMMA from_t)
 THOR_KERNEL(large0, 4, map_hlane, , )
-THOR_KERNEL(large1, sizeof(H) == 8 ? 3 : 4, map_hlane, , )
+THOR_KERNEL(large1, sizeof(H) == 8 ? LARGE1_OCC_D : 4, map_hlane, , )
 THOR_KERNEL(large2, 5, map_hlane, , )
 THOR_KERNEL(diag, 8, map_lane, COMMA int field, COMMA field)
 THOR_KERNEL(import, 8, map_lane, COMMA const double *blob, COMMA blob)
