@@ -110,15 +110,20 @@ inline int n_blocks_h(const Consts &c, int wpb) { return n_blocks_for(c.N, c.hcp
 // Acoustic substeps take dtau = dt / div (div = 3 in stage 1, n otherwise);
 // first = first substep of an RK stage (restart from Phi[t], p* = 0);
 // last = final substep of the large step (the physics is applied there).
+// ev0 / ev1 (timing, may be null): events recorded by the dispatch itself
+// when the family's first kernel starts and its last kernel ends.
 template <typename H>
-void launch_hmom(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, hipStream_t s);
+void launch_hmom(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, hipStream_t s,
+                 hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename H>
 void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, bool last,
-                 hipStream_t s);
+                 hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename H>
-void launch_slow(const Fields<H> &f, const Consts &c, int wpb, bool from_t, hipStream_t s);
+void launch_slow(const Fields<H> &f, const Consts &c, int wpb, bool from_t, hipStream_t s,
+                 hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename H>
-void launch_large(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s);
+void launch_large(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s, hipEvent_t ev0 = nullptr,
+                  hipEvent_t ev1 = nullptr);
 template <typename H>
 void launch_diag_field(const Fields<H> &f, const Consts &c, int field, hipStream_t s);
 template <typename H>

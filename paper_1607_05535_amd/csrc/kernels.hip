@@ -23,6 +23,7 @@
 //   grad s = (1/r) sum_{j=1..6} c_j (s_j - s_0)            (Eq. grad; the curvature term
 //                                                           cancels the constant part)
 //   lap s = (1/r^2) sum_{j=1..6} l_j (s_j - s_0)           (Sec. 4 triangle-gradient form)
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -1884,54 +1885,68 @@ void kb_vert(const Planet<H> *P, const int2 *tiles, int parity, int div, int fir
 
 }  // namespace
 
+// One dispatch; with events (timing) they are recorded by the dispatch
+// itself, at the kernel's start and end.
+template <typename K, typename... Args>
+void dispatch(K kernel, dim3 g, dim3 b, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kernel, g, b, 0, s, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, g, b, 0, s, args...);
+}
+
 template <typename H>
-void launch_hmom(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, hipStream_t s) {
-  hipLaunchKernelGGL(k_hmom<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c, div, (int)first);
+void launch_hmom(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, hipStream_t s, hipEvent_t ev0,
+                 hipEvent_t ev1) {
+  dispatch(k_hmom<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), s, ev0, ev1, f, c, div, (int)first);
 }
 template <typename H>
-void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, bool last,
-                 hipStream_t s) {
+void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool first, bool last, hipStream_t s,
+                 hipEvent_t ev0, hipEvent_t ev1) {
   const dim3 g(c.vnl == 4 ? n_blocks_h(c, wpb) : c.vnl == 2 ? n_blocks_for(c.N, c.vcpw, wpb) : n_blocks(c, wpb)),
       b(64 * wpb);
+  const bool fr = last && c.forcing == THOR_FORCING_HELD_SUAREZ;
+  hipEvent_t e1 = fr ? nullptr : ev1;   // with the friction kernel, the family ends with it
   if (last) {
     if (c.vnl == 4)
-      hipLaunchKernelGGL((k_vert4<H, true>), g, b, 0, s, f, c, div, (int)first);
+      dispatch(k_vert4<H, true>, g, b, s, ev0, e1, f, c, div, (int)first);
     else if (c.vnl == 2)
-      hipLaunchKernelGGL((k_vert2<H, true>), g, b, 0, s, f, c, div, (int)first);
+      dispatch(k_vert2<H, true>, g, b, s, ev0, e1, f, c, div, (int)first);
     else if (c.vorder == 3)
-      hipLaunchKernelGGL((k_vert3<H, true>), g, b, 0, s, f, c, div, (int)first);
+      dispatch(k_vert3<H, true>, g, b, s, ev0, e1, f, c, div, (int)first);
     else
-      hipLaunchKernelGGL((k_vert<H, true>), g, b, 0, s, f, c, div, (int)first);
-    if (c.forcing == THOR_FORCING_HELD_SUAREZ)
-      hipLaunchKernelGGL(k_friction<H>, dim3(n_blocks_h(c, 4)), dim3(256), 0, s, f, c);
+      dispatch(k_vert<H, true>, g, b, s, ev0, e1, f, c, div, (int)first);
+    if (fr) dispatch(k_friction<H>, dim3(n_blocks_h(c, 4)), dim3(256), s, nullptr, ev1, f, c);
   } else {
     if (c.vnl == 4)
-      hipLaunchKernelGGL((k_vert4<H, false>), g, b, 0, s, f, c, div, (int)first);
+      dispatch(k_vert4<H, false>, g, b, s, ev0, ev1, f, c, div, (int)first);
     else if (c.vnl == 2)
-      hipLaunchKernelGGL((k_vert2<H, false>), g, b, 0, s, f, c, div, (int)first);
+      dispatch(k_vert2<H, false>, g, b, s, ev0, ev1, f, c, div, (int)first);
     else if (c.vorder == 3)
-      hipLaunchKernelGGL((k_vert3<H, false>), g, b, 0, s, f, c, div, (int)first);
+      dispatch(k_vert3<H, false>, g, b, s, ev0, ev1, f, c, div, (int)first);
     else
-      hipLaunchKernelGGL((k_vert<H, false>), g, b, 0, s, f, c, div, (int)first);
+      dispatch(k_vert<H, false>, g, b, s, ev0, ev1, f, c, div, (int)first);
   }
 }
 template <typename H>
-void launch_slow(const Fields<H> &f, const Consts &c, int wpb, bool from_t, hipStream_t s) {
+void launch_slow(const Fields<H> &f, const Consts &c, int wpb, bool from_t, hipStream_t s, hipEvent_t ev0,
+                 hipEvent_t ev1) {
   const dim3 g(n_blocks_h(c, wpb)), b(64 * wpb);
   if (c.vorder == 3 && c.shallow)
-    hipLaunchKernelGGL((k_slow_var<H, true, 3>), g, b, 0, s, f, c, (int)from_t);
+    dispatch(k_slow_var<H, true, 3>, g, b, s, ev0, ev1, f, c, (int)from_t);
   else if (c.vorder == 3)
-    hipLaunchKernelGGL((k_slow_var<H, false, 3>), g, b, 0, s, f, c, (int)from_t);
+    dispatch(k_slow_var<H, false, 3>, g, b, s, ev0, ev1, f, c, (int)from_t);
   else if (c.shallow)
-    hipLaunchKernelGGL((k_slow_var<H, true, 1>), g, b, 0, s, f, c, (int)from_t);
+    dispatch(k_slow_var<H, true, 1>, g, b, s, ev0, ev1, f, c, (int)from_t);
   else
-    hipLaunchKernelGGL(k_slow<H>, g, b, 0, s, f, c, (int)from_t);
+    dispatch(k_slow<H>, g, b, s, ev0, ev1, f, c, (int)from_t);
 }
 template <typename H>
-void launch_large(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s) {
-  hipLaunchKernelGGL(k_large0<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c);
-  hipLaunchKernelGGL(k_large1<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c);
-  hipLaunchKernelGGL(k_large2<H>, dim3(n_blocks_h(c, wpb)), dim3(64 * wpb), 0, s, f, c);
+void launch_large(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  const dim3 g(n_blocks_h(c, wpb)), b(64 * wpb);
+  dispatch(k_large0<H>, g, b, s, ev0, nullptr, f, c);
+  dispatch(k_large1<H>, g, b, s, nullptr, nullptr, f, c);
+  dispatch(k_large2<H>, g, b, s, nullptr, ev1, f, c);
 }
 template <typename H>
 void launch_diag_field(const Fields<H> &f, const Consts &c, int field, hipStream_t s) {
@@ -1992,10 +2007,13 @@ void launch_batch(const Planet<H> *P, const int2 *tiles, int n_tiles, int wpb, i
 }
 
 #define THOR_INSTANTIATE(H)                                                                          \
-  template void launch_hmom<H>(const Fields<H> &, const Consts &, int, int, bool, hipStream_t);      \
-  template void launch_vert<H>(const Fields<H> &, const Consts &, int, int, bool, bool, hipStream_t); \
-  template void launch_slow<H>(const Fields<H> &, const Consts &, int, bool, hipStream_t);           \
-  template void launch_large<H>(const Fields<H> &, const Consts &, int, hipStream_t);                \
+  template void launch_hmom<H>(const Fields<H> &, const Consts &, int, int, bool, hipStream_t, hipEvent_t,   \
+                               hipEvent_t);                                                          \
+  template void launch_vert<H>(const Fields<H> &, const Consts &, int, int, bool, bool, hipStream_t,        \
+                               hipEvent_t, hipEvent_t);                                              \
+  template void launch_slow<H>(const Fields<H> &, const Consts &, int, bool, hipStream_t, hipEvent_t,       \
+                               hipEvent_t);                                                          \
+  template void launch_large<H>(const Fields<H> &, const Consts &, int, hipStream_t, hipEvent_t, hipEvent_t); \
   template void launch_diag_field<H>(const Fields<H> &, const Consts &, int, hipStream_t);           \
   template void launch_mass<H>(const Fields<H> &, const Consts &, hipStream_t, int *);               \
   template void launch_to_state<H>(const Fields<H> &, const Consts &, const double *, hipStream_t);  \

@@ -288,17 +288,17 @@ hipEvent_t next_event(thor_state *s) {
   return s->event_pool[s->next_event++];
 }
 
-// Enqueue one launch, bracketed by timing events when timing is on.
+// Enqueue one kernel family; when timing is on, the dispatches themselves
+// record a start event (first kernel) and an end event (last kernel), so the
+// interval is the family's execution without event-packet overheads.
 template <typename F>
 void timed(thor_state *s, hipStream_t st, const char *family, F &&launch) {
   if (!s->timing) {
-    launch();
+    launch(nullptr, nullptr);
     return;
   }
   hipEvent_t a = next_event(s), b = next_event(s);
-  (void)hipEventRecord(a, st);
-  launch();
-  (void)hipEventRecord(b, st);
+  launch(a, b);
   s->timed.push_back({family, a, b});
 }
 
@@ -310,15 +310,18 @@ void enqueue_large_step(thor_state *s, const Fields<H> &f, int n, hipStream_t st
     int nb = 0;
     launch_energy(f, c, 0, f.epart, st, &nb);
   }
-  timed(s, st, "large", [&] { launch_large(f, c, it[FAM_LARGE], st); });
+  timed(s, st, "large", [&](hipEvent_t a, hipEvent_t b) { launch_large(f, c, it[FAM_LARGE], st, a, b); });
   const int ns[3] = {1, n / 2, n};
   const int div[3] = {3, n, n};   // dtau = dt / div
   for (int stage = 0; stage < 3; ++stage) {
-    timed(s, st, "slow", [&] { launch_slow(f, c, it[FAM_SLOW], stage == 0, st); });
+    timed(s, st, "slow", [&](hipEvent_t a, hipEvent_t b) { launch_slow(f, c, it[FAM_SLOW], stage == 0, st, a, b); });
     for (int i = 0; i < ns[stage]; ++i) {
       const bool first = i == 0, last = stage == 2 && i + 1 == ns[stage];
-      timed(s, st, "hmom", [&] { launch_hmom(f, c, it[FAM_HMOM], div[stage], first, st); });
-      timed(s, st, "vert", [&] { launch_vert(f, c, it[FAM_VERT], div[stage], first, last && !c.energy_fixer, st); });
+      timed(s, st, "hmom",
+            [&](hipEvent_t a, hipEvent_t b) { launch_hmom(f, c, it[FAM_HMOM], div[stage], first, st, a, b); });
+      timed(s, st, "vert", [&](hipEvent_t a, hipEvent_t b) {
+        launch_vert(f, c, it[FAM_VERT], div[stage], first, last && !c.energy_fixer, st, a, b);
+      });
     }
   }
   if (c.energy_fixer) launch_fixer(f, c, st);
