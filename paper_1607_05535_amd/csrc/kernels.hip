@@ -41,13 +41,16 @@
 #ifndef HMOM_OCC_F
 #define HMOM_OCC_F 4
 #endif
-// Fields of k_large1's velocity/temperature Laplacians in flight together,
-// and its minimum wavefronts per SIMD in FP64.
-#ifndef LARGE1_FU
-#define LARGE1_FU 4
+// Two-ring rows of D that k_hmom loads together.
+#ifndef HMOM_DU
+#define HMOM_DU 18
 #endif
+// Minimum wavefronts per SIMD of k_large1 in FP64 and in mixed precision.
 #ifndef LARGE1_OCC_D
-#define LARGE1_OCC_D 3
+#define LARGE1_OCC_D 2
+#endif
+#ifndef LARGE1_OCC_F
+#define LARGE1_OCC_F 2
 #endif
 #ifndef VERT4_OCC
 #define VERT4_OCC 2
@@ -253,13 +256,28 @@ __device__ __forceinline__ void st4(float *p, int nv, const float v[kHq]) {
   }
 }
 
-template <typename H, bool VEC>
-__device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, const HLane &ln, double dtau,
-                                           int first) {
+// Phase M of one lane's kHq levels.  FIRST (the first substep: p* = 0, D
+// of the [t] state) and DD (divergence damping) are compile-time, so each
+// form is straight-line code whose gathers (the six p* rows, the 18 two-ring
+// D rows) are fully unrolled: the scheduler can put the rows of both
+// gathers and of M, S_M in flight together, which shortens the chain of
+// dependent memory round trips a wavefront waits through.  The sums keep
+// their term order (j, m ascending).
+template <typename H, bool VEC, bool FIRST, bool DD>
+__device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, const HLane &ln, double dtau) {
   const int col = ln.col, nv = ln.nv;
   const size_t idx = (size_t)col * c.S + ln.lev0;
   int nb[6];
-  load_nbr(f.nbr, col, nb);
+  if (!FIRST) load_nbr(f.nbr, col, nb);
+  int ring[kRing2];
+  if (DD) {
+    const int32_t *di = f.ddi + (size_t)col * kRing2;
+#pragma unroll
+    for (int m = 0; m < kRing2; ++m) {
+      const int v = di[m];
+      ring[m] = v < 0 ? col : v;
+    }
+  }
   const H *dc = f.dc + (size_t)col * 21;
   H ir[kHq];
 #pragma unroll
@@ -267,11 +285,11 @@ __device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, 
   H gx[kHq], gy[kHq], gz[kHq];
 #pragma unroll
   for (int q = 0; q < kHq; ++q) gx[q] = gy[q] = gz[q] = 0;
-  if (!first) {
+  if (!FIRST) {
     // (1/r) sum_j c_j (p*_j - p*_0)
     H s0[kHq];
     ld4<VEC>(f.ps + idx, nv, s0);
-#pragma unroll 2
+#pragma unroll
     for (int j = 0; j < 6; ++j) {
       H sj[kHq];
       ld4<VEC>(f.ps + (size_t)nb[j] * c.S + ln.lev0, nv, sj);
@@ -294,25 +312,16 @@ __device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, 
   H ddx[kHq], ddy[kHq], ddz[kHq];
 #pragma unroll
   for (int q = 0; q < kHq; ++q) ddx[q] = ddy[q] = ddz[q] = 0;
-  if (c.div_damp) {
+  if (DD) {
     // -Kd lap(grad D) over the two-ring, D of the current small-step state
-    const H *D = first ? f.Dt : f.D;
-    const int32_t *di = f.ddi + (size_t)col * kRing2;
+    const H *D = FIRST ? f.Dt : f.D;
     const H *dw = f.ddw + (size_t)col * kRing2 * 3;
-    // all ring ids first, so that the row loads below are independent
-    int ring[kRing2];
-#pragma unroll
-    for (int m = 0; m < kRing2; ++m) {
-      const int v = di[m];
-      ring[m] = v < 0 ? col : v;
-    }
     H d0[kHq];
     ld4<VEC>(D + idx, nv, d0);
-#pragma unroll 6
+#pragma unroll HMOM_DU
     for (int m = 0; m < kRing2; ++m) {
-      const int cm = ring[m];
       H dm[kHq];
-      ld4<VEC>(D + (size_t)cm * c.S + ln.lev0, nv, dm);
+      ld4<VEC>(D + (size_t)ring[m] * c.S + ln.lev0, nv, dm);
       const H wx = dw[3 * m], wy = dw[3 * m + 1], wz = dw[3 * m + 2];
 #pragma unroll
       for (int q = 0; q < kHq; ++q) {
@@ -334,9 +343,9 @@ __device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, 
   const H rx = rh[0], ry = rh[1], rz = rh[2];
   const H dt = (H)dtau;
   H mx[kHq], my[kHq], mz[kHq], sx[kHq], sy[kHq], sz[kHq];
-  ld4<VEC>((first ? f.Mx_t : f.Mx) + idx, nv, mx);
-  ld4<VEC>((first ? f.My_t : f.My) + idx, nv, my);
-  ld4<VEC>((first ? f.Mz_t : f.Mz) + idx, nv, mz);
+  ld4<VEC>((FIRST ? f.Mx_t : f.Mx) + idx, nv, mx);
+  ld4<VEC>((FIRST ? f.My_t : f.My) + idx, nv, my);
+  ld4<VEC>((FIRST ? f.Mz_t : f.Mz) + idx, nv, mz);
   ld4<VEC>(f.SMx + idx, nv, sx);
   ld4<VEC>(f.SMy + idx, nv, sy);
   ld4<VEC>(f.SMz + idx, nv, sz);
@@ -359,7 +368,18 @@ template <typename H>
 __device__ __forceinline__ void b_hmom(const Fields<H> &f, const Consts &c, const HLane &ln, double dtau,
                                        int first) {
   if (!ln.store) return;
-  hmom_cells<H, true>(f, c, ln, dtau, first);   // rows of stride S: whole groups of kHq
+  // rows of stride S: whole groups of kHq
+  if (first) {
+    if (c.div_damp)
+      hmom_cells<H, true, true, true>(f, c, ln, dtau);
+    else
+      hmom_cells<H, true, true, false>(f, c, ln, dtau);
+  } else {
+    if (c.div_damp)
+      hmom_cells<H, true, false, true>(f, c, ln, dtau);
+    else
+      hmom_cells<H, true, false, false>(f, c, ln, dtau);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1398,6 +1418,16 @@ __device__ __forceinline__ void lap4(const T *s, const int nb[6], const H *lc, i
   }
 }
 
+// Per large step, first pass: the inner Laplacians of the hyperdiffusion
+// (rho; rho Kd lap of vx, vy, vz, T; rho_I Kd lap of w at the interfaces),
+// -proj_h grad p[t], the 3D momentum divergence of Phi[t] and the [t]
+// vertical imbalance.  The neighbour loops are neighbour-major: one pass
+// loads the rows of the six Laplacian fields of neighbour j together, a
+// second those of p, Mx, My, Mz, and every sum takes its j-th term, so each
+// sum adds its terms in the same order as a field-by-field pass, with six
+// (four) rows in flight per neighbour instead of one (FP64 at g6 L32: 72
+// against 79 us; one pass over all ten fields needs more registers than
+// two wavefronts per SIMD allow and takes 92 us).
 template <typename H, bool VEC>
 __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
   const int L = c.L, lev0 = ln.lev0, nv = ln.nv, col = ln.col;
@@ -1424,52 +1454,87 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
     const double rC = radius_c(c, lev0 + q);
     irc2[q] = 1.0 / (rC * rC);
   }
+  // Laplacian fields: rho, vx, vy, vz, T, w (rho is rho[] itself)
+  const double *lsrc[6] = {f.rho_t, f.vx, f.vy, f.vz, f.T, f.wI};
+  double s0[6][kHq], lap[6][kHq];
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) s0[0][q] = rho[q];
+#pragma unroll
+  for (int k = 1; k < 6; ++k) ld4<VEC>(lsrc[k] + idx, nv, s0[k]);
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) lap[k][q] = 0;
+  double gx[kHq], gy[kHq], gz[kHq];
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) gx[q] = gy[q] = gz[q] = 0;
+  H dm[kHq];
+  {
+    H mx[kHq], my[kHq], mz[kHq];
+    ld4<VEC>(f.Mx_t + idx, nv, mx);
+    ld4<VEC>(f.My_t + idx, nv, my);
+    ld4<VEC>(f.Mz_t + idx, nv, mz);
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) dm[q] = dch[0] * mx[q] + dch[1] * my[q] + dch[2] * mz[q];
+  }
+#pragma unroll 1
+  for (int j = 0; j < 6; ++j) {
+    const size_t nj = (size_t)nb[j] * c.S + lev0;
+    double sj[6][kHq];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ld4<VEC>(lsrc[k] + nj, nv, sj[k]);
+    const double w = (double)lch[j];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int q = 0; q < kHq; ++q) lap[k][q] += w * (sj[k][q] - s0[k][q]);
+  }
+#pragma unroll 1
+  for (int j = 0; j < 6; ++j) {
+    const size_t nj = (size_t)nb[j] * c.S + lev0;
+    double pj[kHq];
+    H mx[kHq], my[kHq], mz[kHq];
+    ld4<VEC>(f.p_t + nj, nv, pj);
+    ld4<VEC>(f.Mx_t + nj, nv, mx);
+    ld4<VEC>(f.My_t + nj, nv, my);
+    ld4<VEC>(f.Mz_t + nj, nv, mz);
+    const double cx = dch[3 * (j + 1)], cy = dch[3 * (j + 1) + 1], cz = dch[3 * (j + 1) + 2];
+    const H hx = dch[3 * (j + 1)], hy = dch[3 * (j + 1) + 1], hz = dch[3 * (j + 1) + 2];
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) {
+      const double dp = pj[q] - p[q];
+      gx[q] += cx * dp;
+      gy[q] += cy * dp;
+      gz[q] += cz * dp;
+      dm[q] += hx * mx[q] + hy * my[q] + hz * mz[q];
+    }
+  }
   {
     double l[kHq];
-    lap4<VEC>(f.rho_t, nb, lch, c.S, lev0, nv, idx, l);
 #pragma unroll
-    for (int q = 0; q < kHq; ++q) l[q] = irc2[q] * l[q];
+    for (int q = 0; q < kHq; ++q) l[q] = irc2[q] * lap[0][q];
     st4<VEC>(f.Xrho + idx, nv, l);
   }
-  const double *vsrc[4] = {f.vx, f.vy, f.vz, f.T};
   double *vdst[4] = {f.Xvx, f.Xvy, f.Xvz, f.XT};
-#pragma unroll LARGE1_FU
+#pragma unroll
   for (int k = 0; k < 4; ++k) {
     double l[kHq];
-    lap4<VEC>(vsrc[k], nb, lch, c.S, lev0, nv, idx, l);
 #pragma unroll
-    for (int q = 0; q < kHq; ++q) l[q] = rho[q] * Kd * irc2[q] * l[q];
+    for (int q = 0; q < kHq; ++q) l[q] = rho[q] * Kd * irc2[q] * lap[k + 1][q];
     st4<VEC>(vdst[k] + idx, nv, l);
   }
   {
     double l[kHq];
-    lap4<VEC>(f.wI, nb, lch, c.S, lev0, nv, idx, l);
 #pragma unroll
     for (int q = 0; q < kHq; ++q) {
       const int lev = lev0 + q;
       const double rI = radius_i(c, lev);
-      l[q] = lev == 0 ? 0.0 : rhoI[q] * Kd / (rI * rI) * l[q];
+      l[q] = lev == 0 ? 0.0 : rhoI[q] * Kd / (rI * rI) * lap[5][q];
     }
     st4<VEC>(f.Xw + idx, nv, l);
   }
-  // grad p[t] (in double: full pressure), projected
+  // -grad p[t] (in double: full pressure), projected
   {
-    double gx[kHq], gy[kHq], gz[kHq];
-#pragma unroll
-    for (int q = 0; q < kHq; ++q) gx[q] = gy[q] = gz[q] = 0;
-#pragma unroll 2
-    for (int j = 0; j < 6; ++j) {
-      double pj[kHq];
-      ld4<VEC>(f.p_t + (size_t)nb[j] * c.S + lev0, nv, pj);
-      const double cx = dch[3 * (j + 1)], cy = dch[3 * (j + 1) + 1], cz = dch[3 * (j + 1) + 2];
-#pragma unroll
-      for (int q = 0; q < kHq; ++q) {
-        const double dp = pj[q] - p[q];
-        gx[q] += cx * dp;
-        gy[q] += cy * dp;
-        gz[q] += cz * dp;
-      }
-    }
     const H *rh = f.rhat + (size_t)col * 3;
     const double rx = rh[0], ry = rh[1], rz = rh[2];
     H ox[kHq], oy[kHq], oz[kHq];
@@ -1486,24 +1551,8 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
     st4<VEC>(f.FMy + idx, nv, oy);
     st4<VEC>(f.FMz + idx, nv, oz);
   }
-  // 3D momentum divergence of Phi[t]
+  // 3D momentum divergence of Phi[t] and the [t] vertical imbalance
   {
-    H mx[kHq], my[kHq], mz[kHq], dm[kHq];
-    ld4<VEC>(f.Mx_t + idx, nv, mx);
-    ld4<VEC>(f.My_t + idx, nv, my);
-    ld4<VEC>(f.Mz_t + idx, nv, mz);
-#pragma unroll
-    for (int q = 0; q < kHq; ++q) dm[q] = dch[0] * mx[q] + dch[1] * my[q] + dch[2] * mz[q];
-#pragma unroll 2
-    for (int j = 0; j < 6; ++j) {
-      const size_t nj = (size_t)nb[j] * c.S + lev0;
-      ld4<VEC>(f.Mx_t + nj, nv, mx);
-      ld4<VEC>(f.My_t + nj, nv, my);
-      ld4<VEC>(f.Mz_t + nj, nv, mz);
-      const H cx = dch[3 * (j + 1)], cy = dch[3 * (j + 1) + 1], cz = dch[3 * (j + 1) + 2];
-#pragma unroll
-      for (int q = 0; q < kHq; ++q) dm[q] += cx * mx[q] + cy * my[q] + cz * mz[q];
-    }
     H Dt[kHq];
     double FW[kHq];
 #pragma unroll
@@ -1819,7 +1868,7 @@ __device__ __forceinline__ void b_import(const Fields<H> &f, const Consts &c, co
 #define COMMA ,
 THOR_KERNEL(slow, sizeof(H) == 8 ? 2 : 4, map_hlane, COMMA int from_t, COMMA from_t)
 THOR_KERNEL(large0, 4, map_hlane, , )
-THOR_KERNEL(large1, sizeof(H) == 8 ? LARGE1_OCC_D : 4, map_hlane, , )
+THOR_KERNEL(large1, sizeof(H) == 8 ? LARGE1_OCC_D : LARGE1_OCC_F, map_hlane, , )
 THOR_KERNEL(large2, 5, map_hlane, , )
 THOR_KERNEL(diag, 8, map_lane, COMMA int field, COMMA field)
 THOR_KERNEL(import, 8, map_lane, COMMA const double *blob, COMMA blob)

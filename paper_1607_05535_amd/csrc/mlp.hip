@@ -35,9 +35,21 @@ constexpr int kBiasSplit = 32;     // batch chunks of the bias gradient
 
 enum Epilogue { EPI_STORE = 0, EPI_GELU = 1, EPI_GELU_ONLY = 2 };
 
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+// erf by Abramowitz & Stegun 7.1.26: erf x = 1 - t (a1 + t (a2 + ... a5 t))
+// e^(-x^2), t = 1 / (1 + p x) for x >= 0, odd in x; absolute error below
+// 1.5e-7, far under the BF16 rounding of the activations it feeds, and
+// branch-free (the epilogues evaluate it for every hidden activation).
+__device__ __forceinline__ float erf_as(float x) {
+  const float a = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(1.f + 0.3275911f * a);
+  const float poly =
+      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  const float e = 1.f - poly * __expf(-a * a);
+  return copysignf(e, x);
+}
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.f + erf_as(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad_f(float z) {
-  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+  return 0.5f * (1.f + erf_as(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
 }
 
 // Piece h (0, 1) of a 64 x 64 operand tile, 16 bytes per thread (256
@@ -158,27 +170,37 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, int 
 
 // ---------------------------------------------------------------------------
 // Fused inference of a 4-layer network whose hidden widths are all kFH =
-// 256 (the corrector's shape): one workgroup of 4 wavefronts per tile of
-// kFM = 64 rows runs every layer.  The 64 x 256 hidden activations stay in
-// LDS (bf16) from one layer to the next, so only the inputs, the weights
-// (from L2) and the outputs cross the memory hierarchy.  Each wavefront
-// reads its own MFMA operand fragments from global memory (inputs in the
-// first layer, weights in every layer) into a ring of kFD chunks of 64 k
-// in registers, so kFD - 1 chunks are in flight while one is multiplied
-// and no barrier is needed inside a layer.  Wavefront w owns hidden columns
-// 64 w .. 64 w + 63 as 4 x 4 MFMA tiles of 16 x 16 over the tile's 64 rows;
-// in the output layer the 16-column tiles w, w + 4, w + 8, ...  Per tile
-// the products and their order (k ascending in steps of 32) equal k_gemm's,
-// so the outputs equal the layer-by-layer path.
+// 256 (the corrector's shape): one workgroup of kFW = 8 wavefronts (2 per
+// SIMD) per tile of kFM = 64 rows runs every layer.
+//   * The tile's inputs (64 rows x in, bf16) are staged once into LDS by
+//     direct global-to-LDS loads (global_load_lds_dwordx4), all issued
+//     before the first wait, laid out [k / 8][row][8] so that a
+//     wavefront's 16-byte operand reads hit 64 distinct banks.
+//   * The 64 x 256 hidden activations then live in the same LDS ([row][k],
+//     rows padded) from one layer to the next, so only the inputs, the
+//     weights (from L2) and the outputs cross the memory hierarchy.
+//   * Each layer is its own loop over k in substeps of 32; a wavefront
+//     streams its weight fragments through a ring of kFD substeps in
+//     registers, kFD - 1 substeps in flight while one is multiplied, with
+//     no barrier inside a layer.
+// Wavefront w owns the 16-column tiles w + kFW j (j < kFT) of a layer
+// below its width / 16, over the tile's 64 rows (4 MFMA tiles of 16 x 16
+// each).  Per tile the products and their order (k ascending in steps of
+// 32) equal k_gemm's, so the outputs equal the layer-by-layer path bit for
+// bit.
 // ---------------------------------------------------------------------------
 constexpr int kFM = 64;              // rows per workgroup
 constexpr int kFH = 256;             // hidden width
-constexpr int kFK = 64;              // k per chunk
+constexpr int kFW = 8;               // wavefronts per workgroup
+constexpr int kFT = kFH / 16 / kFW;  // 16-column tiles per wavefront (2)
+constexpr int kFK0Max = 1152;        // widest input the LDS tile holds
 #ifndef MLP_FD
-#define MLP_FD 3
+#define MLP_FD 8
 #endif
-constexpr int kFD = MLP_FD;          // chunks in the register ring
+constexpr int kFD = MLP_FD;          // 32-k substeps in the weight ring
 constexpr int kHRow = kFH + 8;       // LDS row of the hidden activations, padded
+constexpr int kFLds = kFK0Max / 8 * kFM * 8;   // bf16 values of the LDS tile (147,456 bytes)
+static_assert(kFM * kHRow <= kFLds, "hidden activations must fit the input tile's LDS");
 
 struct FusedNet {
   const __bf16 *W[4];   // [out][in] bf16
@@ -186,112 +208,112 @@ struct FusedNet {
   int in, out;          // widths of the input and output layers
 };
 
-// Operand fragments of one 64-k chunk: a[2 i + s] rows 16 i + r (first
-// layer only), b[2 j + s] weight rows of tile j; s = 32-k substep.
-struct FusedFrag {
-  bf16x8 a[8], b[8];
-};
+// acc[i][j] += A(rows 16 i + .., k) W(rows 16 tile[j] + .., k) over k in
+// [0, K), K a multiple of 32 (KC: K known at compile time, else 0).  XS: A
+// is the staged input tile ([k / 8][row][8]), else the hidden activations
+// ([row][kHRow]).  Tiles with use[j] false are loaded (from a valid row)
+// but not multiplied.  The ring is refilled unconditionally (a substep past
+// the end reloads the last one), so every substep issues the same loads and
+// the wait before a substep's products covers only its own fragments, kFD
+// substeps old.
+template <bool XS, int KC>
+__device__ __forceinline__ void fused_layer(const __bf16 *__restrict__ W, int K_rt, const int tile[kFT],
+                                            const bool use[kFT], const __bf16 *lds, f32x4 acc[4][kFT]) {
+  const int K = KC ? KC : K_rt;
+  const int lane = threadIdx.x & 63, r = lane & 15, kq = (lane >> 4) * 8;
+  const int nsub = K >> 5, nfull = nsub / kFD;
+  const __bf16 *wrow[kFT];
+#pragma unroll
+  for (int j = 0; j < kFT; ++j) wrow[j] = W + (size_t)(16 * tile[j] + r) * K + kq;
+  auto load = [&](int t, bf16x8 fr[kFT]) {
+    const int tt = min(t, nsub - 1);
+#pragma unroll
+    for (int j = 0; j < kFT; ++j) fr[j] = *reinterpret_cast<const bf16x8 *>(wrow[j] + 32 * tt);
+  };
+  auto mul = [&](int t, const bf16x8 fr[kFT]) {
+    bf16x8 a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      a[i] = XS ? *reinterpret_cast<const bf16x8 *>(lds + ((((32 * t + kq) >> 3) * kFM) + 16 * i + r) * 8)
+                : *reinterpret_cast<const bf16x8 *>(lds + (16 * i + r) * kHRow + 32 * t + kq);
+#pragma unroll
+    for (int j = 0; j < kFT; ++j)
+      if (use[j])
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], fr[j], acc[i][j], 0, 0, 0);
+  };
+  bf16x8 ring[kFD][kFT];
+#pragma unroll
+  for (int d = 0; d < kFD; ++d) load(d, ring[d]);
+  for (int b = 0; b < nfull; ++b) {
+#pragma unroll
+    for (int d = 0; d < kFD; ++d) {
+      const int t = b * kFD + d;
+      mul(t, ring[d]);
+      if (!KC || t + kFD < nsub) load(t + kFD, ring[d]);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < kFD; ++d)
+    if (nfull * kFD + d < nsub) mul(nfull * kFD + d, ring[d]);
+}
 
-__global__ __launch_bounds__(256) void k_mlp_fused4(FusedNet net, const __bf16 *__restrict__ X, int B,
-                                                    float *__restrict__ Y) {
-  __shared__ __align__(16) __bf16 Hs[kFM * kHRow];
+__global__ __launch_bounds__(64 * kFW) void k_mlp_fused4(FusedNet net, const __bf16 *__restrict__ X, int B,
+                                                         float *__restrict__ Y) {
+  __shared__ __align__(16) __bf16 lds[kFLds];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r = lane & 15, kq = (lane >> 4) * 8;
+  const int r = lane & 15;
   const int m0 = blockIdx.x * kFM;
   const int K0 = net.in, N3 = net.out;
-  const int nk0 = (K0 + kFK - 1) / kFK, nkh = kFH / kFK;
-  const int n_chunks = nk0 + 3 * nkh;
-  const bf16x8 zero = {};
-  auto layer_of = [&](int c) { return c < nk0 ? 0 : 1 + (c - nk0) / nkh; };
-  auto k0_of = [&](int c) { return c < nk0 ? c * kFK : ((c - nk0) % nkh) * kFK; };
-  // 16-column tile j of this wavefront in layer l (-1: none)
-  auto tile_of = [&](int l, int j) {
-    const int tj = l == 3 ? w + 4 * j : 4 * w + j;
-    return tj < (l == 3 ? N3 / 16 : kFH / 16) ? tj : -1;
-  };
-  auto fetch = [&](int c, FusedFrag &fr) {
-    const int l = layer_of(c), k0 = k0_of(c);
-    const int K = l == 0 ? K0 : kFH;
-    const __bf16 *W = net.W[l];
+  // stage the input tile: wavefront w takes k blocks w, w + kFW, ...; lane =
+  // row (rows past the batch repeat its last row; their outputs are dropped)
+  {
+    const __bf16 *xrow = X + (size_t)min(m0 + lane, B - 1) * K0;
+    for (int kb = w; kb < K0 / 8; kb += kFW)
+      __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(xrow + 8 * kb),
+                                       (__attribute__((address_space(3))) void *)(lds + kb * (kFM * 8)), 16, 0, 0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);   // the direct-to-LDS loads have landed
+  __syncthreads();
+  f32x4 acc[4][kFT];
+  for (int l = 0; l < 4; ++l) {
+    const int n_tiles = (l == 3 ? N3 : kFH) / 16;
+    int tile[kFT];
+    bool use[kFT];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int tj = tile_of(l, j);
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int k = k0 + 32 * s + kq;
-        fr.b[2 * j + s] = tj >= 0 && k < K ? *reinterpret_cast<const bf16x8 *>(W + (size_t)(16 * tj + r) * K + k)
-                                           : zero;
-      }
+    for (int j = 0; j < kFT; ++j) {
+      use[j] = w + kFW * j < n_tiles;
+      tile[j] = use[j] ? w + kFW * j : 0;
     }
-    if (l == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < kFT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (l == 0)
+      fused_layer<true, 0>(net.W[0], K0, tile, use, lds, acc);
+    else
+      fused_layer<false, kFH>(net.W[l], kFH, tile, use, lds, acc);
+    const float *bias = net.b[l];
+    if (l < 3) __syncthreads();   // every wavefront is done reading this layer's input
+#pragma unroll
+    for (int j = 0; j < kFT; ++j) {
+      if (!use[j]) continue;
+      const int col = 16 * tile[j] + r;
+      const float bb = bias[col];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const int row = m0 + 16 * i + r, k = k0 + 32 * s + kq;
-          fr.a[2 * i + s] = row < B && k < K0 ? *reinterpret_cast<const bf16x8 *>(X + (size_t)row * K0 + k) : zero;
+        for (int q = 0; q < 4; ++q) {
+          const int row = 16 * i + (lane >> 4) * 4 + q;
+          const float z = acc[i][j][q] + bb;
+          if (l < 3)
+            lds[row * kHRow + col] = (__bf16)gelu_f(z);
+          else if (m0 + row < B)
+            Y[(size_t)(m0 + row) * N3 + col] = z;
         }
     }
-  };
-  f32x4 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  FusedFrag ring[kFD];
-#pragma unroll
-  for (int d = 0; d < kFD; ++d)
-    if (d < n_chunks) fetch(d, ring[d]);
-  for (int c0 = 0; c0 < n_chunks; c0 += kFD) {
-#pragma unroll
-    for (int d = 0; d < kFD; ++d) {
-      const int c = c0 + d;
-      if (c >= n_chunks) break;
-      const int l = layer_of(c), k0 = k0_of(c);
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        bf16x8 a[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          a[i] = l == 0 ? ring[d].a[2 * i + s]
-                        : *reinterpret_cast<const bf16x8 *>(&Hs[(16 * i + r) * kHRow + k0 + 32 * s + kq]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], ring[d].b[2 * j + s], acc[i][j], 0, 0, 0);
-      }
-      if (c + kFD < n_chunks) fetch(c + kFD, ring[d]);
-      if (c + 1 == n_chunks || layer_of(c + 1) != l) {
-        // end of layer l: bias, then GELU into Hs (hidden) or the output
-        __syncthreads();   // every wavefront is done reading Hs as this layer's input
-        const float *bias = net.b[l];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int tj = tile_of(l, j);
-          if (tj < 0) continue;
-          const int col = 16 * tj + r;
-          const float bb = bias[col];
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int row = 16 * i + (lane >> 4) * 4 + q;
-              const float z = acc[i][j][q] + bb;
-              if (l < 3) {
-                Hs[row * kHRow + col] = (__bf16)gelu_f(z);
-              } else if (m0 + row < B) {
-                Y[(size_t)(m0 + row) * N3 + col] = z;
-              }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        __syncthreads();   // Hs holds the next layer's input
-      }
-    }
+    if (l < 3) __syncthreads();   // the activations are the next layer's input
   }
 }
 
@@ -488,9 +510,10 @@ void gemm(const __bf16 *A, int lda, const __bf16 *B, int ldb, float *C, int ldc,
 int grad_splits(int B) { return std::max(1, std::min(kMaxSplit, B / 256)); }
 
 // The fused inference kernel serves 4-layer networks with hidden widths
-// kFH and an output width of at most kFH.
+// kFH, an input width of at most kFK0Max and an output width of at most kFH.
 bool fused_shape(const thor_mlp *M) {
-  return M->nl == 4 && M->w[1] == kFH && M->w[2] == kFH && M->w[3] == kFH && M->w[4] <= kFH;
+  return M->nl == 4 && M->w[0] <= kFK0Max && M->w[1] == kFH && M->w[2] == kFH && M->w[3] == kFH &&
+         M->w[4] <= kFH;
 }
 
 // Forward pass; the output layer's pre-activation goes to y if given
@@ -504,7 +527,7 @@ void forward(thor_mlp *M, const __bf16 *X, int B, float *y) {
     }
     net.in = M->w[0];
     net.out = M->w[4];
-    hipLaunchKernelGGL(k_mlp_fused4, dim3((B + kFM - 1) / kFM), dim3(256), 0, M->stream, net, X, B, y);
+    hipLaunchKernelGGL(k_mlp_fused4, dim3((B + kFM - 1) / kFM), dim3(64 * kFW), 0, M->stream, net, X, B, y);
     return;
   }
   const __bf16 *in = X;
