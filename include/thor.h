@@ -395,17 +395,18 @@ size_t thor_mlp_param_count(const thor_mlp *m);
 int thor_mlp_set_params(thor_mlp *m, const float *host_params);   /* resets Adam; synchronises */
 int thor_mlp_get_params(thor_mlp *m, float *host_params);         /* synchronises */
 
-/* y[B][out] (device, FP32) = network(x[B][in] device BF16), layer by layer
- * (or fused, see below).  Asynchronous.  EINVAL: B outside 1..max_batch, or
- * x not 16-byte aligned (also for the two calls below). */
+/* y[B][out] (device, FP32) = network(x[B][in] device BF16): one fused kernel
+ * for the corrector's shape, else layer by layer (see below).  Asynchronous.
+ * EINVAL: B outside 1..max_batch, or x not 16-byte aligned (also for the two
+ * calls below). */
 int thor_mlp_forward(thor_mlp *m, const void *x_bf16, int B, float *y);
 
-/* on = 1: thor_mlp_forward runs a 4-layer network with hidden widths of 256
- * and at most 256 outputs (the corrector's shape) as one fused kernel per
- * 64-row tile, the hidden activations kept in LDS; other shapes stay layer
- * by layer.  Both give the same products in the same order (equal outputs).
- * on = 0 (the default, faster at the corrector's batch on gfx950): layer by
- * layer. */
+/* on = 1 (the default): thor_mlp_forward runs a 4-layer network with at
+ * most 1152 inputs, hidden widths of 256 and at most 256 outputs (the
+ * corrector's shape) as one fused kernel per 64-row tile: the tile's inputs
+ * and then its hidden activations kept in LDS (147,456 bytes per
+ * workgroup); other shapes stay layer by layer.  on = 0: layer by layer.
+ * Both give the same products in the same order (equal outputs). */
 int thor_mlp_set_fused(thor_mlp *m, int on);
 
 /* Mean-squared loss sum (y - t)^2 / (B out) and, if grad_host is not NULL,

@@ -195,7 +195,7 @@ constexpr int kFW = 8;               // wavefronts per workgroup
 constexpr int kFT = kFH / 16 / kFW;  // 16-column tiles per wavefront (2)
 constexpr int kFK0Max = 1152;        // widest input the LDS tile holds
 #ifndef MLP_FD
-#define MLP_FD 8
+#define MLP_FD 6
 #endif
 constexpr int kFD = MLP_FD;          // 32-k substeps in the weight ring
 constexpr int kHRow = kFH + 8;       // LDS row of the hidden activations, padded
@@ -416,7 +416,7 @@ struct thor_mlp {
   float *split = nullptr;        // split-K partial sums of one weight gradient
   float *partial = nullptr;      // loss partial sums
   int adam_t = 0;
-  bool fused = false;            // inference through k_mlp_fused4 where the shape allows
+  bool fused = true;             // inference through k_mlp_fused4 where the shape allows
   hipStream_t stream = nullptr;
 };
 

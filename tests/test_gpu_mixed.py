@@ -28,10 +28,12 @@ def test_mixed_tracks_fp64(maker):
     fa, fb = lib_fields(a), lib_fields(b)
     err = cell_errors(fb, fa)
     say(f"        errors {err}")
+    # bars about 30 and 50 times the largest errors measured (thermodynamic
+    # 3.7e-9, winds 1.9e-6 of the RMS speed after 10 steps)
     for k in ("T", "p", "rho", "rhotheta"):
-        assert err[k] < 1e-6, (k, err[k])
+        assert err[k] < 1e-7, (k, err[k])
     for k in ("u", "v", "w"):
-        assert err[k] < 1e-2, (k, err[k])
+        assert err[k] < 1e-4, (k, err[k])
     ma, _ = a.mass()
     mb, rc = b.mass()
     assert rc == 0
@@ -63,7 +65,8 @@ def test_mixed_four_levels_per_lane_matches_one_level():
     b.step(w.n_large, w.n_acoustic)
     err = cell_errors(lib_fields(b), lib_fields(a))
     say(f"[mixed] four vs one level per lane {err}")
+    # measured: thermodynamic 4.4e-9, winds 4.0e-7
     for k in ("T", "p", "rho", "rhotheta"):
-        assert err[k] < 1e-6, (k, err[k])
+        assert err[k] < 1e-7, (k, err[k])
     for k in ("u", "v", "w"):
-        assert err[k] < 1e-4, (k, err[k])
+        assert err[k] < 1e-5, (k, err[k])
