@@ -41,9 +41,19 @@
 #ifndef HMOM_OCC_F
 #define HMOM_OCC_F 4
 #endif
-// Two-ring rows of D that k_hmom loads together.
-#ifndef HMOM_DU
-#define HMOM_DU 18
+// Two-ring rows of D that k_hmom loads together, FP64 and mixed.
+#ifndef HMOM_DU_D
+#define HMOM_DU_D 6
+#endif
+#ifndef HMOM_DU_F
+#define HMOM_DU_F 18
+#endif
+#ifndef HMOM_PU
+#define HMOM_PU 6
+#endif
+// Neighbours whose rows the slow-terms kernel loads together.
+#ifndef SLOW_NU
+#define SLOW_NU 1
 #endif
 // Minimum wavefronts per SIMD of k_large1 in FP64 and in mixed precision.
 #ifndef LARGE1_OCC_D
@@ -257,14 +267,20 @@ __device__ __forceinline__ void st4(float *p, int nv, const float v[kHq]) {
 }
 
 // Phase M of one lane's kHq levels.  FIRST (the first substep: p* = 0, D
-// of the [t] state) and DD (divergence damping) are compile-time, so each
-// form is straight-line code whose gathers (the six p* rows, the 18 two-ring
-// D rows) are fully unrolled: the scheduler can put the rows of both
-// gathers and of M, S_M in flight together, which shortens the chain of
-// dependent memory round trips a wavefront waits through.  The sums keep
-// their term order (j, m ascending).
-template <typename H, bool VEC, bool FIRST, bool DD>
-__device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, const HLane &ln, double dtau) {
+// of the [t] state) and DD (divergence damping) are compile-time (0 or 1)
+// in the single-state kernel, so each form is straight-line code whose
+// gathers (the six p* rows, the 18 two-ring D rows) are unrolled: the
+// scheduler can put the rows of both gathers and of M, S_M in flight
+// together (FP64 unchanged, mixed 17.4 -> 15.9 us at g6 L32).  The
+// ensemble kernel passes -1 for both (runtime flags, partly unrolled
+// gathers): there the four forms measured slower (1.31 -> 1.38-1.45 ms per
+// launch over 64 planets).  Every form adds its terms in the same order (j,
+// m ascending), so all give the same bits.
+template <typename H, bool VEC, int FIRST_, int DD_>
+__device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, const HLane &ln, double dtau,
+                                           int first_rt) {
+  const bool FIRST = FIRST_ < 0 ? first_rt != 0 : FIRST_ != 0;
+  const bool DD = DD_ < 0 ? c.div_damp != 0 : DD_ != 0;
   const int col = ln.col, nv = ln.nv;
   const size_t idx = (size_t)col * c.S + ln.lev0;
   int nb[6];
@@ -289,7 +305,7 @@ __device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, 
     // (1/r) sum_j c_j (p*_j - p*_0)
     H s0[kHq];
     ld4<VEC>(f.ps + idx, nv, s0);
-#pragma unroll
+#pragma unroll(FIRST_ < 0 ? 2 : HMOM_PU)
     for (int j = 0; j < 6; ++j) {
       H sj[kHq];
       ld4<VEC>(f.ps + (size_t)nb[j] * c.S + ln.lev0, nv, sj);
@@ -318,7 +334,7 @@ __device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, 
     const H *dw = f.ddw + (size_t)col * kRing2 * 3;
     H d0[kHq];
     ld4<VEC>(D + idx, nv, d0);
-#pragma unroll HMOM_DU
+#pragma unroll(DD_ < 0 ? 6 : sizeof(H) == 8 ? HMOM_DU_D : HMOM_DU_F)
     for (int m = 0; m < kRing2; ++m) {
       H dm[kHq];
       ld4<VEC>(D + (size_t)ring[m] * c.S + ln.lev0, nv, dm);
@@ -364,21 +380,23 @@ __device__ __forceinline__ void hmom_cells(const Fields<H> &f, const Consts &c, 
   st4<VEC>(f.Mz + idx, nv, mz);
 }
 
-template <typename H>
+template <typename H, bool FORMS>
 __device__ __forceinline__ void b_hmom(const Fields<H> &f, const Consts &c, const HLane &ln, double dtau,
                                        int first) {
   if (!ln.store) return;
   // rows of stride S: whole groups of kHq
-  if (first) {
+  if (!FORMS) {
+    hmom_cells<H, true, -1, -1>(f, c, ln, dtau, first);
+  } else if (first) {
     if (c.div_damp)
-      hmom_cells<H, true, true, true>(f, c, ln, dtau);
+      hmom_cells<H, true, 1, 1>(f, c, ln, dtau, first);
     else
-      hmom_cells<H, true, true, false>(f, c, ln, dtau);
+      hmom_cells<H, true, 1, 0>(f, c, ln, dtau, first);
   } else {
     if (c.div_damp)
-      hmom_cells<H, true, false, true>(f, c, ln, dtau);
+      hmom_cells<H, true, 0, 1>(f, c, ln, dtau, first);
     else
-      hmom_cells<H, true, false, false>(f, c, ln, dtau);
+      hmom_cells<H, true, 0, 0>(f, c, ln, dtau, first);
   }
 }
 
@@ -1179,7 +1197,7 @@ __device__ __forceinline__ void slow_cells(const Fields<H> &f, const Consts &c, 
       }
     }
   }
-#pragma unroll 1
+#pragma unroll SLOW_NU
   for (int j = 0; j < 6; ++j) {
     const size_t nj = (size_t)nb[j] * c.S + lev0;
     double wn[kHq], rj[kHq];
@@ -1877,7 +1895,7 @@ template <typename H>
 __global__ __launch_bounds__(kMaxBlock)
 __attribute__((amdgpu_waves_per_eu(sizeof(H) == 8 ? HMOM_OCC_D : HMOM_OCC_F, sizeof(H) == 8 ? HMOM_OCC_D : HMOM_OCC_F)))
 void k_hmom(Fields<H> f, Consts c, int div, int first) {
-  b_hmom(f, c, map_hlane(c, xcd_block()), c.dt / div, first);
+  b_hmom<H, true>(f, c, map_hlane(c, xcd_block()), c.dt / div, first);
 }
 template <typename H>
 __global__ __launch_bounds__(kMaxBlock)
@@ -1887,7 +1905,7 @@ void kb_hmom(const Planet<H> *P, const int2 *tiles, int parity, int div, int fir
   if (t.x < 0) return;
   const Fields<H> &f = P[t.x].f[parity];
   const Consts &c = P[t.x].c;
-  b_hmom(f, c, map_hlane(c, t.y), c.dt / div, first);
+  b_hmom<H, false>(f, c, map_hlane(c, t.y), c.dt / div, first);
 }
 // slow terms of the shallow-atmosphere form and of the cubic vertical
 // interpolation (single states only)
