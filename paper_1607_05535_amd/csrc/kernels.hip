@@ -51,7 +51,8 @@
 #ifndef HMOM_PU
 #define HMOM_PU 6
 #endif
-// Neighbours whose rows the slow-terms kernel loads together.
+// Neighbours whose rows the slow-terms kernel loads together (1; 2 and 3
+// measured no faster in FP64 and slower in the mixed form at g6 L32).
 #ifndef SLOW_NU
 #define SLOW_NU 1
 #endif
