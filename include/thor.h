@@ -403,9 +403,11 @@ int thor_mlp_forward(thor_mlp *m, const void *x_bf16, int B, float *y);
 
 /* on = 1 (the default): thor_mlp_forward runs a 4-layer network with at
  * most 1152 inputs, hidden widths of 256 and at most 256 outputs (the
- * corrector's shape) as one fused kernel per 64-row tile: the tile's inputs
+ * corrector's shape) as one fused kernel per 48-row tile: the tile's inputs
  * and then its hidden activations kept in LDS (147,456 bytes per
- * workgroup); other shapes stay layer by layer.  on = 0: layer by layer.
+ * workgroup), the weights read from a copy in MFMA fragment order kept
+ * beside the BF16 copy; other shapes stay layer by layer.  on = 0: layer by
+ * layer.
  * Both give the same products in the same order (equal outputs). */
 int thor_mlp_set_fused(thor_mlp *m, int on);
 

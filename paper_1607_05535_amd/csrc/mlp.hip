@@ -171,25 +171,35 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16 *__restrict__ A, int 
 // ---------------------------------------------------------------------------
 // Fused inference of a 4-layer network whose hidden widths are all kFH =
 // 256 (the corrector's shape): one workgroup of kFW = 8 wavefronts (2 per
-// SIMD) per tile of kFM = 64 rows runs every layer.
-//   * The tile's inputs (64 rows x in, bf16) are staged once into LDS by
+// SIMD) per tile of kFM = 48 rows runs every layer (214 workgroups for the
+// g5 corrector's 10242 columns, one per CU, against 161 for 64-row tiles).
+//   * The tile's inputs (48 rows x in, bf16) are staged once into LDS by
 //     direct global-to-LDS loads (global_load_lds_dwordx4), all issued
-//     before the first wait, laid out [k / 8][row][8] so that a
-//     wavefront's 16-byte operand reads hit 64 distinct banks.
-//   * The 64 x 256 hidden activations then live in the same LDS ([row][k],
-//     rows padded) from one layer to the next, so only the inputs, the
-//     weights (from L2) and the outputs cross the memory hierarchy.
-//   * Each layer is its own loop over k in substeps of 32; a wavefront
-//     streams its weight fragments through a ring of kFD substeps in
-//     registers, kFD - 1 substeps in flight while one is multiplied, with
-//     no barrier inside a layer.
+//     before the first wait, laid out [k / 8][row slot][8] with 64 row slots
+//     (one per lane of the loading wavefront), so that a wavefront's 16-byte
+//     operand reads hit 64 distinct banks.
+//   * The hidden activations then live in the same LDS ([row][k], rows
+//     padded) from one layer to the next, so only the inputs, the weights
+//     (from L2) and the outputs cross the memory hierarchy.
+//   * The weights are read from a copy in MFMA fragment order
+//     (k_weights_frag), one contiguous KiB per wavefront load.  Each layer
+//     is its own loop over k in substeps of 32; a wavefront streams its
+//     weight fragments through a ring of kFD substeps in registers, kFD - 1
+//     substeps in flight while one is multiplied, with no barrier inside a
+//     layer, and the next layer's first kFD substeps go in flight before the
+//     current layer's epilogue.
 // Wavefront w owns the 16-column tiles w + kFW j (j < kFT) of a layer
-// below its width / 16, over the tile's 64 rows (4 MFMA tiles of 16 x 16
+// below its width / 16, over the tile's rows (kFI MFMA tiles of 16 x 16
 // each).  Per tile the products and their order (k ascending in steps of
 // 32) equal k_gemm's, so the outputs equal the layer-by-layer path bit for
 // bit.
 // ---------------------------------------------------------------------------
-constexpr int kFM = 64;              // rows per workgroup
+#ifndef MLP_FI
+#define MLP_FI 3
+#endif
+constexpr int kFI = MLP_FI;          // 16-row MFMA tiles per workgroup
+constexpr int kFM = 16 * kFI;        // rows per workgroup
+constexpr int kFR = 64;              // row slots per staged k block (one per lane of a wavefront)
 constexpr int kFH = 256;             // hidden width
 constexpr int kFW = 8;               // wavefronts per workgroup
 constexpr int kFT = kFH / 16 / kFW;  // 16-column tiles per wavefront (2)
@@ -199,64 +209,86 @@ constexpr int kFK0Max = 1152;        // widest input the LDS tile holds
 #endif
 constexpr int kFD = MLP_FD;          // 32-k substeps in the weight ring
 constexpr int kHRow = kFH + 8;       // LDS row of the hidden activations, padded
-constexpr int kFLds = kFK0Max / 8 * kFM * 8;   // bf16 values of the LDS tile (147,456 bytes)
+constexpr int kFLds = kFK0Max / 8 * kFR * 8;   // bf16 values of the LDS tile (147,456 bytes)
 static_assert(kFM * kHRow <= kFLds, "hidden activations must fit the input tile's LDS");
 
 struct FusedNet {
-  const __bf16 *W[4];   // [out][in] bf16
+  const __bf16 *W[4];   // bf16 in MFMA fragment order (k_weights_frag)
   const float *b[4];
   int in, out;          // widths of the input and output layers
 };
 
-// acc[i][j] += A(rows 16 i + .., k) W(rows 16 tile[j] + .., k) over k in
-// [0, K), K a multiple of 32 (KC: K known at compile time, else 0).  XS: A
-// is the staged input tile ([k / 8][row][8]), else the hidden activations
-// ([row][kHRow]).  Tiles with use[j] false are loaded (from a valid row)
-// but not multiplied.  The ring is refilled unconditionally (a substep past
-// the end reloads the last one), so every substep issues the same loads and
-// the wait before a substep's products covers only its own fragments, kFD
-// substeps old.
+// A wavefront's weight stream of one layer: its fragment of tile j at
+// substep 0 and the layer's number of 32-k substeps.
+struct FusedW {
+  const __bf16 *row[kFT];
+  int nsub;
+};
+
+__device__ __forceinline__ FusedW fused_w(const __bf16 *W, int K, const int tile[kFT]) {
+  FusedW fw;
+  fw.nsub = K >> 5;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < kFT; ++j) fw.row[j] = W + ((size_t)tile[j] * fw.nsub * 64 + lane) * 8;
+  return fw;
+}
+
+// Substep t's fragments (a substep past the end reloads the last one).
+__device__ __forceinline__ void fused_load(const FusedW &fw, int t, bf16x8 fr[kFT]) {
+  const int tt = min(t, fw.nsub - 1);
+#pragma unroll
+  for (int j = 0; j < kFT; ++j) fr[j] = *reinterpret_cast<const bf16x8 *>(fw.row[j] + (size_t)tt * 512);
+}
+
+// acc[i][j] += A(rows 16 i + .., k) W(rows 16 tile[j] + .., k) over the
+// layer's k, with ring[d] holding substep d on entry (the caller issues
+// those loads early: before the input tile's wait, or before the previous
+// layer's epilogue).  KC: the layer's k width if known at compile time,
+// else 0.  XS: A is the staged input tile ([k / 8][row][8]), else the
+// hidden activations ([row][kHRow]).  Tiles with use[j] false are loaded
+// (from a valid row) but not multiplied.  The ring is refilled
+// unconditionally, so every substep issues the same loads and the wait
+// before a substep's products covers only its own fragments, kFD substeps
+// old.
 template <bool XS, int KC>
-__device__ __forceinline__ void fused_layer(const __bf16 *__restrict__ W, int K_rt, const int tile[kFT],
-                                            const bool use[kFT], const __bf16 *lds, f32x4 acc[4][kFT]) {
-  const int K = KC ? KC : K_rt;
+__device__ __forceinline__ void fused_layer(const FusedW &fw, const bool use[kFT], const __bf16 *lds,
+                                            f32x4 acc[kFI][kFT], bf16x8 ring[kFD][kFT]) {
   const int lane = threadIdx.x & 63, r = lane & 15, kq = (lane >> 4) * 8;
-  const int nsub = K >> 5, nfull = nsub / kFD;
-  const __bf16 *wrow[kFT];
-#pragma unroll
-  for (int j = 0; j < kFT; ++j) wrow[j] = W + (size_t)(16 * tile[j] + r) * K + kq;
-  auto load = [&](int t, bf16x8 fr[kFT]) {
-    const int tt = min(t, nsub - 1);
-#pragma unroll
-    for (int j = 0; j < kFT; ++j) fr[j] = *reinterpret_cast<const bf16x8 *>(wrow[j] + 32 * tt);
-  };
+  const int nsub = KC ? KC >> 5 : fw.nsub, nfull = nsub / kFD;
   auto mul = [&](int t, const bf16x8 fr[kFT]) {
-    bf16x8 a[4];
+    bf16x8 a[kFI];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      a[i] = XS ? *reinterpret_cast<const bf16x8 *>(lds + ((((32 * t + kq) >> 3) * kFM) + 16 * i + r) * 8)
+    for (int i = 0; i < kFI; ++i)
+      a[i] = XS ? *reinterpret_cast<const bf16x8 *>(lds + ((((32 * t + kq) >> 3) * kFR) + 16 * i + r) * 8)
                 : *reinterpret_cast<const bf16x8 *>(lds + (16 * i + r) * kHRow + 32 * t + kq);
 #pragma unroll
     for (int j = 0; j < kFT; ++j)
       if (use[j])
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < kFI; ++i)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], fr[j], acc[i][j], 0, 0, 0);
   };
-  bf16x8 ring[kFD][kFT];
-#pragma unroll
-  for (int d = 0; d < kFD; ++d) load(d, ring[d]);
   for (int b = 0; b < nfull; ++b) {
 #pragma unroll
     for (int d = 0; d < kFD; ++d) {
       const int t = b * kFD + d;
       mul(t, ring[d]);
-      if (!KC || t + kFD < nsub) load(t + kFD, ring[d]);
+      if (!KC || t + kFD < nsub) fused_load(fw, t + kFD, ring[d]);
     }
   }
 #pragma unroll
   for (int d = 0; d < kFD; ++d)
     if (nfull * kFD + d < nsub) mul(nfull * kFD + d, ring[d]);
+}
+
+// Tiles of wavefront w in layer l (out of n_tiles): w + kFW j.
+__device__ __forceinline__ void fused_tiles(int w, int n_tiles, int tile[kFT], bool use[kFT]) {
+#pragma unroll
+  for (int j = 0; j < kFT; ++j) {
+    use[j] = w + kFW * j < n_tiles;
+    tile[j] = use[j] ? w + kFW * j : 0;
+  }
 }
 
 __global__ __launch_bounds__(64 * kFW) void k_mlp_fused4(FusedNet net, const __bf16 *__restrict__ X, int B,
@@ -267,33 +299,43 @@ __global__ __launch_bounds__(64 * kFW) void k_mlp_fused4(FusedNet net, const __b
   const int m0 = blockIdx.x * kFM;
   const int K0 = net.in, N3 = net.out;
   // stage the input tile: wavefront w takes k blocks w, w + kFW, ...; lane =
-  // row (rows past the batch repeat its last row; their outputs are dropped)
+  // row (lanes past the tile or the batch repeat its last row; their outputs
+  // are dropped)
   {
-    const __bf16 *xrow = X + (size_t)min(m0 + lane, B - 1) * K0;
+    const __bf16 *xrow = X + (size_t)min(m0 + min(lane, kFM - 1), B - 1) * K0;
     for (int kb = w; kb < K0 / 8; kb += kFW)
       __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(xrow + 8 * kb),
-                                       (__attribute__((address_space(3))) void *)(lds + kb * (kFM * 8)), 16, 0, 0);
+                                       (__attribute__((address_space(3))) void *)(lds + kb * (kFR * 8)), 16, 0, 0);
   }
-  __builtin_amdgcn_s_waitcnt(0);   // the direct-to-LDS loads have landed
+  int tile[kFT];
+  bool use[kFT];
+  fused_tiles(w, kFH / 16, tile, use);
+  FusedW fw = fused_w(net.W[0], K0, tile);
+  bf16x8 ring[kFD][kFT];
+#pragma unroll
+  for (int d = 0; d < kFD; ++d) fused_load(fw, d, ring[d]);
+  __builtin_amdgcn_s_waitcnt(0);   // the direct-to-LDS loads (and the first weights) have landed
   __syncthreads();
-  f32x4 acc[4][kFT];
+  f32x4 acc[kFI][kFT];
   for (int l = 0; l < 4; ++l) {
-    const int n_tiles = (l == 3 ? N3 : kFH) / 16;
-    int tile[kFT];
-    bool use[kFT];
 #pragma unroll
-    for (int j = 0; j < kFT; ++j) {
-      use[j] = w + kFW * j < n_tiles;
-      tile[j] = use[j] ? w + kFW * j : 0;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kFI; ++i)
 #pragma unroll
       for (int j = 0; j < kFT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (l == 0)
-      fused_layer<true, 0>(net.W[0], K0, tile, use, lds, acc);
+      fused_layer<true, 0>(fw, use, lds, acc, ring);
     else
-      fused_layer<false, kFH>(net.W[l], kFH, tile, use, lds, acc);
+      fused_layer<false, kFH>(fw, use, lds, acc, ring);
+    // the next layer's first weights go in flight before this epilogue
+    int tile_n[kFT];
+    bool use_n[kFT];
+    FusedW fw_n = fw;
+    if (l < 3) {
+      fused_tiles(w, (l == 2 ? N3 : kFH) / 16, tile_n, use_n);
+      fw_n = fused_w(net.W[l + 1], kFH, tile_n);
+#pragma unroll
+      for (int d = 0; d < kFD; ++d) fused_load(fw_n, d, ring[d]);
+    }
     const float *bias = net.b[l];
     if (l < 3) __syncthreads();   // every wavefront is done reading this layer's input
 #pragma unroll
@@ -302,7 +344,7 @@ __global__ __launch_bounds__(64 * kFW) void k_mlp_fused4(FusedNet net, const __b
       const int col = 16 * tile[j] + r;
       const float bb = bias[col];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < kFI; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int row = 16 * i + (lane >> 4) * 4 + q;
@@ -313,7 +355,15 @@ __global__ __launch_bounds__(64 * kFW) void k_mlp_fused4(FusedNet net, const __b
             Y[(size_t)(m0 + row) * N3 + col] = z;
         }
     }
-    if (l < 3) __syncthreads();   // the activations are the next layer's input
+    if (l < 3) {
+      __syncthreads();   // the activations are the next layer's input
+      fw = fw_n;
+#pragma unroll
+      for (int j = 0; j < kFT; ++j) {
+        tile[j] = tile_n[j];
+        use[j] = use_n[j];
+      }
+    }
   }
 }
 
@@ -392,6 +442,23 @@ __global__ void k_weights_bf16(const float *W, __bf16 *Wb, size_t n) {
   Wb[i] = (__bf16)W[i];
 }
 
+// W[N][K] (FP32) into BF16 MFMA fragment order for the fused kernel:
+// fragment (tile j, 32-k substep t, lane l) holds the 8 values
+// W[16 j + l % 16][32 t + 8 (l / 16) .. + 7] at ((j K/32 + t) 64 + l) 8,
+// so a wavefront's operand load for one tile and substep is 1 KiB
+// contiguous.  N % 16 == 0, K % 32 == 0.
+__global__ void k_weights_frag(const float *W, __bf16 *Wf, int N, int K) {
+  const size_t f = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const int nsub = K / 32;
+  if (f >= (size_t)N * K / 8) return;
+  const int lane = (int)(f % 64), t = (int)((f / 64) % nsub), j = (int)(f / 64 / nsub);
+  const float *src = W + (size_t)(16 * j + lane % 16) * K + 32 * t + 8 * (lane / 16);
+  bf16x8 v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = (__bf16)src[e];
+  *reinterpret_cast<bf16x8 *>(Wf + f * 8) = v;
+}
+
 inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 inline unsigned nb(size_t n, unsigned t = 256) { return (unsigned)((n + t - 1) / t); }
 
@@ -408,6 +475,7 @@ struct thor_mlp {
   std::vector<size_t> woff, boff;   // offsets of W_l, b_l in the packed arrays
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
   std::vector<__bf16 *> Wb;      // bf16 copies of W_l [out][in]
+  std::vector<__bf16 *> Wf;      // the same in MFMA fragment order (fused inference)
   std::vector<float *> Z;        // pre-activations, [B][w_{l+1}]
   std::vector<__bf16 *> H;       // hidden activations, [B][w_{l+1}]
   std::vector<float *> dZ;
@@ -446,6 +514,7 @@ size_t mlp_layout(thor_mlp *M, char *base) {
   M->m = (float *)take(M->n_params * 4);
   M->v = (float *)take(M->n_params * 4);
   M->Wb.assign(nl, nullptr);
+  M->Wf.assign(nl, nullptr);
   M->Z.assign(nl, nullptr);
   M->H.assign(nl, nullptr);
   M->dZ.assign(nl, nullptr);
@@ -453,6 +522,7 @@ size_t mlp_layout(thor_mlp *M, char *base) {
   for (int l = 0; l < nl; ++l) {
     const size_t wsz = (size_t)M->w[l] * M->w[l + 1];
     M->Wb[l] = (__bf16 *)take(wsz * 2);
+    M->Wf[l] = (__bf16 *)take(wsz * 2);
     M->Z[l] = (float *)take((size_t)B * M->w[l + 1] * 4);
     M->H[l] = (__bf16 *)take((size_t)B * M->w[l + 1] * 2);
     M->dZ[l] = (float *)take((size_t)B * M->w[l + 1] * 4);
@@ -493,6 +563,8 @@ void refresh_bf16(thor_mlp *M) {
   for (int l = 0; l < M->nl; ++l) {
     const size_t n = (size_t)M->w[l] * M->w[l + 1];
     hipLaunchKernelGGL(k_weights_bf16, dim3(nb(n)), dim3(256), 0, M->stream, M->p + M->woff[l], M->Wb[l], n);
+    hipLaunchKernelGGL(k_weights_frag, dim3(nb(n / 8)), dim3(256), 0, M->stream, M->p + M->woff[l], M->Wf[l],
+                       M->w[l + 1], M->w[l]);
   }
 }
 
@@ -522,7 +594,7 @@ void forward(thor_mlp *M, const __bf16 *X, int B, float *y) {
   if (y && fused_shape(M) && M->fused) {
     FusedNet net;
     for (int l = 0; l < 4; ++l) {
-      net.W[l] = M->Wb[l];
+      net.W[l] = M->Wf[l];
       net.b[l] = M->p + M->boff[l];
     }
     net.in = M->w[0];
