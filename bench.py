@@ -414,7 +414,12 @@ def main():
                          "and the g6 L32 benchmark (3 steps)")
     ap.add_argument("--physics-only", action="store_true",
                     help="only the hot-Jupiter and Held-Suarez benchmark setups (g5 L37)")
+    ap.add_argument("--corrector-mlp-only", action="store_true",
+                    help="only the corrector network's inference and training rates (g5 shape)")
     args = ap.parse_args()
+    if args.corrector_mlp_only:
+        print(json.dumps({"corrector_mlp": run_corrector_mlp()}), flush=True)
+        return
     if args.copy_probe:
         copy_probe()
         return
