@@ -201,7 +201,10 @@ constexpr int kFI = MLP_FI;          // 16-row MFMA tiles per workgroup
 constexpr int kFM = 16 * kFI;        // rows per workgroup
 constexpr int kFR = 64;              // row slots per staged k block (one per lane of a wavefront)
 constexpr int kFH = 256;             // hidden width
-constexpr int kFW = 8;               // wavefronts per workgroup
+#ifndef MLP_FW
+#define MLP_FW 8
+#endif
+constexpr int kFW = MLP_FW;          // wavefronts per workgroup
 constexpr int kFT = kFH / 16 / kFW;  // 16-column tiles per wavefront (2)
 constexpr int kFK0Max = 1152;        // widest input the LDS tile holds
 #ifndef MLP_FD
