@@ -30,7 +30,7 @@ def _ref_params(net):
 
 def test_forward_matches_reference():
     import torch
-    B = 100    # ragged against the 64-row tiles
+    B = 100    # ragged against the 64-row GEMM tiles and the 48-row fused tiles
     say(f"[mlp] forward widths={WIDTHS} B={B}")
     net, x, xr, t, tr = _net(B)
     y = torch.empty(B, WIDTHS[-1], dtype=torch.float32, device="cuda:0")
@@ -44,10 +44,11 @@ def test_forward_matches_reference():
 
 @pytest.mark.parametrize("B", [1, 100, 10242])
 def test_fused_inference_equals_layer_by_layer(B):
-    """The fused 4-layer inference kernel (one workgroup per 64-row tile,
-    hidden activations in LDS) against the layer-by-layer GEMMs: the same
-    products in the same order, so the same outputs, at a single row, a
-    ragged tile and the g5 corrector's 10242 columns."""
+    """The fused 4-layer inference kernel (one workgroup per 48-row tile,
+    inputs and hidden activations in LDS, weights in fragment order) against
+    the layer-by-layer GEMMs: the same products in the same order, so the
+    same outputs, at a single row, a ragged tile and the g5 corrector's
+    10242 columns."""
     import torch
     net, x, xr, t, tr = _net(B, seed=7)
     y1 = torch.empty(B, WIDTHS[-1], dtype=torch.float32, device="cuda:0")
