@@ -270,9 +270,10 @@ __device__ __forceinline__ void st4(float *p, int nv, const float v[kHq]) {
 // Phase M of one lane's kHq levels.  FIRST (the first substep: p* = 0, D
 // of the [t] state) and DD (divergence damping) are compile-time (0 or 1)
 // in the single-state kernel, so each form is straight-line code whose
-// gathers (the six p* rows, the 18 two-ring D rows) are unrolled: the
-// scheduler can put the rows of both gathers and of M, S_M in flight
-// together (FP64 unchanged, mixed 17.4 -> 15.9 us at g6 L32).  The
+// gathers are unrolled (the six p* rows; the 18 two-ring D rows six at a
+// time in FP64, all together in the mixed form): the scheduler can put
+// the rows of both gathers and of M, S_M in flight together (FP64
+// unchanged, mixed 17.4 -> 15.9 us at g6 L32).  The
 // ensemble kernel passes -1 for both (runtime flags, partly unrolled
 // gathers): there the four forms measured slower (1.31 -> 1.38-1.45 ms per
 // launch over 64 planets).  Every form adds its terms in the same order (j,
