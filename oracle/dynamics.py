@@ -29,7 +29,16 @@ notes):
   * divergence damping: DD = -Kd lap(grad D) per Cartesian component, with
     D the 3D momentum divergence of the current small-step state;
   * levels equally spaced in height, linear (k = 1) Lagrange interpolation
-    between centres and interfaces; W = 0 at the bottom and the lid.
+    between centres and interfaces; W = 0 at the bottom and the lid;
+  * anelastic switch: the mass flux of the continuity equation becomes
+    rho_r v with v = momentum / rho[t] and rho_r the isothermal hydrostatic
+    column of the initial state; the factors rho_r / rho[t] (centres, and
+    interpolated ratio at interior interfaces) are frozen over the large
+    step and scale the horizontal mass divergence, the vertical mass flux
+    of the density update and, so that both stay consistent, the buoyancy
+    the density change adds to the vertical momentum equation; the
+    divergence-damping D, rho theta, the momenta and the equation of state
+    are unchanged.
 
 State arrays: rho[n, L], M[n, L, 3] (horizontal momentum, Cartesian),
 rth[n, L] (rho theta), W[n, L+1] (rho v_r at interfaces).
@@ -68,6 +77,7 @@ class Numerics:
     hydrostatic: bool = False    # Sec. 3: hydrostatic approximation
     shallow: bool = False        # Sec. 3: shallow atmosphere, traditional approximation
     lagrange_order: int = 1      # Sec. 2.1: order k of the vertical interpolation
+    anelastic: bool = False      # Sec. 3: anelastic approximation (reading: mass flux rho_r v)
 
 
 @dataclass
@@ -142,6 +152,9 @@ class Model:
         dbar = grid_mod.mean_spacing(self.G.g, pl.radius)
         self.Kd = self.num.diff_D * dbar ** 4 / self.num.dt
         self.rhat = self.G.P
+        # anelastic reference column (model_from_workload sets it to the
+        # initial state's isothermal column)
+        self.rho_ref = None
         # Newtonian relaxation target (day/night contrast, height independent)
         lam, phi = lon_lat(self.rhat)
         f = self.forcing
@@ -172,9 +185,11 @@ class State:
 # ---------------------------------------------------------------------------
 # Initial state: isothermal, in discrete hydrostatic balance, plus noise
 # ---------------------------------------------------------------------------
-def init_state(model, init, planet_index=0):
+def isothermal_column(model, init):
+    """Density of the isothermal column at T0 in discrete hydrostatic
+    balance with the W equation, p at the first centre p_s exp(-g dz / 2 Rd T0)."""
     pl = model.planet
-    L, n = model.vert.n_lev, model.G.n
+    L = model.vert.n_lev
     RT = pl.Rd * init.T0
     half = 0.5 * pl.gravity * model.dz
     rho_col = np.empty(L)
@@ -182,6 +197,14 @@ def init_state(model, init, planet_index=0):
     for k in range(1, L):
         # p_k - p_{k-1} = -g dz (rho_{k-1} + rho_k) / 2 with p = rho Rd T0
         rho_col[k] = rho_col[k - 1] * (RT - half) / (RT + half)
+    return rho_col
+
+
+def init_state(model, init, planet_index=0):
+    pl = model.planet
+    L, n = model.vert.n_lev, model.G.n
+    RT = pl.Rd * init.T0
+    rho_col = isothermal_column(model, init)
     p_col = rho_col * RT
     eps = rng.column_noise(init.seed, n, L, init.noise_amp, planet_index)
     T = init.T0 + eps
@@ -430,8 +453,10 @@ def acoustic_substep(model, st, f, dtau, large):
     # (H) explicit horizontal momentum with the deviation pressure gradient
     M = st.M + dtau * (-op.grad(G, p - p_t, rC) + f["S_M"] + DD)
     M = op.proj_h(M, rhat)
-    # (Div) horizontal mass and theta fluxes of the new momentum
-    D_rho = op.div(G, M, rC)
+    # (Div) horizontal mass and theta fluxes of the new momentum (anelastic:
+    # the mass flux is rho_r / rho[t] times the momentum)
+    ane = model.num.anelastic
+    D_rho = op.div(G, large["fC"][..., None] * M, rC) if ane else op.div(G, M, rC)
     D_th = op.div(G, f["thetaC"][..., None] * M, rC)
     # (Pred) explicit parts of density and pressure
     rho_hat = st.rho + dtau * (-D_rho + f["S_rho"])
@@ -448,8 +473,11 @@ def acoustic_substep(model, st, f, dtau, large):
         j = np.arange(1, L)
         c1 = dtau / dz
         c2 = 0.5 * g * dtau
-        a = -c1 * Gam[:, j - 1] * am[j - 1] * th[:, j - 1] + c2 * am[j - 1]
-        c = -c1 * Gam[:, j] * ap[j] * th[:, j + 1] - c2 * ap[j]
+        # the density change of the vertical mass flux enters through the
+        # buoyancy: anelastic, that flux is rho_r / rho[t] times W
+        fI = large["fI"] if ane else np.ones((G.n, L + 1))
+        a = -c1 * Gam[:, j - 1] * am[j - 1] * th[:, j - 1] + c2 * am[j - 1] * fI[:, j - 1]
+        c = -c1 * Gam[:, j] * ap[j] * th[:, j + 1] - c2 * ap[j] * fI[:, j + 1]
         if model.num.hydrostatic:
             # no vertical acceleration (no time derivative, advection or
             # other slow terms of rho v_r): the new W is the one that leaves
@@ -457,19 +485,23 @@ def acoustic_substep(model, st, f, dtau, large):
             # imbalance I plus the deviation pressure gradient and buoyancy
             # summing to zero
             b = (c1 * th[:, j] * (Gam[:, j] * am[j] + Gam[:, j - 1] * ap[j - 1])
-                 + c2 * (am[j] - ap[j - 1]))
+                 + c2 * (am[j] - ap[j - 1]) * fI[:, j])
             d = (dtau * large["I"][:, j] - c1 * (p_hs[:, j] - p_hs[:, j - 1])
                  - c2 * (rho_hs[:, j - 1] + rho_hs[:, j]))
         else:
             b = (1.0 + c1 * th[:, j] * (Gam[:, j] * am[j] + Gam[:, j - 1] * ap[j - 1])
-                 + c2 * (am[j] - ap[j - 1]))
+                 + c2 * (am[j] - ap[j - 1]) * fI[:, j])
             d = (st.W[:, j] + dtau * f["S_W"][:, j] - c1 * (p_hs[:, j] - p_hs[:, j - 1])
                  - c2 * (rho_hs[:, j - 1] + rho_hs[:, j]))
         W[:, 1:L] = thomas(a, b, c, d)
     W[:, 0] = 0.0
     W[:, L] = 0.0
     # (Upd) density (Eq. dens2) and rho theta (Eq. pt2) with the new W
-    rho = rho_hat - ap * W[:, 1:] + am * W[:, :-1]
+    if ane:
+        fI = large["fI"]
+        rho = rho_hat - ap * fI[:, 1:] * W[:, 1:] + am * fI[:, :-1] * W[:, :-1]
+    else:
+        rho = rho_hat - ap * W[:, 1:] + am * W[:, :-1]
     rth = (st.rth + dtau * (-D_th + f["S_rth"])
            - ap * th[:, 1:] * W[:, 1:] + am * th[:, :-1] * W[:, :-1])
     return State(rho, M, rth, W)
@@ -490,8 +522,20 @@ def large_step_terms(model, st):
     if L > 1:
         I[:, 1:L] = (-(p_t[:, 1:] - p_t[:, :-1]) / model.dz
                      - 0.5 * g * (st.rho[:, :-1] + st.rho[:, 1:]))
-    return dict(p_t=p_t, rho_t=st.rho.copy(), H_rho=H_rho, H_M=H_M, H_W=H_W,
-                H_rth=H_rth, G_t=G_t, I=I)
+    out = dict(p_t=p_t, rho_t=st.rho.copy(), H_rho=H_rho, H_M=H_M, H_W=H_W,
+               H_rth=H_rth, G_t=G_t, I=I)
+    if model.num.anelastic:
+        # Sec. 3 anelastic approximation: the mass flux rho v of the
+        # continuity equation becomes rho_r v, with rho_r the reference
+        # column and v the momentum over the density of Phi[t]; the factors
+        # rho_r / rho[t] at the centres and interior interfaces are frozen
+        # over the large step (boundary interfaces only meet W = 0)
+        rr = np.repeat(model.rho_ref[None, :], G.n, axis=0)
+        fI = np.ones((G.n, L + 1))
+        if L > 1:
+            fI[:, 1:L] = interp_c2i(model, rr) / interp_c2i(model, st.rho)
+        out.update(fC=rr / st.rho, fI=fI)
+    return out
 
 
 def t_vert(f, z):
@@ -646,10 +690,12 @@ def model_from_workload(w, G):
     planet = Planet(w.radius, w.omega, w.gravity, w.Rd, w.Cp, w.p_ref)
     vert = Vertical(w.n_lev, w.z_top)
     num = Numerics(w.dt, w.diff_D, w.div_damp, w.energy_fixer, w.hydrostatic, w.shallow,
-                   w.lagrange_order)
+                   w.lagrange_order, getattr(w, "anelastic", False))
     forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar,
                       w.lapse, w.z_strat, w.dT_strat, w.sigma_strat, w.k_f, w.k_a, w.k_s, w.sigma_b,
                       w.dT_y, w.dtheta_z, w.p_star, w.T_top, w.T_min)
     model = Model(G, planet, vert, num, forcing)
-    st = init_state(model, Init(w.T0, w.p_surf, w.noise_amp, w.seed))
+    init = Init(w.T0, w.p_surf, w.noise_amp, w.seed)
+    model.rho_ref = isothermal_column(model, init)
+    st = init_state(model, init)
     return model, st
