@@ -506,7 +506,8 @@ def main():
         # the switchable approximations of the g6 L32 workload, FP64
         out["variants"] = {}
         for name, attr, val in (("hydrostatic", "hydrostatic", True), ("shallow", "shallow", True),
-                                ("cubic_vertical_interpolation", "lagrange_order", 3)):
+                                ("cubic_vertical_interpolation", "lagrange_order", 3),
+                                ("anelastic", "anelastic", True)):
             wv = workloads.gas_giant_c2()
             setattr(wv, attr, val)
             kv = max(1, args.steps // 2)

@@ -182,6 +182,23 @@ typedef struct {
                       at the ground and the lid; n_lev >= 4).  The buoyancy
                       of the vertical solve and the diagnostics keep the
                       two-point mean.  3 is not available in ensembles. */
+  int anelastic;    /* 1: the anelastic approximation of Sec. 3: the density
+                      in the mass-flux divergence of the continuity equation
+                      is a reference density rho_r(z) that depends on height
+                      only.  rho_r is the initial isothermal column (the
+                      density of thor_init's hydrostatic state before the
+                      noise); the flux is rho_r v with v = (rho v) / rho[t],
+                      rho[t] the density at the start of the large step, so
+                      each acoustic substep scales the horizontal mass
+                      divergence by rho_r / rho[t] at the centres and the
+                      vertical mass flux W, in the density update and in the
+                      buoyancy of the vertical solve, by the ratio of the
+                      two-point means at the interfaces.  Momenta, rho theta,
+                      the equation of state and the divergence damping are
+                      unchanged.  0: the paper's compressible continuity
+                      equation.  Needs lagrange_order 0 or 1; phase V then
+                      always runs the four-levels-per-lane mapping; not
+                      available in ensembles. */
 } thor_numerics;
 
 /* Physics after each large step (Sec. 5, Eq. im_eq_t): backward-Euler
@@ -307,7 +324,8 @@ int thor_state_import(thor_state *s, const void *blob, size_t bytes);
  * steps with n_acoustic substeps on this state, keep the fastest, and restore
  * the state from a checkpoint taken before tuning (the state is unchanged).
  * With linear interpolation the "vert" family also tries four levels per
- * lane, and for 32 < n_lev <= 64 two (thor_set_vert_levels_per_lane).
+ * lane, and for 32 < n_lev <= 64 two (thor_set_vert_levels_per_lane); with
+ * the anelastic switch it keeps four.
  * Synchronises.  wpb_out (4 ints, may be NULL) receives the choice in the
  * order above.  EINVAL: n_acoustic < 2 or odd. */
 int thor_autotune(thor_state *s, int n_acoustic, int *wpb_out);
@@ -322,7 +340,7 @@ int thor_autotune(thor_state *s, int n_acoustic, int *wpb_out);
  * ensemble member bitwise; thor_autotune may choose another (then the two
  * agree to rounding).
  * EINVAL: nl not 1, 2 or 4; 2 where n_lev <= 32; 2 or 4 where
- * lagrange_order is 3.  Synchronises. */
+ * lagrange_order is 3; 1 or 2 with the anelastic switch.  Synchronises. */
 int thor_set_vert_levels_per_lane(thor_state *s, int nl);
 
 /* Mean duration [ms] of the last n kernel launches of the named kernel family
@@ -350,8 +368,9 @@ int thor_batch_bytes(int n, const thor_grid *const *grids, const thor_vertical *
 
 /* Initialise member i exactly as thor_state_init would, inside one
  * caller-owned buffer (256-byte aligned).  EINVAL: any member's
- * configuration is invalid or precisions differ.  ENOMEM: dev_bytes too
- * small.  Synchronises. */
+ * configuration is invalid, uses a switch ensembles do not offer (energy
+ * fixer, shallow, lagrange_order 3, anelastic), or precisions differ.
+ * ENOMEM: dev_bytes too small.  Synchronises. */
 int thor_batch_init(int n, const thor_grid *const *grids, const thor_planet *planets,
                     const thor_vertical *v, const thor_numerics *num,
                     const thor_forcing *forcings, const thor_init *inits,

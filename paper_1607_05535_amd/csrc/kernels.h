@@ -57,6 +57,13 @@ struct Fields {
   double *partial;        // per-block partial sums
   double *epart;          // energy fixer: partial sums of the step's start and of
                           // the dynamics output, then the temperature increment
+  // anelastic switch only (null otherwise): the reference column rho_r [S]
+  // (padding levels repeat the top level) and, frozen per large step,
+  // rho_r / rho[t] at the centres and the ratio of the two-point means at
+  // interface slot j (slot 0, the ground, holds 1)
+  const double *rref;
+  H *fC;                  // [N][L]
+  double *fI;             // [N][L]
 };
 
 struct Consts {
@@ -72,6 +79,7 @@ struct Consts {
   int hydrostatic;        // 1: no vertical acceleration in the acoustic substeps
   int shallow;            // 1: shallow atmosphere (r = radius), traditional Coriolis
   int vorder;             // order of the vertical Lagrange interpolation (1 or 3)
+  int anelastic;          // 1: reference-density mass flux (needs vorder 1 and vnl 4)
   int vnl, vlpc, vcpw;    // phase V: levels per lane (1 or 2); with 2, lanes per column and columns per wavefront
   int forcing;
   double tau;

@@ -845,7 +845,11 @@ __device__ __forceinline__ VLane map_vlane(const Consts &c, int lb) {
   return r;
 }
 
-template <typename H, bool LAST>
+// ANEL (the anelastic switch): the density update takes the divergence of
+// the reference-density mass flux, fC M horizontally and fI W vertically,
+// and the buoyancy terms of the tridiagonal the matching fI W; the
+// divergence-damping D keeps the plain momentum divergence.
+template <typename H, bool LAST, bool ANEL = false>
 __device__ __forceinline__ void b_vert4(const Fields<H> &f, const Consts &c, const VLane &ln, double dtau,
                                         int first) {
   const int L = c.L, col = ln.col, lev0 = ln.lev0;
@@ -870,35 +874,39 @@ __device__ __forceinline__ void b_vert4(const Fields<H> &f, const Consts &c, con
     gm[k] = rI * rI * irc2dz;
   }
 
-  // horizontal divergences of M and theta_L M
-  H drho[kHq], dth[kHq], thl[kHq];
+  // horizontal divergences of M and theta_L M (ANEL: and of fC M)
+  H drho[kHq], dth[kHq], thl[kHq], dmass[kHq];
   {
-    H mx[kHq], my[kHq], mz[kHq];
+    H mx[kHq], my[kHq], mz[kHq], fc[kHq];
     ld4<true>(f.Mx + idx, kHq, mx);
     ld4<true>(f.My + idx, kHq, my);
     ld4<true>(f.Mz + idx, kHq, mz);
     ld4<true>(f.thL + idx, kHq, thl);
+    if (ANEL) ld4<true>(f.fC + idx, kHq, fc);
     const H c0x = dc[0], c0y = dc[1], c0z = dc[2];
 #pragma unroll
     for (int q = 0; q < kHq; ++q) {
       const H t = c0x * mx[q] + c0y * my[q] + c0z * mz[q];
       drho[q] = t;
       dth[q] = thl[q] * t;
+      if (ANEL) dmass[q] = fc[q] * t;
     }
 #pragma unroll VERT4_UNROLL
     for (int j = 0; j < 6; ++j) {
       const size_t nj = (size_t)nb[j] * c.S + lev0;
-      H nx[kHq], ny[kHq], nz[kHq], nt[kHq];
+      H nx[kHq], ny[kHq], nz[kHq], nt[kHq], nf[kHq];
       ld4<true>(f.Mx + nj, kHq, nx);
       ld4<true>(f.My + nj, kHq, ny);
       ld4<true>(f.Mz + nj, kHq, nz);
       ld4<true>(f.thL + nj, kHq, nt);
+      if (ANEL) ld4<true>(f.fC + nj, kHq, nf);
       const H cx = dc[3 * (j + 1)], cy = dc[3 * (j + 1) + 1], cz = dc[3 * (j + 1) + 2];
 #pragma unroll
       for (int q = 0; q < kHq; ++q) {
         const H u = cx * nx[q] + cy * ny[q] + cz * nz[q];
         drho[q] += u;
         dth[q] += nt[q] * u;
+        if (ANEL) dmass[q] += nf[q] * u;
       }
     }
 #pragma unroll
@@ -906,6 +914,7 @@ __device__ __forceinline__ void b_vert4(const Fields<H> &f, const Consts &c, con
       const H ir = (H)irc[q + 1];
       drho[q] *= ir;
       dth[q] *= ir;
+      if (ANEL) dmass[q] *= ir;
     }
   }
 
@@ -947,7 +956,7 @@ __device__ __forceinline__ void b_vert4(const Fields<H> &f, const Consts &c, con
     for (int q = 0; q < kHq; ++q) {
       gam[q] = (double)gh[q];
       thC[q] = (double)thl[q];
-      const double Dr = (double)drho[q], Dt = (double)dth[q], Hr = (double)hrth[q];
+      const double Dr = (double)(ANEL ? dmass[q] : drho[q]), Dt = (double)dth[q], Hr = (double)hrth[q];
       rho_hat[q] = rho0[q] + dtau * (-Dr + (double)hrho[q]);
       rth_hat[q] = rth0[q] + dtau * (-Dt + Hr);
       phs[q] = (double)psh[q] + dtau * gam[q] * (-Dt + Hr);
@@ -966,6 +975,15 @@ __device__ __forceinline__ void b_vert4(const Fields<H> &f, const Consts &c, con
 
   const double c1 = dtau * idz, c2 = 0.5 * c.grav * dtau;
 
+  // ANEL: the mass-flux factors of the lane's interfaces and of interfaces
+  // lev0 - 1 and lev0 + 4
+  double fI[kHq] = {1.0, 1.0, 1.0, 1.0}, fI_dn = 1.0, fI_up = 1.0;
+  if (ANEL) {
+    ld4<true>(f.fI + idx, kHq, fI);
+    fI_dn = shfl(fI[3], lm);
+    fI_up = shfl(fI[0], lp);
+  }
+
   // rows of interfaces lev0 + q: a x[j-1] + b x[j] + cc x[j+1] = d
   const double thI_dn = shfl(thI[3], lm);   // interface lev0 - 1
   double a[kHq], b[kHq], cc[kHq], d[kHq];
@@ -976,15 +994,24 @@ __device__ __forceinline__ void b_vert4(const Fields<H> &f, const Consts &c, con
     const double apm = dtau * gp[q], amm = dtau * gm[q];         // cell j - 1
     const double gmq = q ? gam[q - 1] : gam_m, phsm = q ? phs[q - 1] : phs_m, rhsm = q ? rhs[q - 1] : rhs_m;
     const double thIm = q ? thI[q - 1] : thI_dn, thIp = q < kHq - 1 ? thI[q + 1] : thI_up;
+    // ANEL: the buoyancy terms (c2) see the density change of fI W
+    const double fIm = q ? fI[q - 1] : fI_dn, fIp = q < kHq - 1 ? fI[q + 1] : fI_up;
     a[q] = 0.0;
     b[q] = 1.0;
     cc[q] = 0.0;
     d[q] = 0.0;
     if (ln.real_col && j > 0 && j < L) {
-      a[q] = j == 1 ? 0.0 : -c1 * gmq * amm * thIm + c2 * amm;
-      b[q] = c.hydrostatic ? c1 * thI[q] * (gam[q] * am + gmq * apm) + c2 * (am - apm)
-                           : 1.0 + c1 * thI[q] * (gam[q] * am + gmq * apm) + c2 * (am - apm);
-      cc[q] = j == L - 1 ? 0.0 : -c1 * gam[q] * ap * thIp - c2 * ap;
+      if (ANEL) {
+        a[q] = j == 1 ? 0.0 : -c1 * gmq * amm * thIm + c2 * amm * fIm;
+        b[q] = c.hydrostatic ? c1 * thI[q] * (gam[q] * am + gmq * apm) + c2 * (am - apm) * fI[q]
+                             : 1.0 + c1 * thI[q] * (gam[q] * am + gmq * apm) + c2 * (am - apm) * fI[q];
+        cc[q] = j == L - 1 ? 0.0 : -c1 * gam[q] * ap * thIp - c2 * ap * fIp;
+      } else {
+        a[q] = j == 1 ? 0.0 : -c1 * gmq * amm * thIm + c2 * amm;
+        b[q] = c.hydrostatic ? c1 * thI[q] * (gam[q] * am + gmq * apm) + c2 * (am - apm)
+                             : 1.0 + c1 * thI[q] * (gam[q] * am + gmq * apm) + c2 * (am - apm);
+        cc[q] = j == L - 1 ? 0.0 : -c1 * gam[q] * ap * thIp - c2 * ap;
+      }
       d[q] = d0[q] - c1 * (phs[q] - phsm) - c2 * (rhsm + rhs[q]);
     }
   }
@@ -1057,7 +1084,12 @@ __device__ __forceinline__ void b_vert4(const Fields<H> &f, const Consts &c, con
     Wp[q] = j + 1 < L ? (q < kHq - 1 ? x[q + 1] : x4) : 0.0;
     const double thIp = j + 1 < L ? (q < kHq - 1 ? thI[q + 1] : thI_up) : 0.0;
     const double ap = dtau * gp[q + 1], am = dtau * gm[q + 1];
-    rho_new[q] = rho_hat[q] - ap * Wp[q] + am * Wn[q];
+    if (ANEL) {
+      const double fIp = q < kHq - 1 ? fI[q + 1] : fI_up;
+      rho_new[q] = rho_hat[q] - ap * fIp * Wp[q] + am * fI[q] * Wn[q];
+    } else {
+      rho_new[q] = rho_hat[q] - ap * Wp[q] + am * Wn[q];
+    }
     rth_new[q] = rth_hat[q] - ap * thIp * Wp[q] + am * thI[q] * Wn[q];
     p[q] = c.p_ref * powd(c.Rd * rth_new[q] / c.p_ref, c.gamma);
   }
@@ -1419,6 +1451,33 @@ __device__ __forceinline__ void large0_cells(const Fields<H> &f, const Consts &c
   st4<VEC>(f.wI + idx, nv, wI);
 }
 
+// Anelastic switch only (Sec. 3 anelastic approximation): the mass flux is
+// rho_r v with v the momentum over rho[t]; its factors rho_r / rho[t] at the
+// centres and the ratio of the two-point means at the interior interfaces
+// are frozen for the large step (interface 0 only meets W = 0).
+template <typename H, bool VEC>
+__device__ __forceinline__ void anel_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
+  const int lev0 = ln.lev0, nv = ln.nv;
+  const size_t idx = (size_t)ln.col * c.S + lev0;
+  const int lane = threadIdx.x & 63;
+  const int lm = lane > 0 ? lane - 1 : 0;
+  const double rho_m = shfl(f.rho_t[idx + kHq - 1], lm);   // every lane shuffles
+  if (!ln.store) return;
+  double rho[kHq], rr[kHq], fi[kHq];
+  H fc[kHq];
+  ld4<VEC>(f.rho_t + idx, nv, rho);
+  ld4<VEC>(f.rref + lev0, nv, rr);
+  const double rr_m = lev0 ? f.rref[lev0 - 1] : 0.0;
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) {
+    fc[q] = (H)(rr[q] / rho[q]);
+    const double rhoI = 0.5 * ((q ? rho[q - 1] : rho_m) + rho[q]);
+    fi[q] = lev0 + q == 0 ? 1.0 : 0.5 * ((q ? rr[q - 1] : rr_m) + rr[q]) / rhoI;
+  }
+  st4<VEC>(f.fC + idx, nv, fc);
+  st4<VEC>(f.fI + idx, nv, fi);
+}
+
 // sum_j l_j (s_j - s_0) at kHq consecutive levels: the Laplacian without
 // its 1/r^2.
 template <bool VEC, typename T, typename H>
@@ -1668,6 +1727,7 @@ __device__ __forceinline__ void large2_cells(const Fields<H> &f, const Consts &c
     NAME##_cells<H, true>(f, c, ln);   /* rows of stride S: whole groups of kHq */            \
   }
 THOR_HBODY(large0)
+THOR_HBODY(anel)
 THOR_HBODY(large1)
 THOR_HBODY(large2)
 #undef THOR_HBODY
@@ -1888,6 +1948,7 @@ __device__ __forceinline__ void b_import(const Fields<H> &f, const Consts &c, co
 #define COMMA ,
 THOR_KERNEL(slow, sizeof(H) == 8 ? 2 : 4, map_hlane, COMMA int from_t, COMMA from_t)
 THOR_KERNEL(large0, 4, map_hlane, , )
+THOR_KERNEL(anel, 8, map_hlane, , )
 THOR_KERNEL(large1, sizeof(H) == 8 ? LARGE1_OCC_D : LARGE1_OCC_F, map_hlane, , )
 THOR_KERNEL(large2, 5, map_hlane, , )
 THOR_KERNEL(diag, 8, map_lane, COMMA int field, COMMA field)
@@ -1929,10 +1990,10 @@ void k_vert2(Fields<H> f, Consts c, int div, int first) {
   b_vert2<H, LAST>(f, c, map_lane2(c, xcd_block()), c.dt / div, first);
 }
 // phase V on the gather mapping (kHq levels per lane)
-template <typename H, bool LAST>
+template <typename H, bool LAST, bool ANEL = false>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(VERT4_OCC)))
 void k_vert4(Fields<H> f, Consts c, int div, int first) {
-  b_vert4<H, LAST>(f, c, map_vlane(c, xcd_block()), c.dt / div, first);
+  b_vert4<H, LAST, ANEL>(f, c, map_vlane(c, xcd_block()), c.dt / div, first);
 }
 // phase V with the cubic interface theta (single states only)
 template <typename H, bool LAST>
@@ -1977,7 +2038,9 @@ void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool fir
   const bool fr = last && c.forcing == THOR_FORCING_HELD_SUAREZ;
   hipEvent_t e1 = fr ? nullptr : ev1;   // with the friction kernel, the family ends with it
   if (last) {
-    if (c.vnl == 4)
+    if (c.anelastic)
+      dispatch(k_vert4<H, true, true>, g, b, s, ev0, e1, f, c, div, (int)first);
+    else if (c.vnl == 4)
       dispatch(k_vert4<H, true>, g, b, s, ev0, e1, f, c, div, (int)first);
     else if (c.vnl == 2)
       dispatch(k_vert2<H, true>, g, b, s, ev0, e1, f, c, div, (int)first);
@@ -1987,7 +2050,9 @@ void launch_vert(const Fields<H> &f, const Consts &c, int wpb, int div, bool fir
       dispatch(k_vert<H, true>, g, b, s, ev0, e1, f, c, div, (int)first);
     if (fr) dispatch(k_friction<H>, dim3(n_blocks_h(c, 4)), dim3(256), s, nullptr, ev1, f, c);
   } else {
-    if (c.vnl == 4)
+    if (c.anelastic)
+      dispatch(k_vert4<H, false, true>, g, b, s, ev0, ev1, f, c, div, (int)first);
+    else if (c.vnl == 4)
       dispatch(k_vert4<H, false>, g, b, s, ev0, ev1, f, c, div, (int)first);
     else if (c.vnl == 2)
       dispatch(k_vert2<H, false>, g, b, s, ev0, ev1, f, c, div, (int)first);
@@ -2014,6 +2079,7 @@ template <typename H>
 void launch_large(const Fields<H> &f, const Consts &c, int wpb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const dim3 g(n_blocks_h(c, wpb)), b(64 * wpb);
   dispatch(k_large0<H>, g, b, s, ev0, nullptr, f, c);
+  if (c.anelastic) dispatch(k_anel<H>, g, b, s, nullptr, nullptr, f, c);
   dispatch(k_large1<H>, g, b, s, nullptr, nullptr, f, c);
   dispatch(k_large2<H>, g, b, s, nullptr, ev1, f, c);
 }

@@ -54,7 +54,7 @@ struct Carver {
 inline size_t row_stride(size_t L) { return (L + kHq - 1) / kHq * kHq; }
 
 template <typename H>
-void carve(Carver &cv, Fields<H> &f, size_t N, size_t L) {
+void carve(Carver &cv, Fields<H> &f, size_t N, size_t L, bool anelastic) {
   const size_t NL = N * row_stride(L), NLc = N * L;
   f.nbr = cv.take<int32_t>(N * 6);
   f.dc = cv.take<H>(N * 21);
@@ -107,6 +107,10 @@ void carve(Carver &cv, Fields<H> &f, size_t N, size_t L) {
   f.diag = cv.take<double>(6 * NLc);
   f.partial = cv.take<double>(2 * ((N + 3) / 4 + 16));
   f.epart = cv.take<double>(4 * ((N + 3) / 4 + 16) + 8);
+  // after everything else, so that the other arrays keep their offsets
+  f.rref = anelastic ? cv.take<double>(row_stride(L)) : nullptr;
+  f.fC = anelastic ? cv.take<H>(NL) : nullptr;
+  f.fI = anelastic ? cv.take<double>(NL) : nullptr;
 }
 
 template <typename H>
@@ -149,9 +153,11 @@ bool validate(const thor_planet *pl, const thor_vertical *v, const thor_numerics
       (num->div_damp != 0 && num->div_damp != 1) || (num->energy_fixer != 0 && num->energy_fixer != 1) ||
       (num->hydrostatic != 0 && num->hydrostatic != 1) || (num->shallow != 0 && num->shallow != 1) ||
       (num->lagrange_order < 0 || num->lagrange_order > 3 || num->lagrange_order == 2) ||
-      (num->lagrange_order == 3 && v->n_lev < 4)) {
+      (num->lagrange_order == 3 && v->n_lev < 4) || (num->anelastic != 0 && num->anelastic != 1) ||
+      (num->anelastic && num->lagrange_order == 3)) {
     set_error("thor_state_init: numerics need dt > 0, diff_D >= 0, precision FP64|MIXED, div_damp 0|1, "
-              "energy_fixer 0|1, hydrostatic 0|1, shallow 0|1, lagrange_order 0, 1 or 3 (3: n_lev >= 4)");
+              "energy_fixer 0|1, hydrostatic 0|1, shallow 0|1, lagrange_order 0, 1 or 3 (3: n_lev >= 4), "
+              "anelastic 0|1 (1: lagrange_order 0 or 1)");
     return false;
   }
   if (fo->kind != THOR_FORCING_NONE && fo->kind != THOR_FORCING_NEWTONIAN && fo->kind != THOR_FORCING_HOT_JUPITER &&
@@ -192,14 +198,14 @@ bool validate(const thor_planet *pl, const thor_vertical *v, const thor_numerics
   return true;
 }
 
-size_t bytes_for(int precision, size_t N, size_t L) {
+size_t bytes_for(int precision, size_t N, size_t L, bool anelastic) {
   Carver cv{nullptr};
   if (precision == THOR_MIXED) {
     Fields<float> f;
-    carve(cv, f, N, L);
+    carve(cv, f, N, L, anelastic);
   } else {
     Fields<double> f;
-    carve(cv, f, N, L);
+    carve(cv, f, N, L, anelastic);
   }
   return cv.off;
 }
@@ -209,7 +215,7 @@ int upload(thor_state *s, const Grid &G, const thor_planet *pl, const thor_verti
            const thor_forcing *fo, const thor_init *in, char *base, Fields<H> *fp) {
   Carver cv{base};
   const size_t N = G.n, L = v->n_lev, S = row_stride(L), NL = N * S;
-  carve(cv, fp[0], N, L);
+  carve(cv, fp[0], N, L, s->c.anelastic != 0);
   // every array starts at zero (padding levels included)
   if (!hip_ok(hipMemsetAsync(base, 0, cv.off, s->stream), "clear state")) return THOR_EHIP;
   fp[1] = swapped(fp[0]);
@@ -241,6 +247,9 @@ int upload(thor_state *s, const Grid &G, const thor_planet *pl, const thor_verti
   rcol[0] = in->p_surf * std::exp(-half / RT) / RT;
   for (size_t k = 1; k < L; ++k) rcol[k] = rcol[k - 1] * (RT - half) / (RT + half);
   for (size_t k = 0; k < L; ++k) pcol[k] = rcol[k] * RT;
+  // anelastic reference column: the same isothermal column, padded to S
+  std::vector<double> rref(S);
+  for (size_t k = 0; k < S; ++k) rref[k] = rcol[k < L ? k : L - 1];
   std::vector<double> rho(NL), rth(NL), zero(NL, 0.0);
   std::vector<H> zeroH(NL, (H)0);
   const uint64_t pbase = (uint64_t)in->planet_index << 40;
@@ -275,6 +284,8 @@ int upload(thor_state *s, const Grid &G, const thor_planet *pl, const thor_verti
             hip_ok(hipMemcpyAsync(f.My_t, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy My") &&
             hip_ok(hipMemcpyAsync(f.Mz_t, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy Mz") &&
             hip_ok(hipMemcpyAsync(f.ps, zeroH.data(), NL * sizeof(H), hipMemcpyHostToDevice, st), "copy ps") &&
+            (!f.rref || hip_ok(hipMemcpyAsync((void *)f.rref, rref.data(), S * sizeof(double),
+                                              hipMemcpyHostToDevice, st), "copy rref")) &&
             hip_ok(hipStreamSynchronize(st), "init synchronize");
   return ok ? THOR_OK : THOR_EHIP;
 }
@@ -487,7 +498,7 @@ int thor_state_bytes(const thor_grid *g, const thor_vertical *v, const thor_nume
   if (!g || !v || !num || !bytes) { set_error("thor_state_bytes: NULL argument"); return THOR_EINVAL; }
   if (v->n_lev < 1 || v->n_lev > 64) { set_error("thor_state_bytes: n_lev must be 1..64"); return THOR_EINVAL; }
   if (num->precision != THOR_FP64 && num->precision != THOR_MIXED) { set_error("thor_state_bytes: bad precision"); return THOR_EINVAL; }
-  *bytes = bytes_for(num->precision, (size_t)g->g.n, (size_t)v->n_lev);
+  *bytes = bytes_for(num->precision, (size_t)g->g.n, (size_t)v->n_lev, num->anelastic == 1);
   return THOR_OK;
 }
 
@@ -499,7 +510,7 @@ int thor_state_init(const thor_grid *g, const thor_planet *pl, const thor_vertic
   *out = nullptr;
   if (!validate(pl, v, num, fo, in)) return THOR_EINVAL;
   if (((uintptr_t)dev_buf & 255) != 0) { set_error("thor_state_init: dev_buf must be 256-byte aligned"); return THOR_EINVAL; }
-  const size_t need = bytes_for(num->precision, (size_t)g->g.n, (size_t)v->n_lev);
+  const size_t need = bytes_for(num->precision, (size_t)g->g.n, (size_t)v->n_lev, num->anelastic == 1);
   if (dev_bytes < need) {
     set_error("thor_state_init: dev_bytes smaller than thor_state_bytes");
     return THOR_ENOMEM;
@@ -535,6 +546,7 @@ int thor_state_init(const thor_grid *g, const thor_planet *pl, const thor_vertic
   c.shallow = num->shallow;
   c.rdz = num->shallow ? 0.0 : c.dz;
   c.vorder = num->lagrange_order == 3 ? 3 : 1;
+  c.anelastic = num->anelastic;
   // phase V: four levels per lane (the gather mapping), as in the ensemble
   // kernels, so that a planet's results equal its ensemble member's bitwise;
   // with cubic interpolation one level per lane.  thor_autotune may choose
@@ -618,8 +630,10 @@ int thor_autotune(thor_state *s, int n_acoustic, int *iters_out) {
   const bool timing0 = s->timing;
   // phase V may also choose its mapping: one level per lane, two (L > 32)
   // or four (the gather mapping), with linear interpolation
-  const bool two_ok = s->c.L > 32 && s->c.vorder == 1;
+  // (the anelastic switch has the four-level mapping only)
+  const bool two_ok = s->c.L > 32 && s->c.vorder == 1 && !s->c.anelastic;
   const bool four_ok = s->c.vorder == 1;
+  const bool one_ok = !s->c.anelastic;
   for (int fam = 0; fam < FAM_COUNT; ++fam) {
     double best = 1e30;
     int best_it = s->wpb[fam], best_nl = s->c.vnl;
@@ -627,6 +641,7 @@ int thor_autotune(thor_state *s, int n_acoustic, int *iters_out) {
       const int it = cand[k & 3], nl = k < 4 ? 1 : k < 8 ? 2 : 4;
       if (nl != 1 && fam != FAM_VERT) continue;
       if ((nl == 2 && !two_ok) || (nl == 4 && !four_ok)) continue;
+      if (nl == 1 && fam == FAM_VERT && !one_ok) continue;
       if (fam == FAM_VERT) s->c.vnl = nl;
       s->wpb[fam] = it;
       s->timing = true;
@@ -696,9 +711,10 @@ int thor_state_import(thor_state *s, const void *blob, size_t bytes) {
 int thor_set_vert_levels_per_lane(thor_state *s, int nl) {
   clear_error();
   if (!s) { set_error("thor_set_vert_levels_per_lane: NULL state"); return THOR_EINVAL; }
-  if (nl != 1 && ((nl != 2 && nl != 4) || s->c.vorder != 1 || (nl == 2 && s->c.L <= 32))) {
+  if ((nl != 1 && ((nl != 2 && nl != 4) || s->c.vorder != 1 || (nl == 2 && s->c.L <= 32))) ||
+      (s->c.anelastic && nl != 4)) {
     set_error("thor_set_vert_levels_per_lane: 1, 4 with linear interpolation, or 2 with 33..64 levels and linear "
-              "interpolation");
+              "interpolation; 4 only with the anelastic switch");
     return THOR_EINVAL;
   }
   if (!hip_ok(hipStreamSynchronize(s->stream), "vert mapping synchronize")) return THOR_EHIP;
@@ -877,9 +893,9 @@ int thor_batch_init(int n, const thor_grid *const *grids, const thor_planet *pl,
   if (dev_bytes < need) { set_error("thor_batch_init: dev_bytes smaller than thor_batch_bytes"); return THOR_ENOMEM; }
   for (int i = 0; i < n; ++i) {
     if (!validate(&pl[i], &v[i], &num[i], &fo[i], &in[i])) return THOR_EINVAL;
-    if (num[i].energy_fixer || num[i].shallow || num[i].lagrange_order == 3) {
-      set_error("thor_batch_init: the energy fixer, the shallow-atmosphere form and cubic vertical "
-                "interpolation are not available in ensembles");
+    if (num[i].energy_fixer || num[i].shallow || num[i].lagrange_order == 3 || num[i].anelastic) {
+      set_error("thor_batch_init: the energy fixer, the shallow-atmosphere form, cubic vertical "
+                "interpolation and the anelastic switch are not available in ensembles");
       return THOR_EINVAL;
     }
   }

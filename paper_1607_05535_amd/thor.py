@@ -63,7 +63,7 @@ class Vertical(ctypes.Structure):
 class Numerics(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("diff_D", ctypes.c_double), ("div_damp", ctypes.c_int),
                 ("precision", ctypes.c_int), ("energy_fixer", ctypes.c_int), ("hydrostatic", ctypes.c_int),
-                ("shallow", ctypes.c_int), ("lagrange_order", ctypes.c_int)]
+                ("shallow", ctypes.c_int), ("lagrange_order", ctypes.c_int), ("anelastic", ctypes.c_int)]
 
 
 class Forcing(ctypes.Structure):
@@ -372,7 +372,7 @@ def structs_from_workload(w, precision=THOR_FP64):
     planet = Planet(w.radius, w.omega, w.gravity, w.Rd, w.Cp, w.p_ref)
     vert = Vertical(w.n_lev, w.z_top)
     num = Numerics(w.dt, w.diff_D, int(w.div_damp), precision, int(w.energy_fixer), int(w.hydrostatic),
-                   int(w.shallow), int(w.lagrange_order))
+                   int(w.shallow), int(w.lagrange_order), int(getattr(w, "anelastic", False)))
     forcing = Forcing(w.forcing_kind, w.tau, w.T_mean, w.dT_daynight, w.lon_substellar,
                       w.lapse, w.z_strat, w.dT_strat, w.sigma_strat, w.k_f, w.k_a, w.k_s, w.sigma_b,
                       w.dT_y, w.dtheta_z, w.p_star, w.T_top, w.T_min)

@@ -6,7 +6,8 @@ of a full-size workload at seeded sample cells.
     python tests/golden/make_full_size_samples.py hs_g5l37   # Held-Suarez, 10242 x 37
     python tests/golden/make_full_size_samples.py hj_g5l37   # hot Jupiter, 10242 x 37
     python tests/golden/make_full_size_samples.py g6l32_fixer   # also _hydrostatic, _shallow,
-                                                                # _cubic: g6 L32 with a switch on
+                                                                # _cubic, _anelastic: g6 L32
+                                                                # with a switch on
     python tests/golden/make_full_size_samples.py ensemble_member0_g6l48   # first planet of the
                                                                            # 64-planet ensemble
 
@@ -36,6 +37,7 @@ def _workload(case):
             "g6l32_hydrostatic": lambda: _switched("hydrostatic", True),
             "g6l32_shallow": lambda: _switched("shallow", True),
             "g6l32_cubic": lambda: _switched("lagrange_order", 3),
+            "g6l32_anelastic": lambda: _switched("anelastic", True),
             "ensemble_member0_g6l48": lambda: workloads.ensemble()[0]}[case]()
 
 
@@ -48,7 +50,8 @@ def _switched(attr, value):
 
 
 CASES = ("g6l32", "g7l48", "hs_g5l37", "hj_g5l37",
-         "g6l32_fixer", "g6l32_hydrostatic", "g6l32_shallow", "g6l32_cubic", "ensemble_member0_g6l48")
+         "g6l32_fixer", "g6l32_hydrostatic", "g6l32_shallow", "g6l32_cubic", "g6l32_anelastic",
+         "ensemble_member0_g6l48")
 # the hot Jupiter starts at rest with no noise: its winds appear in the
 # second step, once the first step's relaxation has set up the day/night
 # contrast

@@ -177,6 +177,42 @@ def test_state_bytes_and_config_errors():
     assert e.value.code == thor.THOR_ENOMEM
 
 
+def test_anelastic_switch_layout_and_config_errors():
+    """The anelastic switch adds its reference column and per-step factors
+    at the end of the state, and is refused (before any device work) with
+    cubic vertical interpolation, in ensembles and for values other than
+    0 and 1."""
+    thor = _thor()
+    G = thor.Grid(2)
+    v = thor.Vertical(20, 36e3)
+    planet = thor.Planet(6.371e6, 7.292e-5, 9.8, 287.0, 1005.0, 1e5)
+    forcing = thor.Forcing(0, 1e5, 0, 0, 0)
+    init = thor.Init(300.0, 1e5, 0.1, 1, 0)
+    for prec, hb in ((thor.THOR_FP64, 8), (thor.THOR_MIXED, 4)):
+        num = thor.Numerics(600.0, 0.0048, 1, prec)
+        b0 = thor.thor_state_bytes(G.handle, v, num)
+        num.anelastic = 1
+        b1 = thor.thor_state_bytes(G.handle, v, num)
+        n, S = G.n, 20
+        al = lambda x: (x + 255) // 256 * 256
+        assert b1 - b0 == al(S * 8) + al(n * S * hb) + al(n * S * 8)
+    fake = ctypes.create_string_buffer(1024)
+    addr = (ctypes.addressof(fake) + 255) & ~255
+    for order, flag in ((3, 1), (1, 2)):
+        num = thor.Numerics(600.0, 0.0048, 1, thor.THOR_FP64)
+        num.lagrange_order, num.anelastic = order, flag
+        with pytest.raises(thor.ThorError) as e:
+            thor.thor_state_init(G.handle, planet, v, num, forcing, init, addr, 1 << 40, 0)
+        assert e.value.code == thor.THOR_EINVAL
+        assert "anelastic" in str(e.value)
+    num = thor.Numerics(600.0, 0.0048, 1, thor.THOR_FP64)
+    num.lagrange_order, num.anelastic = 1, 1
+    with pytest.raises(thor.ThorError) as e:
+        thor.thor_batch_init([G.handle], [(planet, v, num, forcing, init)], addr, 1 << 40, 0)
+    assert e.value.code == thor.THOR_EINVAL
+    assert "anelastic" in str(e.value)
+
+
 @pytest.mark.parametrize("g,smooth", [(3, True), (4, False)])
 def test_two_ring_damping_stencil_equals_lap_of_grad(g, smooth):
     """The folded divergence-damping stencil reproduces the oracle's

@@ -117,14 +117,15 @@ def test_gas_giant_g7_l48_full_size_samples_after_one_step(precision):
 
 
 @pytest.mark.parametrize("attr,value", [("energy_fixer", True), ("hydrostatic", True), ("shallow", True),
-                                        ("lagrange_order", 3)])
+                                        ("lagrange_order", 3), ("anelastic", True)])
 def test_gas_giant_g6_l32_switches_full_size_samples_after_one_step(attr, value):
     """The benchmark workload with each of the switches the benchmark times
-    (energy fixer, hydrostatic, shallow, cubic vertical interpolation)."""
+    (energy fixer, hydrostatic, shallow, cubic vertical interpolation,
+    anelastic)."""
     w = workloads.gas_giant_c2()
     setattr(w, attr, value)
     name = {"energy_fixer": "fixer", "hydrostatic": "hydrostatic", "shallow": "shallow",
-            "lagrange_order": "cubic"}[attr]
+            "lagrange_order": "cubic", "anelastic": "anelastic"}[attr]
     tol_w = None
     if attr == "hydrostatic":
         # the hydrostatic form diagnoses W from a nearly cancelling balance:

@@ -12,7 +12,7 @@ TOL = 1e-10
 
 def _parity(w, precision=0, tol=TOL, names=("T", "u", "v", "w", "p", "rho", "rhotheta")):
     say(f"[variant] {w.name} g{w.glevel} L{w.n_lev} hydrostatic={w.hydrostatic} shallow={w.shallow} order={w.lagrange_order} "
-        f"n_large={w.n_large} precision={precision}")
+        f"anelastic={w.anelastic} n_large={w.n_large} precision={precision}")
     st = lib_state(w, precision)
     st.step(w.n_large, w.n_acoustic)
     got = lib_fields(st, names)
@@ -127,9 +127,82 @@ def test_order_zero_is_order_one_and_bad_orders_are_rejected():
             lib_state(w)
 
 
+@pytest.mark.parametrize("n_lev", [1, 13, 32])
+def test_anelastic_earth(n_lev):
+    """The reference-density mass flux of Sec. 3: one level (horizontal
+    flux only), a ragged top lane, and whole lanes."""
+    w = small_earth(glevel=3, n_lev=n_lev, n_large=3, noise=1.0)
+    w.anelastic = True
+    _parity(w)
+
+
+def test_anelastic_gas_giant_with_forcing():
+    w = workloads.small_gas_giant(glevel=3, n_lev=19, n_large=3)
+    w.anelastic = True
+    _parity(w)
+
+
+def test_anelastic_hydrostatic_shallow_together():
+    w = small_earth(glevel=3, n_lev=16, n_large=3, noise=1.0)
+    w.anelastic = True
+    w.hydrostatic = True
+    w.shallow = True
+    _parity(w)
+
+
+def test_anelastic_held_suarez_with_energy_fixer():
+    w = workloads.held_suarez(glevel=3, n_lev=37, n_large=3, dt=3000.0, noise_amp=1.0)
+    w.anelastic = True
+    w.energy_fixer = True
+    _parity(w)
+
+
+def test_anelastic_mixed_precision_stays_close():
+    w = workloads.small_gas_giant(glevel=3, n_lev=20, n_large=3)
+    w.anelastic = True
+    _parity(w, precision=1, tol=1e-5, names=("T", "p", "rho"))
+
+
+def test_anelastic_conserves_mass_and_changes_the_flow():
+    """The reference-density flux is still a flux divergence, so the total
+    mass keeps to rounding; and the switch is live: the winds differ from
+    the compressible run's by far more than the parity bar."""
+    import numpy as np
+    w = small_earth(glevel=4, n_lev=24, n_large=4, noise=2.0)
+    w.anelastic = True
+    a = lib_state(w)
+    m0, _ = a.mass()
+    a.step(w.n_large, w.n_acoustic)
+    m1, _ = a.mass()
+    say(f"[variant] anelastic mass {m0!r} -> {m1!r}")
+    assert abs(m1 - m0) < 1e-13 * m0
+    w.anelastic = False
+    b = lib_state(w)
+    b.step(w.n_large, w.n_acoustic)
+    fa, fb = lib_fields(a, ("u", "w")), lib_fields(b, ("u", "w"))
+    speed = np.sqrt(np.mean(fb["u"] ** 2))
+    assert np.abs(fa["u"] - fb["u"]).max() > 1e-6 * speed
+    assert np.abs(fa["w"] - fb["w"]).max() > 0
+
+
+def test_anelastic_keeps_the_four_level_mapping():
+    from paper_1607_05535_amd import thor
+    w = small_earth(glevel=2, n_lev=36, n_large=1)
+    w.anelastic = True
+    st = lib_state(w)
+    for nl in (1, 2):
+        with pytest.raises(thor.ThorError, match="anelastic"):
+            thor.thor_set_vert_levels_per_lane(st.handle, nl)
+    thor.thor_set_vert_levels_per_lane(st.handle, 4)
+    w.lagrange_order = 3
+    with pytest.raises(thor.ThorError, match="anelastic"):
+        lib_state(w)
+
+
 @pytest.mark.parametrize("switches", [
     dict(energy_fixer=True, hydrostatic=True),
     dict(shallow=True, lagrange_order=3),
+    dict(anelastic=True, hydrostatic=True),
     dict(energy_fixer=True, shallow=True, lagrange_order=3, forcing_kind=1)])
 def test_switches_under_graphs_checkpoints_and_autotune(switches):
     """With the switches on: graph replays equal eager launches bitwise,

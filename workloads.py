@@ -63,6 +63,7 @@ class Workload:
     hydrostatic: bool = False
     shallow: bool = False
     lagrange_order: int = 1
+    anelastic: bool = False
     extra: dict = field(default_factory=dict)
 
     @property
