@@ -50,7 +50,7 @@ struct Fields {
   H *D;                   // 3D divergence of the small-step state
   H *Dt;                  // and of Phi[t]
   // large-step temporaries
-  double *T, *vx, *vy, *vz, *wI;
+  double *wI;             // w at the interfaces (W / rho_I) of Phi[t]
   double *Xrho, *Xvx, *Xvy, *Xvz, *Xw, *XT;
   // diagnostics
   double *diag;           // [N][L]

@@ -1428,27 +1428,32 @@ __device__ __forceinline__ void large0_cells(const Fields<H> &f, const Consts &c
   double rhoI[kHq];   // rho at interfaces lev0 .. lev0 + 3
   interface_rho<VEC>(c, rho, lev0, lm, lp, rhoI);
   if (!ln.store) return;
-  H mx[kHq], my[kHq], mz[kHq];
-  ld4<VEC>(f.Mx_t + idx, nv, mx);
-  ld4<VEC>(f.My_t + idx, nv, my);
-  ld4<VEC>(f.Mz_t + idx, nv, mz);
-  double p[kHq], T[kHq], vx[kHq], vy[kHq], vz[kHq], wI[kHq];
+  double p[kHq], wI[kHq];
 #pragma unroll
   for (int q = 0; q < kHq; ++q) {
     p[q] = c.p_ref * powd(c.Rd * rth[q] / c.p_ref, c.gamma);
+    wI[q] = lev0 + q == 0 ? 0.0 : W[q] / rhoI[q];
+  }
+  st4<VEC>(f.p_t + idx, nv, p);
+  st4<VEC>(f.wI + idx, nv, wI);
+}
+
+// The velocity M / rho and temperature p / (rho Rd) of kHq cells, the
+// Laplacian inputs of the momentum and pressure hyperdiffusion, formed where
+// they are gathered (every cell forms them the same way, so a neighbour's
+// value equals its own).
+template <typename H>
+__device__ __forceinline__ void vel_temp(const Consts &c, const double rho[kHq], const double p[kHq], const H mx[kHq],
+                                         const H my[kHq], const H mz[kHq], double vx[kHq], double vy[kHq],
+                                         double vz[kHq], double T[kHq]) {
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) {
     const double irho = 1.0 / rho[q];
     T[q] = p[q] * irho / c.Rd;
     vx[q] = (double)mx[q] * irho;
     vy[q] = (double)my[q] * irho;
     vz[q] = (double)mz[q] * irho;
-    wI[q] = lev0 + q == 0 ? 0.0 : W[q] / rhoI[q];
   }
-  st4<VEC>(f.p_t + idx, nv, p);
-  st4<VEC>(f.T + idx, nv, T);
-  st4<VEC>(f.vx + idx, nv, vx);
-  st4<VEC>(f.vy + idx, nv, vy);
-  st4<VEC>(f.vz + idx, nv, vz);
-  st4<VEC>(f.wI + idx, nv, wI);
 }
 
 // Anelastic switch only (Sec. 3 anelastic approximation): the mass flux is
@@ -1500,13 +1505,11 @@ __device__ __forceinline__ void lap4(const T *s, const int nb[6], const H *lc, i
 // Per large step, first pass: the inner Laplacians of the hyperdiffusion
 // (rho; rho Kd lap of vx, vy, vz, T; rho_I Kd lap of w at the interfaces),
 // -proj_h grad p[t], the 3D momentum divergence of Phi[t] and the [t]
-// vertical imbalance.  The neighbour loops are neighbour-major: one pass
-// loads the rows of the six Laplacian fields of neighbour j together, a
-// second those of p, Mx, My, Mz, and every sum takes its j-th term, so each
-// sum adds its terms in the same order as a field-by-field pass, with six
-// (four) rows in flight per neighbour instead of one (FP64 at g6 L32: 72
-// against 79 us; one pass over all ten fields needs more registers than
-// two wavefronts per SIMD allow and takes 92 us).
+// vertical imbalance.  One neighbour-major pass loads the rows of rho, p,
+// Mx, My, Mz and w_I of neighbour j together and forms the neighbour's
+// velocity and temperature from them (rather than reading fields the
+// previous kernel stored); every sum takes its j-th term, so each adds its
+// terms in the same order as a field-by-field pass.
 template <typename H, bool VEC>
 __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
   const int L = c.L, lev0 = ln.lev0, nv = ln.nv, col = ln.col;
@@ -1534,19 +1537,7 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
     irc2[q] = 1.0 / (rC * rC);
   }
   // Laplacian fields: rho, vx, vy, vz, T, w (rho is rho[] itself)
-  const double *lsrc[6] = {f.rho_t, f.vx, f.vy, f.vz, f.T, f.wI};
   double s0[6][kHq], lap[6][kHq];
-#pragma unroll
-  for (int q = 0; q < kHq; ++q) s0[0][q] = rho[q];
-#pragma unroll
-  for (int k = 1; k < 6; ++k) ld4<VEC>(lsrc[k] + idx, nv, s0[k]);
-#pragma unroll
-  for (int k = 0; k < 6; ++k)
-#pragma unroll
-    for (int q = 0; q < kHq; ++q) lap[k][q] = 0;
-  double gx[kHq], gy[kHq], gz[kHq];
-#pragma unroll
-  for (int q = 0; q < kHq; ++q) gx[q] = gy[q] = gz[q] = 0;
   H dm[kHq];
   {
     H mx[kHq], my[kHq], mz[kHq];
@@ -1555,30 +1546,37 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
     ld4<VEC>(f.Mz_t + idx, nv, mz);
 #pragma unroll
     for (int q = 0; q < kHq; ++q) dm[q] = dch[0] * mx[q] + dch[1] * my[q] + dch[2] * mz[q];
+    vel_temp<H>(c, rho, p, mx, my, mz, s0[1], s0[2], s0[3], s0[4]);
   }
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) s0[0][q] = rho[q];
+  ld4<VEC>(f.wI + idx, nv, s0[5]);
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+#pragma unroll
+    for (int q = 0; q < kHq; ++q) lap[k][q] = 0;
+  double gx[kHq], gy[kHq], gz[kHq];
+#pragma unroll
+  for (int q = 0; q < kHq; ++q) gx[q] = gy[q] = gz[q] = 0;
 #pragma unroll 1
   for (int j = 0; j < 6; ++j) {
     const size_t nj = (size_t)nb[j] * c.S + lev0;
-    double sj[6][kHq];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) ld4<VEC>(lsrc[k] + nj, nv, sj[k]);
-    const double w = (double)lch[j];
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-#pragma unroll
-      for (int q = 0; q < kHq; ++q) lap[k][q] += w * (sj[k][q] - s0[k][q]);
-  }
-#pragma unroll 1
-  for (int j = 0; j < 6; ++j) {
-    const size_t nj = (size_t)nb[j] * c.S + lev0;
-    double pj[kHq];
+    double sj[6][kHq], pj[kHq];
     H mx[kHq], my[kHq], mz[kHq];
+    ld4<VEC>(f.rho_t + nj, nv, sj[0]);
     ld4<VEC>(f.p_t + nj, nv, pj);
     ld4<VEC>(f.Mx_t + nj, nv, mx);
     ld4<VEC>(f.My_t + nj, nv, my);
     ld4<VEC>(f.Mz_t + nj, nv, mz);
+    ld4<VEC>(f.wI + nj, nv, sj[5]);
+    vel_temp<H>(c, sj[0], pj, mx, my, mz, sj[1], sj[2], sj[3], sj[4]);
+    const double w = (double)lch[j];
     const double cx = dch[3 * (j + 1)], cy = dch[3 * (j + 1) + 1], cz = dch[3 * (j + 1) + 2];
     const H hx = dch[3 * (j + 1)], hy = dch[3 * (j + 1) + 1], hz = dch[3 * (j + 1) + 2];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int q = 0; q < kHq; ++q) lap[k][q] += w * (sj[k][q] - s0[k][q]);
 #pragma unroll
     for (int q = 0; q < kHq; ++q) {
       const double dp = pj[q] - p[q];

@@ -92,10 +92,6 @@ void carve(Carver &cv, Fields<H> &f, size_t N, size_t L, bool anelastic) {
   f.Gam = cv.take<H>(NL);
   f.D = cv.take<H>(NL);
   f.Dt = cv.take<H>(NL);
-  f.T = cv.take<double>(NL);
-  f.vx = cv.take<double>(NL);
-  f.vy = cv.take<double>(NL);
-  f.vz = cv.take<double>(NL);
   f.wI = cv.take<double>(NL);
   f.Xrho = cv.take<double>(NL);
   f.Xvx = cv.take<double>(NL);
