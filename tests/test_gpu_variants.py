@@ -136,6 +136,15 @@ def test_anelastic_earth(n_lev):
     _parity(w)
 
 
+@pytest.mark.parametrize("glevel,n_lev", [(0, 2), (1, 7), (2, 64)])
+def test_anelastic_edge_sizes(glevel, n_lev):
+    """The 12 pentagons alone (g0) with two levels (one interior
+    interface), g1 with an odd level count, and the largest level count."""
+    w = small_earth(glevel=glevel, n_lev=n_lev, n_large=2, noise=1.0)
+    w.anelastic = True
+    _parity(w)
+
+
 def test_anelastic_gas_giant_with_forcing():
     w = workloads.small_gas_giant(glevel=3, n_lev=19, n_large=3)
     w.anelastic = True
