@@ -1503,9 +1503,8 @@ __device__ __forceinline__ void lap4(const T *s, const int nb[6], const H *lc, i
 }
 
 // Per large step, first pass: the inner Laplacians of the hyperdiffusion
-// (rho; rho Kd lap of vx, vy, vz, T; rho_I Kd lap of w at the interfaces),
-// -proj_h grad p[t], the 3D momentum divergence of Phi[t] and the [t]
-// vertical imbalance.  One neighbour-major pass loads the rows of rho, p,
+// (rho; rho Kd lap of vx, vy, vz, T; rho_I Kd lap of w at the interfaces)
+// and the 3D momentum divergence of Phi[t].  One neighbour-major pass loads the rows of rho, p,
 // Mx, My, Mz and w_I of neighbour j together and forms the neighbour's
 // velocity and temperature from them (rather than reading fields the
 // previous kernel stored); every sum takes its j-th term, so each adds its
@@ -1521,7 +1520,7 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
   ld4<VEC>(f.rho_t + idx, nv, rho);
   ld4<VEC>(f.p_t + idx, nv, p);
   ld4<VEC>(f.W_t + idx, nv, W);
-  const double rho_m = shfl(rho[kHq - 1], lm), p_m = shfl(p[kHq - 1], lm), W_n = shfl(W[0], lp);
+  const double W_n = shfl(W[0], lp);
   double rhoI[kHq];   // rho at interfaces lev0 .. lev0 + 3
   interface_rho<VEC>(c, rho, lev0, lm, lp, rhoI);
   if (!ln.store) return;
@@ -1555,9 +1554,6 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
   for (int k = 0; k < 6; ++k)
 #pragma unroll
     for (int q = 0; q < kHq; ++q) lap[k][q] = 0;
-  double gx[kHq], gy[kHq], gz[kHq];
-#pragma unroll
-  for (int q = 0; q < kHq; ++q) gx[q] = gy[q] = gz[q] = 0;
 #pragma unroll 1
   for (int j = 0; j < 6; ++j) {
     const size_t nj = (size_t)nb[j] * c.S + lev0;
@@ -1571,20 +1567,13 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
     ld4<VEC>(f.wI + nj, nv, sj[5]);
     vel_temp<H>(c, sj[0], pj, mx, my, mz, sj[1], sj[2], sj[3], sj[4]);
     const double w = (double)lch[j];
-    const double cx = dch[3 * (j + 1)], cy = dch[3 * (j + 1) + 1], cz = dch[3 * (j + 1) + 2];
     const H hx = dch[3 * (j + 1)], hy = dch[3 * (j + 1) + 1], hz = dch[3 * (j + 1) + 2];
 #pragma unroll
     for (int k = 0; k < 6; ++k)
 #pragma unroll
       for (int q = 0; q < kHq; ++q) lap[k][q] += w * (sj[k][q] - s0[k][q]);
 #pragma unroll
-    for (int q = 0; q < kHq; ++q) {
-      const double dp = pj[q] - p[q];
-      gx[q] += cx * dp;
-      gy[q] += cy * dp;
-      gz[q] += cz * dp;
-      dm[q] += hx * mx[q] + hy * my[q] + hz * mz[q];
-    }
+    for (int q = 0; q < kHq; ++q) dm[q] += hx * mx[q] + hy * my[q] + hz * mz[q];
   }
   {
     double l[kHq];
@@ -1610,28 +1599,9 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
     }
     st4<VEC>(f.Xw + idx, nv, l);
   }
-  // -grad p[t] (in double: full pressure), projected
-  {
-    const H *rh = f.rhat + (size_t)col * 3;
-    const double rx = rh[0], ry = rh[1], rz = rh[2];
-    H ox[kHq], oy[kHq], oz[kHq];
-#pragma unroll
-    for (int q = 0; q < kHq; ++q) {
-      const double irc = 1.0 / radius_c(c, lev0 + q);
-      const double x = gx[q] * irc, y = gy[q] * irc, z = gz[q] * irc;
-      const double gr = x * rx + y * ry + z * rz;
-      ox[q] = (H)(-(x - gr * rx));
-      oy[q] = (H)(-(y - gr * ry));
-      oz[q] = (H)(-(z - gr * rz));
-    }
-    st4<VEC>(f.FMx + idx, nv, ox);
-    st4<VEC>(f.FMy + idx, nv, oy);
-    st4<VEC>(f.FMz + idx, nv, oz);
-  }
-  // 3D momentum divergence of Phi[t] and the [t] vertical imbalance
+  // 3D momentum divergence of Phi[t]
   {
     H Dt[kHq];
-    double FW[kHq];
 #pragma unroll
     for (int q = 0; q < kHq; ++q) {
       const int lev = lev0 + q;
@@ -1641,20 +1611,20 @@ __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c
       const double Wl = lev == 0 ? 0.0 : W[q];
       const double rI1 = rI + c.rdz;
       Dt[q] = (H)((double)dm[q] * irc + (rI1 * rI1 * W1 - rI * rI * Wl) * (irc * irc / c.dz));
-      // [t] vertical imbalance at interface lev
-      const double pm = q ? p[q - 1] : p_m, rm = q ? rho[q - 1] : rho_m;
-      FW[q] = lev == 0 ? 0.0 : -(p[q] - pm) / c.dz - 0.5 * c.grav * (rm + rho[q]);
     }
     st4<VEC>(f.Dt + idx, nv, Dt);
-    st4<VEC>(f.FW + idx, nv, FW);
   }
 }
 
 template <typename H, bool VEC>
 __device__ __forceinline__ void large2_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
-  if (!ln.store) return;
   const int lev0 = ln.lev0, nv = ln.nv, col = ln.col;
   const size_t idx = (size_t)col * c.S + lev0;
+  const int lane = threadIdx.x & 63;
+  const int lm = lane > 0 ? lane - 1 : 0;
+  // p[t] and rho[t] of the level below the lane's first (every lane shuffles)
+  const double p_m = shfl(f.p_t[idx + kHq - 1], lm), rho_m = shfl(f.rho_t[idx + kHq - 1], lm);
+  if (!ln.store) return;
   int nb[6];
   load_nbr(f.nbr, col, nb);
   const H *lch = f.lc + (size_t)col * 6;
@@ -1673,16 +1643,44 @@ __device__ __forceinline__ void large2_cells(const Fields<H> &f, const Consts &c
     st4<VEC>(f.Hrho + idx, nv, h);
   }
   {
+    const H *rh = f.rhat + (size_t)col * 3;
+    const double rx = rh[0], ry = rh[1], rz = rh[2];
+    // -grad p[t] (in double: full pressure), projected, in the horizontal
+    // precision; the momentum hyperdiffusion is added to it below
+    H fx[kHq], fy[kHq], fz[kHq];
+    {
+      const H *dch = f.dc + (size_t)col * 21;
+      double p[kHq], gx[kHq], gy[kHq], gz[kHq];
+      ld4<VEC>(f.p_t + idx, nv, p);
+#pragma unroll
+      for (int q = 0; q < kHq; ++q) gx[q] = gy[q] = gz[q] = 0;
+#pragma unroll 2
+      for (int j = 0; j < 6; ++j) {
+        double pj[kHq];
+        ld4<VEC>(f.p_t + (size_t)nb[j] * c.S + lev0, nv, pj);
+        const double cx = dch[3 * (j + 1)], cy = dch[3 * (j + 1) + 1], cz = dch[3 * (j + 1) + 2];
+#pragma unroll
+        for (int q = 0; q < kHq; ++q) {
+          const double dp = pj[q] - p[q];
+          gx[q] += cx * dp;
+          gy[q] += cy * dp;
+          gz[q] += cz * dp;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kHq; ++q) {
+        const double irc = 1.0 / radius_c(c, lev0 + q);
+        const double x = gx[q] * irc, y = gy[q] * irc, z = gz[q] * irc;
+        const double gr = x * rx + y * ry + z * rz;
+        fx[q] = (H)(-(x - gr * rx));
+        fy[q] = (H)(-(y - gr * ry));
+        fz[q] = (H)(-(z - gr * rz));
+      }
+    }
     double hx[kHq], hy[kHq], hz[kHq];
     lap4<VEC>(f.Xvx, nb, lch, c.S, lev0, nv, idx, hx);
     lap4<VEC>(f.Xvy, nb, lch, c.S, lev0, nv, idx, hy);
     lap4<VEC>(f.Xvz, nb, lch, c.S, lev0, nv, idx, hz);
-    const H *rh = f.rhat + (size_t)col * 3;
-    const double rx = rh[0], ry = rh[1], rz = rh[2];
-    H fx[kHq], fy[kHq], fz[kHq];
-    ld4<VEC>(f.FMx + idx, nv, fx);
-    ld4<VEC>(f.FMy + idx, nv, fy);
-    ld4<VEC>(f.FMz + idx, nv, fz);
 #pragma unroll
     for (int q = 0; q < kHq; ++q) {
       const double x = -irc2[q] * hx[q], y = -irc2[q] * hy[q], z = -irc2[q] * hz[q];
@@ -1696,12 +1694,17 @@ __device__ __forceinline__ void large2_cells(const Fields<H> &f, const Consts &c
     st4<VEC>(f.FMz + idx, nv, fz);
   }
   {
-    double l[kHq], fw[kHq];
+    // the [t] vertical imbalance at interface lev plus the hyperdiffusion
+    // of rho v_r
+    double l[kHq], p[kHq], rho[kHq], fw[kHq];
     lap4<VEC>(f.Xw, nb, lch, c.S, lev0, nv, idx, l);
-    ld4<VEC>(f.FW + idx, nv, fw);
+    ld4<VEC>(f.p_t + idx, nv, p);
+    ld4<VEC>(f.rho_t + idx, nv, rho);
 #pragma unroll
     for (int q = 0; q < kHq; ++q) {
       const int lev = lev0 + q;
+      const double pm = q ? p[q - 1] : p_m, rm = q ? rho[q - 1] : rho_m;
+      fw[q] = lev == 0 ? 0.0 : -(p[q] - pm) / c.dz - 0.5 * c.grav * (rm + rho[q]);
       const double rI = radius_i(c, lev);
       if (lev > 0) fw[q] += -l[q] / (rI * rI);
     }
@@ -1948,7 +1951,7 @@ THOR_KERNEL(slow, sizeof(H) == 8 ? 2 : 4, map_hlane, COMMA int from_t, COMMA fro
 THOR_KERNEL(large0, 4, map_hlane, , )
 THOR_KERNEL(anel, 8, map_hlane, , )
 THOR_KERNEL(large1, sizeof(H) == 8 ? LARGE1_OCC_D : LARGE1_OCC_F, map_hlane, , )
-THOR_KERNEL(large2, 5, map_hlane, , )
+THOR_KERNEL(large2, 4, map_hlane, , )
 THOR_KERNEL(diag, 8, map_lane, COMMA int field, COMMA field)
 THOR_KERNEL(import, 8, map_lane, COMMA const double *blob, COMMA blob)
 THOR_KERNEL(friction, 8, map_hlane, , )
