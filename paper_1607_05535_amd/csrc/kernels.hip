@@ -1504,11 +1504,13 @@ __device__ __forceinline__ void lap4(const T *s, const int nb[6], const H *lc, i
 
 // Per large step, first pass: the inner Laplacians of the hyperdiffusion
 // (rho; rho Kd lap of vx, vy, vz, T; rho_I Kd lap of w at the interfaces)
-// and the 3D momentum divergence of Phi[t].  One neighbour-major pass loads the rows of rho, p,
-// Mx, My, Mz and w_I of neighbour j together and forms the neighbour's
-// velocity and temperature from them (rather than reading fields the
-// previous kernel stored); every sum takes its j-th term, so each adds its
-// terms in the same order as a field-by-field pass.
+// and the 3D momentum divergence of Phi[t] (the second pass forms -grad
+// p[t] and the [t] imbalance next to the hyperdiffusion it adds to them).
+// One neighbour-major pass loads the rows of rho, p, Mx, My, Mz and w_I of
+// neighbour j together and forms the neighbour's velocity and temperature
+// from them (rather than reading fields the previous kernel stored); every
+// sum takes its j-th term, so each adds its terms in the same order as a
+// field-by-field pass.
 template <typename H, bool VEC>
 __device__ __forceinline__ void large1_cells(const Fields<H> &f, const Consts &c, const HLane &ln) {
   const int L = c.L, lev0 = ln.lev0, nv = ln.nv, col = ln.col;
